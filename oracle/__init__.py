@@ -1,0 +1,284 @@
+"""CPU oracle of the TPC track-finding hot path — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The product path (the HIP library and its
+binding) never loads it; the two share no code.
+
+The arithmetic lives in ``tpc_oracle.cpp`` (plain, slow, brute force), built
+with ``g++ -O2 -ffp-contract=off -fno-fast-math`` so that the binary32 mode
+runs in IEEE single precision in the written operation order. This module
+only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libtpcoracle.so")
+_SRC = os.path.join(_HERE, "tpc_oracle.cpp")
+CFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC", "-pthread"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_rows", ctypes.c_int32),
+        ("bz", ctypes.c_double),
+        ("sigma_y", ctypes.c_double),
+        ("sigma_z", ctypes.c_double),
+        ("win_ty", ctypes.c_double),
+        ("win_tz", ctypes.c_double),
+        ("win_ny", ctypes.c_double),
+        ("win_nz", ctypes.c_double),
+        ("nbr_score_max", ctypes.c_double),
+        ("nsig", ctypes.c_double),
+        ("chi2_pick", ctypes.c_double),
+        ("chi2_rej", ctypes.c_double),
+        ("sinphi_max", ctypes.c_double),
+        ("cov_reset", ctypes.c_double),
+        ("q_max", ctypes.c_double),
+        ("u_max", ctypes.c_double),
+        ("c0", ctypes.c_double * 5),
+        ("n_min", ctypes.c_int32),
+        ("max_miss", ctypes.c_int32),
+        ("hits_per_bin", ctypes.c_int32),
+        ("n_threads", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++"] + CFLAGS + [_SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.orc_default_params.argtypes = [ctypes.POINTER(Params)]
+        L.orc_run.restype = vp
+        L.orc_run.argtypes = [ctypes.POINTER(Params), i32, i32, vp, vp, vp, vp]
+        L.orc_free.argtypes = [vp]
+        L.orc_sizes.argtypes = [vp, vp]
+        L.orc_get_grid.argtypes = [vp] + [vp] * 8
+        L.orc_get_links.argtypes = [vp] + [vp] * 4
+        L.orc_get_tracklets.argtypes = [vp] + [vp] * 8
+        L.orc_get_selected.argtypes = [vp] + [vp] * 5
+        L.orc_get_tracks.argtypes = [vp] + [vp] * 11
+        L.orc_propagate.restype = i32
+        L.orc_propagate.argtypes = [ctypes.POINTER(Params), i32, vp, dbl, dbl]
+        L.orc_update.restype = dbl
+        L.orc_update.argtypes = [ctypes.POINTER(Params), i32, vp, dbl, dbl]
+        L.orc_asin_over.restype = dbl
+        L.orc_asin_over.argtypes = [i32, dbl]
+        L.orc_seed.restype = i32
+        L.orc_seed.argtypes = [ctypes.POINTER(Params), i32, vp, vp]
+        L.orc_refit.restype = i32
+        L.orc_refit.argtypes = [ctypes.POINTER(Params), i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_replay_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 11
+        _lib = L
+    return _lib
+
+
+def default_params(**over) -> Params:
+    p = Params()
+    lib().orc_default_params(ctypes.byref(p))
+    for k, v in over.items():
+        if k == "c0":
+            for i in range(5):
+                p.c0[i] = v[i]
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+@dataclass
+class OracleResult:
+    precision: int
+    n_rows: int
+    # grid
+    sorted_id: np.ndarray
+    bin_start: np.ndarray
+    g_ny: np.ndarray
+    g_nz: np.ndarray
+    g_meta: np.ndarray  # [n_seg, 4]: ymin zmin invy invz
+    # CA links (input-id space)
+    up: np.ndarray
+    dn: np.ndarray
+    upc: np.ndarray
+    dnc: np.ndarray
+    # starts / tracklets
+    start_hit: np.ndarray
+    start_inst: np.ndarray
+    start_tid: np.ndarray
+    tl_nhits: np.ndarray
+    tl_rowhit: np.ndarray  # [N_s, n_rows]
+    tl_state: np.ndarray  # [N_s, 20]
+    tl_row: np.ndarray
+    weight: np.ndarray
+    # selected (pre-refit) tracks
+    sel_tl: np.ndarray
+    sel_hit_start: np.ndarray
+    sel_hit: np.ndarray
+    sel_mask: np.ndarray
+    sel_status: np.ndarray
+    # output tracks
+    trk_inst: np.ndarray
+    trk_sel: np.ndarray
+    trk_x: np.ndarray
+    trk_alpha: np.ndarray
+    trk_param: np.ndarray  # [n_t, 5]
+    trk_cov: np.ndarray  # [n_t, 15]
+    trk_chi2: np.ndarray
+    trk_ndf: np.ndarray
+    trk_hit_start: np.ndarray
+    trk_hit: np.ndarray
+    chi2_total: float
+    ndf_total: int
+
+    @property
+    def n_tracks(self) -> int:
+        return int(self.trk_inst.shape[0])
+
+
+def run(cs, precision: int = 32, params: Params | None = None, threads: int = 1) -> OracleResult:
+    """Track a ClusterSet (instances x rows CSR) with the oracle."""
+    L = lib()
+    p = params if params is not None else default_params()
+    p.n_threads = threads
+    nr = p.n_rows
+    inst_sector = np.ascontiguousarray(cs.inst_sector, dtype=np.int32)
+    row_start = np.ascontiguousarray(cs.row_start, dtype=np.int64)
+    y = np.ascontiguousarray(cs.y, dtype=np.float32)
+    z = np.ascontiguousarray(cs.z, dtype=np.float32)
+    h = L.orc_run(ctypes.byref(p), precision, int(cs.n_inst), inst_sector.ctypes.data, row_start.ctypes.data,
+                  _ptr(y), _ptr(z))
+    try:
+        sz = np.zeros(6, np.int64)
+        L.orc_sizes(h, sz.ctypes.data)
+        N, ns, nsel, nselh, nt, nth = (int(v) for v in sz)
+        nseg = int(cs.n_inst) * nr
+        sorted_id = np.zeros(N, np.int32)
+        bin_start = np.zeros(N + nseg + 1, np.int32)
+        g_ny, g_nz = np.zeros(nseg, np.int32), np.zeros(nseg, np.int32)
+        meta = [np.zeros(nseg, np.float64) for _ in range(4)]
+        L.orc_get_grid(h, _ptr(sorted_id), _ptr(bin_start), _ptr(g_ny), _ptr(g_nz), *[_ptr(m) for m in meta])
+        up, dn, upc, dnc = (np.zeros(N, np.int32) for _ in range(4))
+        L.orc_get_links(h, _ptr(up), _ptr(dn), _ptr(upc), _ptr(dnc))
+        start_hit, start_inst, start_tid, nhits = (np.zeros(ns, np.int32) for _ in range(4))
+        rowhit = np.zeros(ns * nr, np.int32)
+        state = np.zeros(ns * 20, np.float64)
+        srow = np.zeros(ns, np.int32)
+        weight = np.zeros(N, np.uint32)
+        L.orc_get_tracklets(h, _ptr(start_hit), _ptr(start_inst), _ptr(start_tid), _ptr(nhits), _ptr(rowhit),
+                            _ptr(state), _ptr(srow), _ptr(weight))
+        sel_tl = np.zeros(nsel, np.int32)
+        sel_hs = np.zeros(nsel + 1, np.int64)
+        sel_hit = np.zeros(nselh, np.int32)
+        sel_mask = np.zeros(nselh, np.uint8)
+        sel_status = np.zeros(nsel, np.int32)
+        L.orc_get_selected(h, _ptr(sel_tl), _ptr(sel_hs), _ptr(sel_hit), _ptr(sel_mask), _ptr(sel_status))
+        ti, tsel, tndf = (np.zeros(nt, np.int32) for _ in range(3))
+        tx, ta, tchi2 = (np.zeros(nt, np.float64) for _ in range(3))
+        tpar = np.zeros(nt * 5, np.float64)
+        tcov = np.zeros(nt * 15, np.float64)
+        ths = np.zeros(nt + 1, np.int64)
+        thit = np.zeros(nth, np.int32)
+        tot = np.zeros(2, np.float64)
+        L.orc_get_tracks(h, _ptr(ti), _ptr(tsel), _ptr(tx), _ptr(ta), _ptr(tpar), _ptr(tcov), _ptr(tchi2), _ptr(tndf),
+                         _ptr(ths), _ptr(thit), _ptr(tot))
+    finally:
+        L.orc_free(h)
+    return OracleResult(
+        precision, nr, sorted_id, bin_start, g_ny, g_nz, np.stack(meta, axis=1), up, dn, upc, dnc,
+        start_hit, start_inst, start_tid, nhits, rowhit.reshape(ns, nr), state.reshape(ns, 20), srow, weight,
+        sel_tl, sel_hs, sel_hit, sel_mask, sel_status, ti, tsel, tx, ta, tpar.reshape(nt, 5),
+        tcov.reshape(nt, 15), tchi2, tndf, ths, thit, float(tot[0]), int(tot[1]))
+
+
+# ---------------------------------------------------------------- primitives
+def propagate(state20, x1, x2, precision=64, params=None):
+    p = params if params is not None else default_params()
+    st = np.ascontiguousarray(np.array(state20, dtype=np.float64))
+    if st.shape != (20,):
+        raise ValueError("state must hold 5 parameters and 15 covariance terms")
+    ok = lib().orc_propagate(ctypes.byref(p), precision, st.ctypes.data, float(x1), float(x2))
+    return bool(ok), st
+
+
+def update(state20, my, mz, precision=64, params=None):
+    p = params if params is not None else default_params()
+    st = np.ascontiguousarray(np.array(state20, dtype=np.float64))
+    if st.shape != (20,):
+        raise ValueError("state must hold 5 parameters and 15 covariance terms")
+    chi2 = lib().orc_update(ctypes.byref(p), precision, st.ctypes.data, float(my), float(mz))
+    return chi2, st
+
+
+def asin_over(u, precision=64):
+    return lib().orc_asin_over(precision, float(u))
+
+
+def seed(points8, precision=64, params=None):
+    p = params if params is not None else default_params()
+    pts = np.ascontiguousarray(np.array(points8, dtype=np.float64))
+    st = np.zeros(20, np.float64)
+    ok = lib().orc_seed(ctypes.byref(p), precision, pts.ctypes.data, st.ctypes.data)
+    return bool(ok), st
+
+
+def refit(state20, row, rows, ys, zs, precision=64, params=None, replay=None):
+    """Three-pass refit of one hit list; returns (ok, state20, chi2, nacc, row, masks)."""
+    p = params if params is not None else default_params()
+    st0 = np.ascontiguousarray(np.array(state20, dtype=np.float64))
+    if st0.shape != (20,):
+        raise ValueError("state must hold 5 parameters and 15 covariance terms")
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32))
+    if len(ys) != len(rows) or len(zs) != len(rows):
+        raise ValueError("rows, ys and zs must have equal length")
+    ys = np.ascontiguousarray(np.asarray(ys, dtype=np.float64))
+    zs = np.ascontiguousarray(np.asarray(zs, dtype=np.float64))
+    n = len(rows)
+    masks = np.zeros(max(n, 1), np.uint8)
+    rp = None if replay is None else np.ascontiguousarray(np.asarray(replay, dtype=np.uint8))
+    out = np.zeros(20, np.float64)
+    sc = np.zeros(3, np.float64)
+    ok = lib().orc_refit(ctypes.byref(p), precision, st0.ctypes.data, int(row), n, _ptr(rows), _ptr(ys), _ptr(zs),
+                         _ptr(rp), masks.ctypes.data, out.ctypes.data, sc.ctypes.data)
+    return bool(ok), out, sc[0], int(sc[1]), int(sc[2]), masks[:n]
+
+
+def replay_f64(st0, row0, hit_start, hit_rows, ys, zs, masks, params=None):
+    """FP64 replay of refits with given start states and accept masks."""
+    p = params if params is not None else default_params()
+    n = len(row0)
+    st0 = np.ascontiguousarray(np.asarray(st0, dtype=np.float64).reshape(n, 20))
+    row0 = np.ascontiguousarray(np.asarray(row0, dtype=np.int32))
+    hit_start = np.ascontiguousarray(np.asarray(hit_start, dtype=np.int64))
+    hit_rows = np.ascontiguousarray(np.asarray(hit_rows, dtype=np.int32))
+    ys = np.ascontiguousarray(np.asarray(ys, dtype=np.float64))
+    zs = np.ascontiguousarray(np.asarray(zs, dtype=np.float64))
+    masks = np.ascontiguousarray(np.asarray(masks, dtype=np.uint8))
+    out = np.zeros((n, 20), np.float64)
+    chi2 = np.zeros(n, np.float64)
+    ok = np.zeros(n, np.int32)
+    lib().orc_replay_f64(ctypes.byref(p), n, _ptr(st0), _ptr(row0), _ptr(hit_start), _ptr(hit_rows), _ptr(ys),
+                         _ptr(zs), _ptr(masks), _ptr(out), _ptr(chi2), _ptr(ok))
+    return ok.astype(bool), out, chi2

@@ -1,0 +1,961 @@
+// TPC track-finding ORACLE — test infrastructure only.
+//
+// A plain, slow CPU implementation of the sector-tracking hot path of
+// Rohr, Gorbunov, Schmidt, Shahoyan, "Track Reconstruction in the ALICE TPC
+// using GPUs for LHC Run 3" (arXiv:1811.11481). Only tests, the smoke check and
+// the benchmark's CPU-baseline leg may load it; the product path never does.
+// It shares no code with the GPU library.
+//
+// What it computes, in the paper's order (Section 2, "TPC Tracking Algorithm
+// and Implementation"; Section 3, "Improvements of Tracking Resolution"):
+//   1. per-(instance, pad row) hit grid (an exported artefact only: every
+//      search below is brute force over the whole row, so no result depends on
+//      the grid);
+//   2. cellular automaton: links between hit triplets on adjacent rows that lie
+//      close to a straight line (neighbour finding), then keeping only mutual
+//      links (the evolution step that concatenates consecutive links), then the
+//      start hits of chains of >= 3 hits;
+//   3. tracklets: a simplified Kalman filter over each chain, extrapolation
+//      outward with pickup of the best hit per row (no multiple hypotheses),
+//      then an inward pass that propagates through the seed again and re-picks
+//      every row (outlier rejection, Section 3);
+//   4. selection: each cluster goes to the tracklet with the largest packed
+//      (nHits, -id) weight; a tracklet survives with >= N_MIN owned clusters;
+//   5. refit: the full Kalman filter iterated inward, outward, inward, with
+//      clusters rejected on their predicted chi2 (Section 3).
+// Numerical readings the paper leaves open (windows, cuts, initial covariance,
+// tie-breaks, the helix step) follow the written algorithm description of this
+// project; every number below is a parameter.
+//
+// Two instantiations: T = double (the FP64 oracle, exact asin in the helix
+// step) and T = float (binary32 in a fixed operation order, no contraction, no
+// library transcendentals: a power series for asin(u)/u).
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fno-fast-math -shared -fPIC
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+extern "C" {
+// Tracking parameters (all physics/geometry numbers; FP64 storage, each mode
+// rounds them to its own precision once).
+typedef struct {
+    int32_t n_rows;        // pad rows (152)
+    double bz;             // solenoid field [T]
+    double sigma_y, sigma_z;  // cluster errors [cm]
+    double win_ty, win_tz, win_ny, win_nz;  // neighbour window: dx * T + N [cm]
+    double nbr_score_max;  // max straight-line deviation score [cm^2]
+    double nsig;           // pickup window in sigmas
+    double chi2_pick;      // pickup chi2 cut (2 dof)
+    double chi2_rej;       // refit rejection chi2 cut (2 dof)
+    double sinphi_max;     // |sin phi| guard
+    double cov_reset;      // diagonal scale at a covariance reset
+    double q_max;          // |q/pT| clamp of the seed estimate [c/GeV]
+    double u_max;          // max |kappa * chord / 2| of one helix step
+    double c0[5];          // initial covariance diagonal
+    int32_t n_min;         // minimum clusters of a tracklet / track
+    int32_t max_miss;      // consecutive empty rows that end the following
+    int32_t hits_per_bin;  // grid occupancy target
+    int32_t n_threads;     // CPU worker threads over instances (0 = 1)
+} orc_params;
+
+void orc_default_params(orc_params* p) {
+    p->n_rows = 152;
+    p->bz = 0.5;
+    p->sigma_y = p->sigma_z = 0.1;
+    p->win_ty = 2.0; p->win_tz = 1.1; p->win_ny = 0.5; p->win_nz = 0.5;
+    p->nbr_score_max = 0.24;
+    p->nsig = 3.0;
+    p->chi2_pick = 16.0;
+    p->chi2_rej = 25.0;
+    p->sinphi_max = 0.95;
+    p->cov_reset = 100.0;
+    p->q_max = 20.0;
+    p->u_max = 0.25;
+    p->c0[0] = 1.0; p->c0[1] = 1.0; p->c0[2] = 0.25; p->c0[3] = 0.25; p->c0[4] = 400.0;
+    p->n_min = 10;
+    p->max_miss = 8;
+    p->hits_per_bin = 2;
+    p->n_threads = 1;
+}
+}
+
+namespace {
+
+// Pad-row plane position: 152 rows evenly spaced between 85 and 247 cm.
+double plane_x(int i) { return 85.0 + i * 162.0 / 151.0; }
+
+// ----------------------------------------------------------------------------
+// Constants of one precision mode.
+template <class T>
+struct Consts {
+    int n_rows;
+    std::vector<T> X;            // row plane x
+    std::vector<T> dxu, dxd;     // X[r+1]-X[r], X[r]-X[r-1]
+    std::vector<T> wyu, wzu, wyd, wzd, tr;
+    T kB;                        // d(sin phi)/dx per unit q/pT
+    T vy, vz;                    // sigma^2
+    T smax, nsig, chi2_pick, chi2_rej, sinphi_max, cov_reset, q_max, u_max2;
+    T c0[5];
+    int n_min, max_miss, hpb;
+    explicit Consts(const orc_params& p) {
+        n_rows = p.n_rows;
+        X.resize(n_rows);
+        for (int i = 0; i < n_rows; ++i) X[i] = (T)plane_x(i);
+        dxu.assign(n_rows, 0); dxd.assign(n_rows, 0);
+        wyu.assign(n_rows, 0); wzu.assign(n_rows, 0); wyd.assign(n_rows, 0); wzd.assign(n_rows, 0);
+        tr.assign(n_rows, 0);
+        const T ty = (T)p.win_ty, tz = (T)p.win_tz, ny = (T)p.win_ny, nz = (T)p.win_nz;
+        for (int r = 1; r + 1 < n_rows; ++r) {
+            dxu[r] = X[r + 1] - X[r];
+            dxd[r] = X[r] - X[r - 1];
+            wyu[r] = dxu[r] * ty + ny;
+            wzu[r] = dxu[r] * tz + nz;
+            wyd[r] = dxd[r] * ty + ny;
+            wzd[r] = dxd[r] * tz + nz;
+            tr[r] = (X[r] - X[r - 1]) / (X[r + 1] - X[r - 1]);
+        }
+        kB = (T)(-0.00299792458 * p.bz);
+        const T sy = (T)p.sigma_y, sz = (T)p.sigma_z;
+        vy = sy * sy;
+        vz = sz * sz;
+        smax = (T)p.nbr_score_max;
+        nsig = (T)p.nsig;
+        chi2_pick = (T)p.chi2_pick;
+        chi2_rej = (T)p.chi2_rej;
+        sinphi_max = (T)p.sinphi_max;
+        cov_reset = (T)p.cov_reset;
+        q_max = (T)p.q_max;
+        const T um = (T)p.u_max;
+        u_max2 = um * um;
+        for (int i = 0; i < 5; ++i) c0[i] = (T)p.c0[i];
+        n_min = p.n_min;
+        max_miss = p.max_miss;
+        hpb = p.hits_per_bin < 1 ? 1 : p.hits_per_bin;
+    }
+};
+
+// ----------------------------------------------------------------------------
+// Track state: (y, z, sin phi, tan lambda, q/pT) at a local x, and the
+// covariance in packed lower-triangular order 00,10,11,20,21,22,30,...,44.
+template <class T>
+struct State {
+    T p[5];
+    T C[15];
+};
+
+inline int pk(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+// asin(u)/u. FP64: the library arcsine. FP32: its Maclaurin series
+// sum_n (2n)! / (4^n (n!)^2 (2n+1)) u^(2n) through u^12, in Horner form.
+inline double asin_over(double u) { return u == 0.0 ? 1.0 : std::asin(u) / u; }
+inline float asin_over(float u) {
+    const float w = u * u;
+    const float c1 = (float)(1.0 / 6.0), c2 = (float)(3.0 / 40.0), c3 = (float)(5.0 / 112.0),
+                c4 = (float)(35.0 / 1152.0), c5 = (float)(63.0 / 2816.0), c6 = (float)(231.0 / 13312.0);
+    return 1.0f + w * (c1 + w * (c2 + w * (c3 + w * (c4 + w * (c5 + w * c6)))));
+}
+// d/du of asin(u)/u from the same series (both precisions; it only enters the
+// Jacobian): u * sum_n 2n c_n u^(2n-2).
+template <class T>
+T asin_over_deriv(T u) {
+    const T w = u * u;
+    const T d1 = (T)(2.0 / 6.0), d2 = (T)(12.0 / 40.0), d3 = (T)(30.0 / 112.0), d4 = (T)(280.0 / 1152.0),
+            d5 = (T)(630.0 / 2816.0), d6 = (T)(2772.0 / 13312.0);
+    return u * (d1 + w * (d2 + w * (d3 + w * (d4 + w * (d5 + w * d6)))));
+}
+
+// Helix step x1 -> x2 in a uniform field along z (Section 3 uses the full field;
+// here Bx = By = 0). The turning rate is d(sin phi)/dx = kB * q/pT; y moves by
+// dx * tan of the mean direction, z by tan(lambda) times the arc length, which
+// is the signed chord times asin(u)/u with u = curvature * chord / 2.
+// Returns false (state untouched) if |sin phi| leaves the guard or u is too big.
+template <class T>
+bool propagate(State<T>& s, T x1, T x2, const Consts<T>& k) {
+    const T one = (T)1, half = (T)0.5, two = (T)2;
+    const T dx = x2 - x1;
+    const T s1 = s.p[2];
+    const T kq = k.kB * s.p[4];
+    const T s2 = s1 + kq * dx;
+    if (!(std::fabs(s2) < k.sinphi_max)) return false;
+    const T c1 = std::sqrt(one - s1 * s1);
+    const T c2 = std::sqrt(one - s2 * s2);
+    const T tt = (s1 + s2) / (c1 + c2);      // tan of the mean direction
+    const T w = one + tt * tt;
+    const T lc = dx * std::sqrt(w);           // signed chord
+    const T u = (kq * lc) * half;
+    if (!(u * u <= k.u_max2)) return false;
+    const T g = asin_over(u);
+    const T arc = lc * g;
+    const T t = s.p[3];
+    // Jacobian F (identity plus these entries), the derivative of this step:
+    // d tan(mean dir) = (1 + tt^2) (dphi1 + dphi2) / 2 with dphi = d(sin phi) / cos,
+    // d arc / d sin(phi1) = dx tt / (c1 c2), and for q/pT the chord and u terms.
+    const T f02 = ((dx * w) * ((one / c1) + (one / c2))) * half;
+    const T f04 = ((dx * w) * ((k.kB * dx) / c2)) * half;
+    const T f12 = t * ((dx * tt) / (c1 * c2));
+    const T f13 = arc;
+    const T dlc = (((k.kB * dx) * lc) * tt) / (two * c2);  // d chord / d(q/pT)
+    const T du = (k.kB * lc + kq * dlc) * half;             // d u / d(q/pT)
+    const T f14 = t * (dlc * g + (lc * asin_over_deriv(u)) * du);
+    const T f24 = k.kB * dx;
+    s.p[0] = s.p[0] + dx * tt;
+    s.p[1] = s.p[1] + t * arc;
+    s.p[2] = s2;
+    // C <- F C F^T: first B = F C (full 5x5), then the lower triangle of B F^T.
+    T Cf[5][5];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) Cf[i][j] = s.C[pk(i, j)];
+    T B[5][5];
+    for (int j = 0; j < 5; ++j) {
+        B[0][j] = (Cf[0][j] + f02 * Cf[2][j]) + f04 * Cf[4][j];
+        B[1][j] = ((Cf[1][j] + f12 * Cf[2][j]) + f13 * Cf[3][j]) + f14 * Cf[4][j];
+        B[2][j] = Cf[2][j] + f24 * Cf[4][j];
+        B[3][j] = Cf[3][j];
+        B[4][j] = Cf[4][j];
+    }
+    for (int i = 0; i < 5; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            T v;
+            if (j == 0) v = (B[i][0] + f02 * B[i][2]) + f04 * B[i][4];
+            else if (j == 1) v = ((B[i][1] + f12 * B[i][2]) + f13 * B[i][3]) + f14 * B[i][4];
+            else if (j == 2) v = B[i][2] + f24 * B[i][4];
+            else v = B[i][j];
+            s.C[pk(i, j)] = v;
+        }
+    }
+    return true;
+}
+
+// Predicted chi2 of a measurement (my, mz) with V = diag(vy, vz): r^T S^-1 r,
+// S = C[0:2,0:2] + V, with the explicit 2x2 inverse.
+template <class T>
+struct Innov {
+    T a00, a01, a11, r0, r1, chi2;
+};
+
+template <class T>
+Innov<T> innovation(const State<T>& s, T my, T mz, const Consts<T>& k) {
+    const T one = (T)1;
+    Innov<T> n;
+    const T s00 = s.C[0] + k.vy, s01 = s.C[1], s11 = s.C[2] + k.vz;
+    const T det = s00 * s11 - s01 * s01;
+    const T idet = one / det;
+    n.a00 = s11 * idet;
+    n.a01 = (-s01) * idet;
+    n.a11 = s00 * idet;
+    n.r0 = my - s.p[0];
+    n.r1 = mz - s.p[1];
+    const T w0 = n.a00 * n.r0 + n.a01 * n.r1;
+    const T w1 = n.a01 * n.r0 + n.a11 * n.r1;
+    n.chi2 = n.r0 * w0 + n.r1 * w1;
+    return n;
+}
+
+// Kalman update with gain K = C H^T S^-1 (H selects y, z).
+template <class T>
+void update(State<T>& s, const Innov<T>& n) {
+    T c0j[5], c1j[5], K0[5], K1[5];
+    for (int j = 0; j < 5; ++j) {
+        c0j[j] = s.C[pk(0, j)];
+        c1j[j] = s.C[pk(1, j)];
+    }
+    for (int i = 0; i < 5; ++i) {
+        K0[i] = c0j[i] * n.a00 + c1j[i] * n.a01;
+        K1[i] = c0j[i] * n.a01 + c1j[i] * n.a11;
+    }
+    for (int i = 0; i < 5; ++i) s.p[i] = s.p[i] + (K0[i] * n.r0 + K1[i] * n.r1);
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j) s.C[pk(i, j)] = s.C[pk(i, j)] - (K0[i] * c0j[j] + K1[i] * c1j[j]);
+}
+
+// Covariance reset at a change of direction or a pass start: keep the
+// variances scaled up, drop the correlations.
+template <class T>
+void reset_cov(State<T>& s, const Consts<T>& k) {
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < i; ++j) s.C[pk(i, j)] = (T)0;
+    for (int i = 0; i < 5; ++i) s.C[pk(i, i)] = s.C[pk(i, i)] * k.cov_reset;
+}
+
+// ----------------------------------------------------------------------------
+struct Input {
+    int32_t n_inst;
+    const int32_t* inst_sector;
+    const int64_t* row_start;  // [n_inst * n_rows + 1]
+    const float* y;
+    const float* z;
+};
+
+template <class T>
+struct Result {
+    int n_rows = 0;
+    // grid
+    std::vector<int32_t> sorted_id;   // [N] input id at each sorted position
+    std::vector<int32_t> bin_start;   // [N + n_seg + 1]; segment s at row_start[s] + s
+    std::vector<int32_t> g_ny, g_nz;  // [n_seg]
+    std::vector<T> g_ymin, g_zmin, g_invy, g_invz;
+    // CA (input-id space)
+    std::vector<int32_t> up, dn, upc, dnc;
+    // starts and tracklets (global order: instance, row, input id)
+    std::vector<int32_t> start_hit, start_inst, start_tid;
+    std::vector<int32_t> tl_nhits, tl_rowhit;  // rowhit [N_s * n_rows], -1 = none
+    std::vector<T> tl_state;                  // [N_s * 20]: p[5], C[15]
+    std::vector<int32_t> tl_row;              // row of the state
+    std::vector<uint32_t> weight;             // [N]
+    // selected tracks (instance, tid order)
+    std::vector<int32_t> sel_tl;              // tracklet index
+    std::vector<int64_t> sel_hit_start;       // CSR over owned hits (ascending row)
+    std::vector<int32_t> sel_hit;             // input ids
+    std::vector<uint8_t> sel_mask;            // refit accept bits per owned hit (b0,b1,b2 = pass 1..3)
+    std::vector<int32_t> sel_status;          // 1 = output track, 0 = dropped
+    // output tracks
+    std::vector<int32_t> trk_inst, trk_sel, trk_ndf;
+    std::vector<T> trk_x, trk_alpha, trk_param, trk_cov, trk_chi2;
+    std::vector<int64_t> trk_hit_start;
+    std::vector<int32_t> trk_hit;
+    double chi2_total = 0;
+    int64_t ndf_total = 0;
+};
+
+// ------------------------------------------------------------------ 1. grid
+// Per (instance, row): exact y/z ranges; T = max(1, n / hits_per_bin) target
+// bins split as ny ~ sqrt(T * Ly / Lz), nz = T / ny; bin = bz * ny + by with
+// b = min(n - 1, trunc((v - vmin) * n / L)); stable counting sort by
+// (bin, input order).
+template <class T>
+void build_grid(const Input& in, const Consts<T>& k, Result<T>& R, int64_t seg) {
+    const int64_t a = in.row_start[seg], b = in.row_start[seg + 1];
+    const int64_t n = b - a;
+    int32_t* bs = R.bin_start.data() + a + seg;
+    if (n == 0) {
+        R.g_ny[seg] = R.g_nz[seg] = 1;
+        R.g_ymin[seg] = R.g_zmin[seg] = R.g_invy[seg] = R.g_invz[seg] = (T)0;
+        bs[0] = 0;  // single empty bin
+        bs[1] = 0;
+        return;
+    }
+    T ymin = (T)in.y[a], ymax = ymin, zmin = (T)in.z[a], zmax = zmin;
+    for (int64_t i = a; i < b; ++i) {
+        ymin = std::min(ymin, (T)in.y[i]); ymax = std::max(ymax, (T)in.y[i]);
+        zmin = std::min(zmin, (T)in.z[i]); zmax = std::max(zmax, (T)in.z[i]);
+    }
+    const T ly = ymax - ymin, lz = zmax - zmin;
+    const int tb = std::max<int64_t>(1, n / k.hpb);
+    int ny, nz;
+    if (ly > (T)0 && lz > (T)0) {
+        const T f = std::sqrt((T)tb * (ly / lz));
+        ny = (f >= (T)tb) ? tb : std::max(1, (int)f);
+    } else if (ly > (T)0) {
+        ny = tb;
+    } else {
+        ny = 1;
+    }
+    nz = std::max(1, tb / ny);
+    const T invy = ly > (T)0 ? (T)ny / ly : (T)0;
+    const T invz = lz > (T)0 ? (T)nz / lz : (T)0;
+    R.g_ny[seg] = ny; R.g_nz[seg] = nz;
+    R.g_ymin[seg] = ymin; R.g_zmin[seg] = zmin; R.g_invy[seg] = invy; R.g_invz[seg] = invz;
+    auto bin_of = [&](T v, T vmin, T inv, int nb) {
+        const T t = (v - vmin) * inv;
+        if (t >= (T)(nb - 1)) return nb - 1;
+        if (t <= (T)0) return 0;
+        return (int)t;
+    };
+    const int nbins = ny * nz;
+    std::vector<int32_t> cnt(nbins + 1, 0), bin(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int by = bin_of((T)in.y[a + i], ymin, invy, ny);
+        const int bz = bin_of((T)in.z[a + i], zmin, invz, nz);
+        bin[i] = bz * ny + by;
+        cnt[bin[i] + 1]++;
+    }
+    for (int q = 0; q < nbins; ++q) cnt[q + 1] += cnt[q];
+    for (int q = 0; q <= nbins; ++q) bs[q] = cnt[q];
+    for (int64_t i = 0; i < n; ++i) R.sorted_id[a + cnt[bin[i]]++] = (int32_t)(a + i);
+}
+
+// ------------------------------------------------------ 2. neighbour links
+// For hit h on row r (1 <= r <= n_rows - 2): candidates u on r+1 and d on r-1
+// inside |dy| <= dx * TY + NY, |dz| <= dx * TZ + NZ; the pair whose linear
+// interpolation at X_r misses h by the least squared distance wins, ties by
+// (id_u, id_d); no link if that score exceeds the cut.
+template <class T>
+void find_links(const Input& in, const Consts<T>& k, Result<T>& R, int inst) {
+    const int nr = k.n_rows;
+    for (int r = 1; r + 1 < nr; ++r) {
+        const int64_t seg = (int64_t)inst * nr + r;
+        const int64_t a = in.row_start[seg], b = in.row_start[seg + 1];
+        const int64_t ua = in.row_start[seg + 1], ub = in.row_start[seg + 2];
+        const int64_t da = in.row_start[seg - 1], db = in.row_start[seg];
+        for (int64_t h = a; h < b; ++h) {
+            const T yh = (T)in.y[h], zh = (T)in.z[h];
+            bool found = false;
+            T best = (T)0;
+            int64_t bu = -1, bd = -1;
+            for (int64_t u = ua; u < ub; ++u) {
+                const T yu = (T)in.y[u], zu = (T)in.z[u];
+                if (!(std::fabs(yu - yh) <= k.wyu[r] && std::fabs(zu - zh) <= k.wzu[r])) continue;
+                for (int64_t d = da; d < db; ++d) {
+                    const T yd = (T)in.y[d], zd = (T)in.z[d];
+                    if (!(std::fabs(yd - yh) <= k.wyd[r] && std::fabs(zd - zh) <= k.wzd[r])) continue;
+                    const T ey = (yd + (yu - yd) * k.tr[r]) - yh;
+                    const T ez = (zd + (zu - zd) * k.tr[r]) - zh;
+                    const T sc = ey * ey + ez * ez;
+                    if (!(sc <= k.smax)) continue;
+                    if (!found || sc < best || (sc == best && (u < bu || (u == bu && d < bd)))) {
+                        found = true;
+                        best = sc;
+                        bu = u;
+                        bd = d;
+                    }
+                }
+            }
+            R.up[h] = (int32_t)bu;
+            R.dn[h] = (int32_t)bd;
+        }
+    }
+}
+
+// ------------------------------------------- 3./4. cleaning and start hits
+template <class T>
+void clean_links(const Input& in, Result<T>& R, int inst, int nr) {
+    const int64_t a = in.row_start[(int64_t)inst * nr], b = in.row_start[(int64_t)(inst + 1) * nr];
+    for (int64_t h = a; h < b; ++h) {
+        const int32_t u = R.up[h], d = R.dn[h];
+        R.upc[h] = (u >= 0 && R.dn[u] == h) ? u : -1;
+        R.dnc[h] = (d >= 0 && R.up[d] == h) ? d : -1;
+    }
+}
+
+// ------------------------------------------------------------ 5. tracklets
+struct Pick {
+    int32_t row;
+    int32_t hit;
+};
+
+// Best hit on a row for the predicted state: inside NSIG * sqrt(S_ii) in y and
+// z, predicted chi2 <= cut, minimum chi2, ties to the smaller input id.
+template <class T>
+int64_t pick_on_row(const Input& in, const Consts<T>& k, const State<T>& s, int64_t seg, Innov<T>* out) {
+    const T s00 = s.C[0] + k.vy, s11 = s.C[2] + k.vz;
+    const T wy = k.nsig * std::sqrt(s00), wz = k.nsig * std::sqrt(s11);
+    int64_t best = -1;
+    Innov<T> bi{};
+    for (int64_t c = in.row_start[seg]; c < in.row_start[seg + 1]; ++c) {
+        const Innov<T> n = innovation(s, (T)in.y[c], (T)in.z[c], k);
+        if (!(std::fabs(n.r0) <= wy && std::fabs(n.r1) <= wz)) continue;
+        if (!(n.chi2 <= k.chi2_pick)) continue;
+        if (best < 0 || n.chi2 < bi.chi2) {  // equal chi2: the earlier (smaller) id stays
+            best = c;
+            bi = n;
+        }
+    }
+    if (best >= 0) *out = bi;
+    return best;
+}
+
+// Seed from a chain h_0..h_{L-1} (rows r0..r0+L-1): circle through the first,
+// middle and last hit in (x, y) gives the curvature and sin(phi) at h_0; the
+// z slope over the arc gives tan(lambda).
+template <class T>
+bool seed_state(const Consts<T>& k, T x0, T y0, T z0, T xm, T ym, T xe, T ye, T ze, State<T>& s) {
+    const T one = (T)1, half = (T)0.5, two = (T)2;
+    const T ax = xm - x0, ay = ym - y0, bx = xe - x0, by = ye - y0, cx = xe - xm, cy = ye - ym;
+    const T cr = ax * by - ay * bx;
+    const T d01 = std::sqrt(ax * ax + ay * ay);
+    const T d02 = std::sqrt(bx * bx + by * by);
+    const T d12 = std::sqrt(cx * cx + cy * cy);
+    const T kap = (two * cr) / ((d01 * d02) * d12);
+    T v = (kap * d02) * half;
+    if (v > one) v = one;
+    if (v < -one) v = -one;
+    const T sn = by / d02, cs = bx / d02;
+    const T s0 = sn * std::sqrt(one - v * v) - cs * v;
+    const T arc = d02 * asin_over(v);
+    const T t0 = (ze - z0) / arc;
+    T q0 = (k.kB != (T)0) ? kap / k.kB : (T)0;
+    if (q0 > k.q_max) q0 = k.q_max;
+    if (q0 < -k.q_max) q0 = -k.q_max;
+    if (!(std::fabs(s0) < k.sinphi_max)) return false;
+    s.p[0] = y0; s.p[1] = z0; s.p[2] = s0; s.p[3] = t0; s.p[4] = q0;
+    for (int i = 0; i < 15; ++i) s.C[i] = (T)0;
+    for (int i = 0; i < 5; ++i) s.C[pk(i, i)] = k.c0[i];
+    return true;
+}
+
+template <class T>
+void build_tracklet(const Input& in, const Consts<T>& k, Result<T>& R, int64_t sidx) {
+    const int nr = k.n_rows;
+    const int inst = R.start_inst[sidx];
+    const int64_t seg0 = (int64_t)inst * nr;
+    int32_t* rowhit = R.tl_rowhit.data() + sidx * nr;
+    for (int r = 0; r < nr; ++r) rowhit[r] = -1;
+    R.tl_nhits[sidx] = 0;
+    R.tl_row[sidx] = -1;
+    // chain via the cleaned up-links
+    std::vector<int32_t> chain;
+    for (int32_t h = R.start_hit[sidx]; h >= 0; h = R.upc[h]) chain.push_back(h);
+    const int L = (int)chain.size();
+    auto row_of = [&](int64_t h) {
+        return (int)(std::upper_bound(in.row_start + seg0, in.row_start + seg0 + nr + 1, (int64_t)h) -
+                     (in.row_start + seg0)) - 1;
+    };
+    const int r0 = row_of(chain[0]);
+    const int m = (L - 1) / 2, e = L - 1;
+    State<T> s;
+    const int32_t h0 = chain[0], hm = chain[m], he = chain[e];
+    if (!seed_state(k, k.X[r0], (T)in.y[h0], (T)in.z[h0], k.X[r0 + m], (T)in.y[hm], k.X[r0 + e], (T)in.y[he],
+                    (T)in.z[he], s))
+        return;
+    // stage 1: simplified filter over the chain, no gating
+    for (int i = 0; i < L; ++i) {
+        if (i > 0 && !propagate(s, k.X[r0 + i - 1], k.X[r0 + i], k)) return;
+        const Innov<T> n = innovation(s, (T)in.y[chain[i]], (T)in.z[chain[i]], k);
+        update(s, n);
+    }
+    // stage 2: outward following
+    int cur = r0 + e, last = r0 + e, miss = 0;
+    for (int r = cur + 1; r < nr && miss < k.max_miss; ++r) {
+        if (!propagate(s, k.X[r - 1], k.X[r], k)) break;
+        cur = r;
+        Innov<T> n;
+        if (pick_on_row(in, k, s, seg0 + r, &n) >= 0) {
+            update(s, n);
+            last = r;
+            miss = 0;
+        } else {
+            ++miss;
+        }
+    }
+    // turn, stage 3: inward through the seed, re-picking every row
+    reset_cov(s, k);
+    bool ok = true;
+    for (int r = cur - 1; r >= last; --r) {
+        if (!propagate(s, k.X[r + 1], k.X[r], k)) { ok = false; break; }
+        cur = r;
+    }
+    int nh = 0;
+    if (ok) {
+        miss = 0;
+        for (int r = last; r >= 0; --r) {
+            if (r != cur) {
+                if (!propagate(s, k.X[cur], k.X[r], k)) break;
+                cur = r;
+            }
+            Innov<T> n;
+            const int64_t c = pick_on_row(in, k, s, seg0 + r, &n);
+            if (c >= 0) {
+                update(s, n);
+                rowhit[r] = (int32_t)c;
+                ++nh;
+                miss = 0;
+            } else if (++miss >= k.max_miss) {
+                break;
+            }
+        }
+    }
+    R.tl_nhits[sidx] = nh;
+    R.tl_row[sidx] = cur;
+    T* st = R.tl_state.data() + sidx * 20;
+    for (int i = 0; i < 5; ++i) st[i] = s.p[i];
+    for (int i = 0; i < 15; ++i) st[5 + i] = s.C[i];
+}
+
+// ---------------------------------------------------------------- 7. refit
+// Three passes inward, outward, inward over the hit rows, each starting with a
+// covariance reset; a hit whose predicted chi2 exceeds the cut is skipped in
+// that pass. Propagation is row by row. With `replay` set the accept decisions
+// are read from it instead of being taken (FP64 replay of an FP32 result).
+template <class T>
+struct RefitOut {
+    bool ok;
+    State<T> s;
+    T chi2;
+    int nacc;
+    int row;  // row of the output state (innermost hit)
+};
+
+template <class T>
+RefitOut<T> refit(const Consts<T>& k, State<T> s, int row, int n, const int32_t* rows, const T* ys, const T* zs,
+                  uint8_t* masks, const uint8_t* replay) {
+    RefitOut<T> o{};
+    o.ok = false;
+    int cur = row;
+    auto move_to = [&](int target) {
+        while (cur != target) {
+            const int nx = cur < target ? cur + 1 : cur - 1;
+            if (!propagate(s, k.X[cur], k.X[nx], k)) return false;
+            cur = nx;
+        }
+        return true;
+    };
+    if (n <= 0 || !move_to(rows[n - 1])) return o;
+    for (int i = 0; i < n; ++i) masks[i] = 0;
+    T chi2sum = (T)0;
+    int nacc = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+        reset_cov(s, k);
+        const bool inward = (pass != 1);
+        for (int q = 0; q < n; ++q) {
+            const int i = inward ? n - 1 - q : q;
+            if (!move_to(rows[i])) return o;
+            const Innov<T> in = innovation(s, ys[i], zs[i], k);
+            const bool acc = replay ? ((replay[i] >> pass) & 1) != 0 : (in.chi2 <= k.chi2_rej);
+            if (acc) {
+                update(s, in);
+                masks[i] |= (uint8_t)(1u << pass);
+                if (pass == 2) {
+                    chi2sum = chi2sum + in.chi2;
+                    ++nacc;
+                }
+            }
+        }
+    }
+    o.ok = true;
+    o.s = s;
+    o.chi2 = chi2sum;
+    o.nacc = nacc;
+    o.row = cur;
+    return o;
+}
+
+// ----------------------------------------------------------------- driver
+template <class T>
+void run_instance_ca(const Input& in, const Consts<T>& k, Result<T>& R, int inst) {
+    const int nr = k.n_rows;
+    for (int r = 0; r < nr; ++r) build_grid(in, k, R, (int64_t)inst * nr + r);
+    find_links(in, k, R, inst);
+}
+
+template <class T>
+Result<T>* run(const orc_params& p, const Input& in) {
+    const Consts<T> k(p);
+    const int nr = k.n_rows;
+    auto* R = new Result<T>;
+    R->n_rows = nr;
+    const int64_t nseg = (int64_t)in.n_inst * nr;
+    const int64_t N = in.row_start[nseg];
+    R->sorted_id.assign(N, -1);
+    R->bin_start.assign(N + nseg + 1, 0);
+    R->g_ny.assign(nseg, 0); R->g_nz.assign(nseg, 0);
+    R->g_ymin.assign(nseg, 0); R->g_zmin.assign(nseg, 0); R->g_invy.assign(nseg, 0); R->g_invz.assign(nseg, 0);
+    R->up.assign(N, -1); R->dn.assign(N, -1); R->upc.assign(N, -1); R->dnc.assign(N, -1);
+    R->weight.assign(N, 0);
+    const int nthreads = std::max(1, p.n_threads);
+    auto parallel_over = [&](int64_t count, auto fn) {
+        if (nthreads == 1 || count < 2) {
+            for (int64_t i = 0; i < count; ++i) fn(i);
+            return;
+        }
+        std::vector<std::thread> th;
+        for (int t = 0; t < nthreads; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t i = t; i < count; i += nthreads) fn(i);
+            });
+        for (auto& x : th) x.join();
+    };
+    parallel_over(in.n_inst, [&](int64_t i) { run_instance_ca(in, k, *R, (int)i); });
+    parallel_over(in.n_inst, [&](int64_t i) { clean_links(in, *R, (int)i, nr); });
+    // start hits, ordered by (instance, row, input id)
+    for (int inst = 0; inst < in.n_inst; ++inst) {
+        int32_t tid = 0;
+        const int64_t a = in.row_start[(int64_t)inst * nr], b = in.row_start[(int64_t)(inst + 1) * nr];
+        for (int64_t h = a; h < b; ++h) {
+            const int32_t u = R->upc[h];
+            if (R->dnc[h] == -1 && u != -1 && R->upc[u] != -1) {
+                R->start_hit.push_back((int32_t)h);
+                R->start_inst.push_back(inst);
+                R->start_tid.push_back(tid++);
+            }
+        }
+    }
+    const int64_t ns = (int64_t)R->start_hit.size();
+    R->tl_nhits.assign(ns, 0);
+    R->tl_row.assign(ns, -1);
+    R->tl_rowhit.assign(ns * nr, -1);
+    R->tl_state.assign(ns * 20, 0);
+    parallel_over(ns, [&](int64_t i) { build_tracklet(in, k, *R, i); });
+    // weights: max over tracklets of (nHits << 20) | (0xFFFFF - tid)
+    for (int64_t i = 0; i < ns; ++i) {
+        const int nh = R->tl_nhits[i];
+        if (nh < k.n_min) continue;
+        const uint32_t w = ((uint32_t)nh << 20) | (uint32_t)(0xFFFFF - R->start_tid[i]);
+        for (int r = 0; r < nr; ++r) {
+            const int32_t h = R->tl_rowhit[i * nr + r];
+            if (h >= 0) R->weight[h] = std::max(R->weight[h], w);
+        }
+    }
+    // selection
+    R->sel_hit_start.push_back(0);
+    for (int64_t i = 0; i < ns; ++i) {
+        const int nh = R->tl_nhits[i];
+        if (nh < k.n_min) continue;
+        const uint32_t w = ((uint32_t)nh << 20) | (uint32_t)(0xFFFFF - R->start_tid[i]);
+        std::vector<int32_t> own;
+        for (int r = 0; r < nr; ++r) {
+            const int32_t h = R->tl_rowhit[i * nr + r];
+            if (h >= 0 && R->weight[h] == w) own.push_back(h);
+        }
+        if ((int)own.size() < k.n_min) continue;
+        R->sel_tl.push_back((int32_t)i);
+        R->sel_hit.insert(R->sel_hit.end(), own.begin(), own.end());
+        R->sel_hit_start.push_back((int64_t)R->sel_hit.size());
+    }
+    // refit
+    const int64_t nsel = (int64_t)R->sel_tl.size();
+    R->sel_mask.assign(R->sel_hit.size(), 0);
+    R->sel_status.assign(nsel, 0);
+    std::vector<RefitOut<T>> outs(nsel);
+    parallel_over(nsel, [&](int64_t t) {
+        const int64_t tl = R->sel_tl[t];
+        const int inst = R->start_inst[tl];
+        const int64_t a = R->sel_hit_start[t], b = R->sel_hit_start[t + 1];
+        const int n = (int)(b - a);
+        std::vector<int32_t> rows(n);
+        std::vector<T> ys(n), zs(n);
+        const int64_t seg0 = (int64_t)inst * nr;
+        for (int i = 0; i < n; ++i) {
+            const int32_t h = R->sel_hit[a + i];
+            rows[i] = (int)(std::upper_bound(in.row_start + seg0, in.row_start + seg0 + nr + 1, (int64_t)h) -
+                            (in.row_start + seg0)) - 1;
+            ys[i] = (T)in.y[h];
+            zs[i] = (T)in.z[h];
+        }
+        State<T> s;
+        const T* st = R->tl_state.data() + tl * 20;
+        for (int i = 0; i < 5; ++i) s.p[i] = st[i];
+        for (int i = 0; i < 15; ++i) s.C[i] = st[5 + i];
+        outs[t] = refit(k, s, R->tl_row[tl], n, rows.data(), ys.data(), zs.data(), R->sel_mask.data() + a, nullptr);
+        R->sel_status[t] = (outs[t].ok && outs[t].nacc >= k.n_min) ? 1 : 0;
+    });
+    R->trk_hit_start.push_back(0);
+    for (int64_t t = 0; t < nsel; ++t) {
+        if (!R->sel_status[t]) continue;
+        const RefitOut<T>& o = outs[t];
+        const int64_t tl = R->sel_tl[t];
+        const int inst = R->start_inst[tl];
+        R->trk_inst.push_back(inst);
+        R->trk_sel.push_back((int32_t)t);
+        R->trk_x.push_back(k.X[o.row]);
+        const int sec = in.inst_sector[inst];
+        R->trk_alpha.push_back((T)(((sec % 18) + 0.5) * 20.0 * 3.14159265358979323846 / 180.0));
+        for (int i = 0; i < 5; ++i) R->trk_param.push_back(o.s.p[i]);
+        for (int i = 0; i < 15; ++i) R->trk_cov.push_back(o.s.C[i]);
+        R->trk_chi2.push_back(o.chi2);
+        R->trk_ndf.push_back(2 * o.nacc - 5);
+        for (int64_t q = R->sel_hit_start[t]; q < R->sel_hit_start[t + 1]; ++q)
+            if (R->sel_mask[q] & 4) R->trk_hit.push_back(R->sel_hit[q]);
+        R->trk_hit_start.push_back((int64_t)R->trk_hit.size());
+        R->chi2_total += (double)o.chi2;
+        R->ndf_total += 2 * o.nacc - 5;
+    }
+    return R;
+}
+
+struct Handle {
+    int prec;  // 32 or 64
+    void* r;
+};
+
+template <class T>
+Result<T>* res(void* h) { return (Result<T>*)((Handle*)h)->r; }
+
+template <class T, class U>
+void copy_out(const std::vector<T>& v, U* dst) {
+    if (dst)
+        for (size_t i = 0; i < v.size(); ++i) dst[i] = (U)v[i];
+}
+
+// state: p[5] then C[15] as double (values are rounded to T on load).
+template <class T>
+void load_state(const double* st, State<T>& s) {
+    for (int i = 0; i < 5; ++i) s.p[i] = (T)st[i];
+    for (int i = 0; i < 15; ++i) s.C[i] = (T)st[5 + i];
+}
+template <class T>
+void store_state(const State<T>& s, double* st) {
+    for (int i = 0; i < 5; ++i) st[i] = (double)s.p[i];
+    for (int i = 0; i < 15; ++i) st[5 + i] = (double)s.C[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+void* orc_run(const orc_params* p, int32_t precision, int32_t n_inst, const int32_t* inst_sector,
+              const int64_t* row_start, const float* y, const float* z) {
+    Input in{n_inst, inst_sector, row_start, y, z};
+    auto* h = new Handle;
+    h->prec = precision;
+    if (precision == 32) h->r = run<float>(*p, in);
+    else h->r = run<double>(*p, in);
+    return h;
+}
+
+void orc_free(void* h) {
+    if (!h) return;
+    Handle* H = (Handle*)h;
+    if (H->prec == 32) delete res<float>(h);
+    else delete res<double>(h);
+    delete H;
+}
+
+// sizes: [0] N, [1] n_starts, [2] n_selected, [3] n_selected_hits, [4] n_tracks, [5] n_track_hits
+void orc_sizes(void* h, int64_t* s) {
+    auto f = [&](auto* R) {
+        s[0] = (int64_t)R->up.size();
+        s[1] = (int64_t)R->start_hit.size();
+        s[2] = (int64_t)R->sel_tl.size();
+        s[3] = (int64_t)R->sel_hit.size();
+        s[4] = (int64_t)R->trk_inst.size();
+        s[5] = (int64_t)R->trk_hit.size();
+    };
+    if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
+}
+
+void orc_get_grid(void* h, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz, double* ymin,
+                  double* zmin, double* invy, double* invz) {
+    auto f = [&](auto* R) {
+        copy_out(R->sorted_id, sorted_id); copy_out(R->bin_start, bin_start);
+        copy_out(R->g_ny, ny); copy_out(R->g_nz, nz); copy_out(R->g_ymin, ymin); copy_out(R->g_zmin, zmin);
+        copy_out(R->g_invy, invy); copy_out(R->g_invz, invz);
+    };
+    if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
+}
+
+void orc_get_links(void* h, int32_t* up, int32_t* dn, int32_t* upc, int32_t* dnc) {
+    auto f = [&](auto* R) { copy_out(R->up, up); copy_out(R->dn, dn); copy_out(R->upc, upc); copy_out(R->dnc, dnc); };
+    if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
+}
+
+void orc_get_tracklets(void* h, int32_t* start_hit, int32_t* start_inst, int32_t* start_tid, int32_t* nhits,
+                       int32_t* rowhit, double* state, int32_t* state_row, uint32_t* weight) {
+    auto f = [&](auto* R) {
+        copy_out(R->start_hit, start_hit); copy_out(R->start_inst, start_inst); copy_out(R->start_tid, start_tid);
+        copy_out(R->tl_nhits, nhits); copy_out(R->tl_rowhit, rowhit); copy_out(R->tl_state, state);
+        copy_out(R->tl_row, state_row); copy_out(R->weight, weight);
+    };
+    if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
+}
+
+void orc_get_selected(void* h, int32_t* sel_tl, int64_t* hit_start, int32_t* hit, uint8_t* mask, int32_t* status) {
+    auto f = [&](auto* R) {
+        copy_out(R->sel_tl, sel_tl); copy_out(R->sel_hit_start, hit_start); copy_out(R->sel_hit, hit);
+        copy_out(R->sel_mask, mask); copy_out(R->sel_status, status);
+    };
+    if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
+}
+
+void orc_get_tracks(void* h, int32_t* inst, int32_t* sel, double* x, double* alpha, double* param, double* cov,
+                    double* chi2, int32_t* ndf, int64_t* hit_start, int32_t* hit, double* totals) {
+    auto f = [&](auto* R) {
+        copy_out(R->trk_inst, inst); copy_out(R->trk_sel, sel); copy_out(R->trk_x, x); copy_out(R->trk_alpha, alpha);
+        copy_out(R->trk_param, param); copy_out(R->trk_cov, cov); copy_out(R->trk_chi2, chi2);
+        copy_out(R->trk_ndf, ndf); copy_out(R->trk_hit_start, hit_start); copy_out(R->trk_hit, hit);
+        if (totals) {
+            totals[0] = R->chi2_total;
+            totals[1] = (double)R->ndf_total;
+        }
+    };
+    if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
+}
+
+// ---- primitives (for pinning the oracle against closed forms) -----------
+int32_t orc_propagate(const orc_params* p, int32_t precision, double* st, double x1, double x2) {
+    auto f = [&](auto zero) -> int32_t {
+        using T = decltype(zero);
+        Consts<T> k(*p);
+        State<T> s;
+        load_state(st, s);
+        if (!propagate(s, (T)x1, (T)x2, k)) return 0;
+        store_state(s, st);
+        return 1;
+    };
+    return precision == 32 ? f(0.0f) : f(0.0);
+}
+
+double orc_update(const orc_params* p, int32_t precision, double* st, double my, double mz) {
+    auto f = [&](auto zero) -> double {
+        using T = decltype(zero);
+        Consts<T> k(*p);
+        State<T> s;
+        load_state(st, s);
+        const Innov<T> n = innovation(s, (T)my, (T)mz, k);
+        update(s, n);
+        store_state(s, st);
+        return (double)n.chi2;
+    };
+    return precision == 32 ? f(0.0f) : f(0.0);
+}
+
+double orc_asin_over(int32_t precision, double u) {
+    return precision == 32 ? (double)asin_over((float)u) : asin_over(u);
+}
+
+int32_t orc_seed(const orc_params* p, int32_t precision, const double* pts /* x0 y0 z0 xm ym xe ye ze */,
+                 double* st) {
+    auto f = [&](auto zero) -> int32_t {
+        using T = decltype(zero);
+        Consts<T> k(*p);
+        State<T> s;
+        if (!seed_state(k, (T)pts[0], (T)pts[1], (T)pts[2], (T)pts[3], (T)pts[4], (T)pts[5], (T)pts[6],
+                        (T)pts[7], s))
+            return 0;
+        store_state(s, st);
+        return 1;
+    };
+    return precision == 32 ? f(0.0f) : f(0.0);
+}
+
+// Refit of one hit list (rows ascending) from a start state at `row`.
+// out: state[20] at the innermost hit; out_scalars: chi2, nacc, row.
+// replay (may be NULL): accept bits per hit to reproduce instead of deciding.
+int32_t orc_refit(const orc_params* p, int32_t precision, const double* st0, int32_t row, int32_t n,
+                  const int32_t* rows, const double* ys, const double* zs, const uint8_t* replay, uint8_t* masks,
+                  double* st_out, double* scalars) {
+    auto f = [&](auto zero) -> int32_t {
+        using T = decltype(zero);
+        Consts<T> k(*p);
+        State<T> s;
+        load_state(st0, s);
+        std::vector<T> y(n), z(n);
+        for (int i = 0; i < n; ++i) {
+            y[i] = (T)ys[i];
+            z[i] = (T)zs[i];
+        }
+        RefitOut<T> o = refit(k, s, row, n, rows, y.data(), z.data(), masks, replay);
+        if (!o.ok) return 0;
+        store_state(o.s, st_out);
+        scalars[0] = (double)o.chi2;
+        scalars[1] = (double)o.nacc;
+        scalars[2] = (double)o.row;
+        return 1;
+    };
+    return precision == 32 ? f(0.0f) : f(0.0);
+}
+
+// FP64 replay of selected tracks: start states (FP32 tracklet states) and
+// accept masks are given; returns params/cov/chi2 of pass 3 in double.
+void orc_replay_f64(const orc_params* p, int64_t n_tracks, const double* st0, const int32_t* row0,
+                    const int64_t* hit_start, const int32_t* hit_rows, const double* ys, const double* zs,
+                    const uint8_t* masks, double* st_out, double* chi2_out, int32_t* ok_out) {
+    Consts<double> k(*p);
+    for (int64_t t = 0; t < n_tracks; ++t) {
+        State<double> s;
+        load_state(st0 + 20 * t, s);
+        const int64_t a = hit_start[t];
+        const int n = (int)(hit_start[t + 1] - a);
+        std::vector<uint8_t> m(n);
+        RefitOut<double> o = refit(k, s, row0[t], n, hit_rows + a, ys + a, zs + a, m.data(), masks + a);
+        ok_out[t] = o.ok ? 1 : 0;
+        if (o.ok) {
+            store_state(o.s, st_out + 20 * t);
+            chi2_out[t] = o.chi2;
+        }
+    }
+}
+
+}  // extern "C"
