@@ -1,0 +1,192 @@
+/*
+ * tpcca.h — C ABI of the MI355X TPC sector tracker.
+ *
+ * Computes the sector-tracking hot path of Rohr et al., "Track Reconstruction
+ * in the ALICE TPC using GPUs for LHC Run 3" (arXiv:1811.11481), Section 2
+ * (cellular-automaton seeding, Kalman-filter track following, final fit) with
+ * the resolution changes of Section 3 (inward pass through the seed with
+ * outlier rejection, chi2-based cluster rejection, three-pass refit):
+ *   clusters per sector instance and pad row in,
+ *   tracks with five parameters, covariance, chi2 and cluster lists out.
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless a
+ *    comment says "host". It must stay valid until the stream has completed
+ *    the call.
+ *  - Clusters are given per instance (one sector of one event or time frame)
+ *    and pad row as a CSR over rows: row_start[k * n_rows + r] is the first
+ *    cluster of row r of instance k; clusters of a row are contiguous and the
+ *    cluster id used everywhere (outputs, exports) is the index into y/z.
+ *    Coordinates are sector-local: x is the pad-row plane params.row_x[r], y
+ *    along the row, z along the drift (any origin: only z differences are used).
+ *  - All track arithmetic is IEEE binary32 in a fixed operation order (no FMA
+ *    contraction); only cross-track sums are FP64.
+ *  - Status codes are the only error channel; tpcca_last_error() gives text.
+ *    Calls are asynchronous on `hip_stream` except where a host output is
+ *    returned (track counts), which synchronises the stream once.
+ *  - A context is used by one host thread at a time (not thread-safe) and owns
+ *    scratch device memory that grows on demand and is reused.
+ */
+#ifndef TPCCA_H
+#define TPCCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TPCCA_OK = 0,
+    TPCCA_E_ARG = 1,      /* invalid argument or malformed input (detected on host or device) */
+    TPCCA_E_CAPACITY = 2, /* output capacity too small (required sizes are returned) or a
+                             per-row / per-instance hard limit exceeded */
+    TPCCA_E_DEVICE = 3,   /* HIP runtime error */
+    TPCCA_E_OOM = 4,      /* device allocation failed */
+    TPCCA_E_INTERNAL = 5
+} tpcca_status;
+
+typedef struct tpcca_ctx tpcca_ctx;
+
+#define TPCCA_MAX_ROWS 255
+#define TPCCA_MAX_ROW_CLUSTERS 16384   /* clusters of one pad row of one instance */
+#define TPCCA_MAX_STARTS_PER_INST 1048576 /* tracklet ids are 20-bit per instance */
+
+/* Tracking parameters. Defaults (tpcca_default_params) are the readings of
+ * the paper recorded with the algorithm description; doubles are rounded to
+ * binary32 once when a context is created. */
+typedef struct {
+    int32_t n_rows;               /* pad rows per instance (1..255), default 152 */
+    float row_x[256];             /* pad-row plane x [cm], strictly increasing; default 85 + i*162/151 */
+    double bz;                    /* solenoid field [T] (Bx = By = 0), default 0.5 */
+    double sigma_y, sigma_z;      /* cluster errors [cm], default 0.1 */
+    double win_ty, win_tz;        /* neighbour window slope terms, default 2.0, 1.1 */
+    double win_ny, win_nz;        /* neighbour window constant terms [cm], default 0.5 */
+    double nbr_score_max;         /* max straight-line deviation of a triplet [cm^2], 0.24 */
+    double nsig;                  /* pickup window in sigmas, 3 */
+    double chi2_pick;             /* pickup chi2 cut (2 dof), 16 */
+    double chi2_rej;              /* refit rejection chi2 cut (2 dof), 25 */
+    double sinphi_max;            /* |sin phi| guard, 0.95 */
+    double cov_reset;             /* variance scale at a covariance reset, 100 */
+    double q_max;                 /* |q/pT| clamp of the seed [c/GeV], 20 */
+    double u_max;                 /* max |curvature * chord / 2| per step, 0.25 */
+    double c0[5];                 /* seed covariance diagonal, (1, 1, 0.25, 0.25, 400) */
+    int32_t n_min;                /* min clusters of a tracklet and of a track, 10 */
+    int32_t max_miss;             /* consecutive empty rows ending the following, 8 */
+    uint32_t flags;               /* TPCCA_FLAG_* */
+} tpcca_params;
+
+#define TPCCA_FLAG_STATS 1u       /* count work items (rows visited, candidates) for the byte model */
+
+/* Launch/tiling choices. They never change results (tested bit-exact). */
+typedef struct {
+    int32_t hits_per_bin;     /* grid occupancy target per bin (>= 1), default 2 */
+    int32_t block_links;      /* threads per block of the neighbour kernel (64..1024), default 256 */
+    int32_t block_tracklet;   /* threads per block of the tracklet kernel, default 128 */
+    int32_t block_refit;      /* threads per block of the refit kernel, default 128 */
+    int32_t block_scan;       /* threads per block of scans/compactions, default 256 */
+    int32_t sort_seeds;       /* 1: process seeds in an order grouped by chain length (default 1) */
+} tpcca_tuning;
+
+/* Input clusters (device pointers, caller-owned). */
+typedef struct {
+    int32_t n_inst;             /* number of sector instances (>= 0) */
+    const int32_t* inst_sector; /* [n_inst] geometric sector 0..35 (alpha = ((s mod 18) + 0.5) * 20 deg) */
+    const int64_t* row_start;   /* [n_inst * n_rows + 1] CSR over (instance, row); row_start[0] = 0,
+                                   non-decreasing, last = n_clusters */
+    const float* y;             /* [n_clusters] local y [cm] */
+    const float* z;             /* [n_clusters] z [cm] */
+    int64_t n_clusters;         /* host value */
+} tpcca_clusters;
+
+/* Output tracks (device pointers with capacities, caller-owned). Tracks are
+ * ordered by (instance, tracklet id); each track's clusters by ascending row. */
+typedef struct {
+    int64_t cap_tracks;   /* host: capacity of the per-track arrays */
+    int64_t cap_hits;     /* host: capacity of hit_id */
+    int32_t* inst;        /* [cap_tracks] instance */
+    float* x_ref;         /* [cap_tracks] local x of the parameters (innermost cluster's row plane) */
+    float* alpha;         /* [cap_tracks] sector rotation angle [rad] */
+    float* param;         /* [cap_tracks * 5] y, z, sin phi, tan lambda, q/pT */
+    float* cov;           /* [cap_tracks * 15] packed lower triangle 00,10,11,20,21,22,30,..,44 */
+    float* chi2;          /* [cap_tracks] sum of accepted predicted chi2 of the last pass */
+    int32_t* ndf;         /* [cap_tracks] 2 * clusters - 5 */
+    int64_t* hit_start;   /* [cap_tracks + 1] CSR into hit_id */
+    int32_t* hit_id;      /* [cap_hits] cluster ids */
+    double* chi2_total;   /* [2] FP64: sum of chi2, sum of ndf (deterministic order) */
+    int64_t n_tracks;     /* host, written on return: tracks found (even if above capacity) */
+    int64_t n_hits;       /* host, written on return */
+} tpcca_tracks;
+
+/* Work counters collected when TPCCA_FLAG_STATS is set (host struct). */
+typedef struct {
+    int64_t n_clusters, n_segments, n_links, n_starts, n_chain_hits;
+    int64_t tl_rows_visited, tl_candidates, tl_picks;
+    int64_t n_selected, n_selected_hits, n_tracks, n_track_hits;
+    int64_t rf_rows_visited, rf_hit_visits;
+    int64_t nb_candidates_u, nb_pairs;
+} tpcca_stats;
+
+tpcca_status tpcca_default_params(tpcca_params* out);          /* host */
+tpcca_status tpcca_default_tuning(tpcca_tuning* out);          /* host */
+
+/* Create a context on HIP device `device` with copies of params and tuning
+ * (tuning may be NULL = defaults). */
+tpcca_status tpcca_create(const tpcca_params* params, const tpcca_tuning* tuning, int device,
+                          tpcca_ctx** out);
+void tpcca_destroy(tpcca_ctx* ctx);
+const char* tpcca_last_error(const tpcca_ctx* ctx);
+tpcca_status tpcca_set_tuning(tpcca_ctx* ctx, const tpcca_tuning* tuning);
+tpcca_status tpcca_get_tuning(const tpcca_ctx* ctx, tpcca_tuning* out);
+
+/* Plain form: every stage is launched once per instance, instances one after
+ * another on `hip_stream`. */
+tpcca_status tpcca_track(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* hip_stream);
+
+/* Batched form: every stage is launched once over all instances; the launch
+ * sequence is captured in a HIP graph and replayed while pointers, sizes and
+ * tuning are unchanged. Output identical to tpcca_track (bit for bit). */
+tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out,
+                                 void* hip_stream);
+
+/* Time the batched form over candidate tunings on `sample` (median of
+ * `repeats` runs each) and write the fastest to *out (also set on ctx).
+ * Outputs go to internal buffers. */
+tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_t repeats,
+                            tpcca_tuning* out, void* hip_stream);
+
+/* ---- exports of intermediate results of the last track call (device
+ * outputs in cluster-id space; sizes from tpcca_export_sizes). ---- */
+/* host sizes[8]: n_clusters, n_segments, n_starts, n_selected, n_selected_hits, n_tracks, n_track_hits, n_rows */
+tpcca_status tpcca_export_sizes(tpcca_ctx* ctx, int64_t* sizes, void* hip_stream);
+/* sorted_id[n_clusters]: cluster id at each grid position; bin_start[n_clusters + n_segments + 1]
+ * (segment s at offset row_start[s] + s); ny, nz[n_segments]; meta[n_segments*4]: ymin zmin inv_y inv_z */
+tpcca_status tpcca_export_grid(tpcca_ctx* ctx, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz,
+                               float* meta, void* hip_stream);
+/* neighbour links and cleaned links per cluster id (-1 = none) */
+tpcca_status tpcca_export_links(tpcca_ctx* ctx, int32_t* up, int32_t* dn, int32_t* up_clean, int32_t* dn_clean,
+                                void* hip_stream);
+/* per start (order instance, row, cluster id): start cluster, instance, tracklet id, nHits, rowhit
+ * [n_starts * n_rows] (cluster id or -1), state [n_starts * 20] (p[5], C[15]), state row; weight[n_clusters] */
+tpcca_status tpcca_export_tracklets(tpcca_ctx* ctx, int32_t* start_hit, int32_t* start_inst, int32_t* start_tid,
+                                    int32_t* nhits, int32_t* rowhit, float* state, int32_t* state_row,
+                                    uint32_t* weight, void* hip_stream);
+/* per selected tracklet: tracklet index, hit_start[n_selected+1], owned cluster ids (ascending row),
+ * refit accept bits per cluster (bit k = pass k+1), status (1 = output track) */
+tpcca_status tpcca_export_selected(tpcca_ctx* ctx, int32_t* sel_tl, int64_t* hit_start, int32_t* hit_id,
+                                   uint8_t* mask, int32_t* status, void* hip_stream);
+tpcca_status tpcca_get_stats(tpcca_ctx* ctx, tpcca_stats* out); /* host out; syncs */
+/* Stage timing of the last batched call (host out, ms): weights clear + grid, links, clean + starts,
+ * tracklets, selection, refit, compaction into the outputs, FP64 totals. Filled only when the
+ * context was created with TPCCA_FLAG_STATS (the batched form then runs without graph capture). */
+tpcca_status tpcca_get_stage_times(tpcca_ctx* ctx, float* ms8);
+
+/* Arithmetic self-check: out_div[i] = a[i] / b[i], out_sqrt[i] = sqrt(|a[i]|) with the
+ * library's binary32 operations (for bit comparison with a CPU). Synchronous. */
+tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div, float* out_sqrt, int64_t n,
+                                  void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPCCA_H */

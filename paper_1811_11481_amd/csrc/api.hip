@@ -1,0 +1,769 @@
+// Host runtime of the TPC sector tracker: the C ABI declared in
+// include/tpcca.h. Owns the per-context constants and scratch arena, checks
+// inputs, enqueues the stage kernels (per instance for the plain form, once
+// over all instances for the batched form), captures the batched sequence in
+// a HIP graph, and reads back the track counts.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tpcca.h"
+#include "internal.h"
+
+using namespace tpcca;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Arena {
+    void* base = nullptr;
+    size_t bytes = 0;
+    int64_t N = -1, nseg = -1, ninst = -1;
+    int nr = 0;
+};
+
+struct GraphKey {
+    const void* p[12];
+    int64_t v[8];
+    bool operator==(const GraphKey& o) const {
+        return std::memcmp(p, o.p, sizeof(p)) == 0 && std::memcmp(v, o.v, sizeof(v)) == 0;
+    }
+};
+
+}  // namespace
+
+struct tpcca_ctx {
+    int device = 0;
+    tpcca_params params{};
+    tpcca_tuning tuning{};
+    DevConsts hK{};
+    DevConsts* dK = nullptr;
+    Counters* dctr = nullptr;
+    Counters* hctr = nullptr;  // pinned
+    int64_t* h_rowstart = nullptr;  // pinned
+    size_t h_rowstart_cap = 0;
+    Arena arena;
+    std::string err;
+    // last call
+    bool has_last = false;
+    Bufs last{};
+    int64_t last_nseg = 0;
+    Counters last_ctr{};
+    // graph of the batched form
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey{};
+    bool has_graph = false;
+    // stage timing
+    hipEvent_t ev[9] = {};
+    hipStream_t own_stream = nullptr;
+    bool events = false;
+    float stage_ms[8] = {};
+};
+
+namespace {
+
+tpcca_status fail(tpcca_ctx* c, tpcca_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+tpcca_status hip_fail(tpcca_ctx* c, hipError_t e, const char* where) {
+    return fail(c, e == hipErrorOutOfMemory ? TPCCA_E_OOM : TPCCA_E_DEVICE,
+                std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+void build_consts(const tpcca_params& p, DevConsts& K) {
+    std::memset(&K, 0, sizeof(K));
+    K.n_rows = p.n_rows;
+    K.n_min = p.n_min;
+    K.max_miss = p.max_miss;
+    K.stats = (p.flags & TPCCA_FLAG_STATS) ? 1 : 0;
+    for (int i = 0; i < p.n_rows; ++i) K.X[i] = p.row_x[i];
+    const float ty = (float)p.win_ty, tz = (float)p.win_tz, ny = (float)p.win_ny, nz = (float)p.win_nz;
+    for (int r = 1; r + 1 < p.n_rows; ++r) {
+        const float du = K.X[r + 1] - K.X[r];
+        const float dd = K.X[r] - K.X[r - 1];
+        K.wyu[r] = du * ty + ny;
+        K.wzu[r] = du * tz + nz;
+        K.wyd[r] = dd * ty + ny;
+        K.wzd[r] = dd * tz + nz;
+        K.tr[r] = (K.X[r] - K.X[r - 1]) / (K.X[r + 1] - K.X[r - 1]);
+    }
+    for (int s = 0; s < 18; ++s) K.alpha[s] = (float)((s + 0.5) * 20.0 * kPi / 180.0);
+    K.kB = (float)(-0.00299792458 * p.bz);
+    const float sy = (float)p.sigma_y, sz = (float)p.sigma_z;
+    K.vy = sy * sy;
+    K.vz = sz * sz;
+    K.smax = (float)p.nbr_score_max;
+    K.nsig = (float)p.nsig;
+    K.chi2_pick = (float)p.chi2_pick;
+    K.chi2_rej = (float)p.chi2_rej;
+    K.sinphi_max = (float)p.sinphi_max;
+    K.cov_reset = (float)p.cov_reset;
+    K.q_max = (float)p.q_max;
+    const float um = (float)p.u_max;
+    K.u_max2 = um * um;
+    for (int i = 0; i < 5; ++i) K.c0[i] = (float)p.c0[i];
+}
+
+tpcca_status check_params(tpcca_ctx* ctx, const tpcca_params& p) {
+    if (p.n_rows < 3 || p.n_rows > TPCCA_MAX_ROWS) return fail(ctx, TPCCA_E_ARG, "n_rows must be in [3, 255]");
+    for (int i = 1; i < p.n_rows; ++i)
+        if (!(p.row_x[i] > p.row_x[i - 1])) return fail(ctx, TPCCA_E_ARG, "row_x must be strictly increasing");
+    if (!(p.sigma_y > 0) || !(p.sigma_z > 0)) return fail(ctx, TPCCA_E_ARG, "cluster errors must be positive");
+    if (!(p.sinphi_max > 0 && p.sinphi_max < 1)) return fail(ctx, TPCCA_E_ARG, "sinphi_max must be in (0, 1)");
+    if (p.n_min < 3 || p.n_min > p.n_rows) return fail(ctx, TPCCA_E_ARG, "n_min must be in [3, n_rows]");
+    if (p.max_miss < 1) return fail(ctx, TPCCA_E_ARG, "max_miss must be >= 1");
+    if (!(p.u_max > 0 && p.u_max <= 0.5)) return fail(ctx, TPCCA_E_ARG, "u_max must be in (0, 0.5]");
+    return TPCCA_OK;
+}
+
+tpcca_status check_tuning(tpcca_ctx* ctx, const tpcca_tuning& t) {
+    auto okb = [](int v) { return v >= 64 && v <= 1024 && (v % 64) == 0; };
+    if (t.hits_per_bin < 1 || t.hits_per_bin > 64) return fail(ctx, TPCCA_E_ARG, "hits_per_bin must be in [1, 64]");
+    if (!okb(t.block_links) || !okb(t.block_tracklet) || !okb(t.block_refit) || !okb(t.block_scan))
+        return fail(ctx, TPCCA_E_ARG, "block sizes must be multiples of 64 in [64, 1024]");
+    return TPCCA_OK;
+}
+
+// Scratch layout for N clusters, nseg segments, ninst instances.
+struct Layout {
+    size_t off[64];
+    int k = 0;
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        off[k] = total;
+        total += align256(bytes ? bytes : 1);
+        return off[k++];
+    }
+};
+
+void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool really, size_t* total) {
+    const int nr = ctx->params.n_rows;
+    const int64_t cap_s = N / 3 + ninst + 1;
+    const int64_t cap_sel = N / std::max(1, ctx->params.n_min) + ninst + 1;
+    Layout L;
+    size_t o_ys = L.add(4 * N), o_zs = L.add(4 * N), o_sid = L.add(4 * N), o_pos = L.add(4 * N);
+    size_t o_bs = L.add(4 * (N + nseg + 1)), o_gny = L.add(4 * nseg), o_gnz = L.add(4 * nseg),
+           o_gm = L.add(16 * nseg);
+    size_t o_up = L.add(4 * N), o_dn = L.add(4 * N), o_upc = L.add(4 * N), o_dnc = L.add(4 * N);
+    size_t o_st = L.add(4 * cap_s), o_sti = L.add(4 * cap_s), o_so = L.add(4 * cap_s), o_sl = L.add(4 * cap_s);
+    size_t o_tn = L.add(4 * cap_s), o_tt = L.add(4 * cap_s), o_tr = L.add(4 * cap_s), o_ts = L.add(80 * cap_s);
+    size_t o_tpp = L.add(4 * cap_s * nr), o_tpr = L.add((size_t)cap_s * nr);
+    size_t o_w = L.add(4 * N);
+    size_t o_sel = L.add(4 * cap_sel), o_soff = L.add(4 * cap_sel), o_sn = L.add(4 * cap_sel);
+    size_t o_spos = L.add(4 * N), o_srow = L.add(N), o_smask = L.add(N);
+    size_t o_rs = L.add(80 * cap_sel), o_rc = L.add(4 * cap_sel), o_rn = L.add(4 * cap_sel),
+           o_rr = L.add(4 * cap_sel), o_rok = L.add(4 * cap_sel);
+    size_t o_part = L.add(8 * kScanBlocks);
+    *total = L.total;
+    if (!really) return;
+    char* base = (char*)ctx->arena.base;
+    b.ys = (float*)(base + o_ys);
+    b.zs = (float*)(base + o_zs);
+    b.sid = (int32_t*)(base + o_sid);
+    b.pos_of = (int32_t*)(base + o_pos);
+    b.bin_start = (int32_t*)(base + o_bs);
+    b.gny = (int32_t*)(base + o_gny);
+    b.gnz = (int32_t*)(base + o_gnz);
+    b.gmeta = (float4*)(base + o_gm);
+    b.up = (int32_t*)(base + o_up);
+    b.dn = (int32_t*)(base + o_dn);
+    b.upc = (int32_t*)(base + o_upc);
+    b.dnc = (int32_t*)(base + o_dnc);
+    b.cap_starts = cap_s;
+    b.starts = (int32_t*)(base + o_st);
+    b.start_inst = (int32_t*)(base + o_sti);
+    b.seed_order = (int32_t*)(base + o_so);
+    b.seed_len = (int32_t*)(base + o_sl);
+    b.tl_nhits = (int32_t*)(base + o_tn);
+    b.tl_tid = (int32_t*)(base + o_tt);
+    b.tl_row = (int32_t*)(base + o_tr);
+    b.tl_state = (float*)(base + o_ts);
+    b.tl_pick_pos = (int32_t*)(base + o_tpp);
+    b.tl_pick_row = (uint8_t*)(base + o_tpr);
+    b.weight = (uint32_t*)(base + o_w);
+    b.cap_sel = cap_sel;
+    b.sel_tl = (int32_t*)(base + o_sel);
+    b.sel_off = (int32_t*)(base + o_soff);
+    b.sel_n = (int32_t*)(base + o_sn);
+    b.sel_pos = (int32_t*)(base + o_spos);
+    b.sel_row = (uint8_t*)(base + o_srow);
+    b.sel_mask = (uint8_t*)(base + o_smask);
+    b.rf_state = (float*)(base + o_rs);
+    b.rf_chi2 = (float*)(base + o_rc);
+    b.rf_nacc = (int32_t*)(base + o_rn);
+    b.rf_row = (int32_t*)(base + o_rr);
+    b.rf_ok = (int32_t*)(base + o_rok);
+    b.scan_part = (unsigned long long*)(base + o_part);
+}
+
+tpcca_status ensure_arena(tpcca_ctx* ctx, int64_t N, int64_t nseg, int64_t ninst) {
+    Arena& A = ctx->arena;
+    if (A.base && N <= A.N && nseg <= A.nseg && ninst <= A.ninst && A.nr == ctx->params.n_rows) return TPCCA_OK;
+    const int64_t n2 = std::max(N, A.N), s2 = std::max(nseg, A.nseg), i2 = std::max(ninst, A.ninst);
+    Bufs tmp{};
+    size_t total = 0;
+    carve(ctx, tmp, n2, s2, i2, false, &total);
+    if (A.base) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(A.base));
+        A.base = nullptr;
+    }
+    if (ctx->has_graph) {
+        hipGraphExecDestroy(ctx->gexec);
+        hipGraphDestroy(ctx->graph);
+        ctx->has_graph = false;
+    }
+    ctx->has_last = false;
+    hipError_t e = hipMalloc(&A.base, total);
+    if (e != hipSuccess) {
+        A.base = nullptr;
+        A.N = A.nseg = A.ninst = -1;
+        return hip_fail(ctx, e, "scratch allocation");
+    }
+    A.bytes = total;
+    A.N = n2;
+    A.nseg = s2;
+    A.ninst = i2;
+    A.nr = ctx->params.n_rows;
+    return TPCCA_OK;
+}
+
+tpcca_status check_io(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out) {
+    if (!ctx) return TPCCA_E_ARG;
+    if (!in || !out) return fail(ctx, TPCCA_E_ARG, "null clusters or tracks");
+    if (in->n_inst < 0 || in->n_clusters < 0) return fail(ctx, TPCCA_E_ARG, "negative sizes");
+    if (in->n_clusters >= (int64_t)1 << 31) return fail(ctx, TPCCA_E_ARG, "more than 2^31-1 clusters");
+    if (in->n_inst > 0 && (!in->row_start || !in->inst_sector))
+        return fail(ctx, TPCCA_E_ARG, "null row_start or inst_sector");
+    if (in->n_clusters > 0 && (!in->y || !in->z)) return fail(ctx, TPCCA_E_ARG, "null cluster coordinates");
+    if (out->cap_tracks < 0 || out->cap_hits < 0) return fail(ctx, TPCCA_E_ARG, "negative capacities");
+    if (!out->hit_start || !out->chi2_total) return fail(ctx, TPCCA_E_ARG, "null hit_start or chi2_total");
+    if (out->cap_tracks > 0 && (!out->inst || !out->x_ref || !out->alpha || !out->param || !out->cov ||
+                                !out->chi2 || !out->ndf))
+        return fail(ctx, TPCCA_E_ARG, "null track arrays");
+    if (out->cap_hits > 0 && !out->hit_id) return fail(ctx, TPCCA_E_ARG, "null hit_id");
+    return TPCCA_OK;
+}
+
+// Read row_start to the host and check the CSR (monotone, within [0, N]).
+tpcca_status load_rowstart(tpcca_ctx* ctx, const tpcca_clusters* in, hipStream_t st) {
+    const int64_t n = (int64_t)in->n_inst * ctx->params.n_rows + 1;
+    if (in->n_inst == 0) return TPCCA_OK;
+    if ((size_t)n > ctx->h_rowstart_cap) {
+        if (ctx->h_rowstart) hipHostFree(ctx->h_rowstart);
+        ctx->h_rowstart = nullptr;
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_rowstart, n * sizeof(int64_t), hipHostMallocDefault));
+        ctx->h_rowstart_cap = n;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->h_rowstart, in->row_start, n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t* rs = ctx->h_rowstart;
+    if (rs[0] != 0) return fail(ctx, TPCCA_E_ARG, "row_start[0] must be 0");
+    for (int64_t i = 1; i < n; ++i)
+        if (rs[i] < rs[i - 1]) return fail(ctx, TPCCA_E_ARG, "row_start must be non-decreasing");
+    if (rs[n - 1] != in->n_clusters) return fail(ctx, TPCCA_E_ARG, "row_start[last] must equal n_clusters");
+    for (int64_t i = 1; i < n; ++i)
+        if (rs[i] - rs[i - 1] > TPCCA_MAX_ROW_CLUSTERS)
+            return fail(ctx, TPCCA_E_CAPACITY, "a pad row of one instance holds more than TPCCA_MAX_ROW_CLUSTERS clusters");
+    return TPCCA_OK;
+}
+
+Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out) {
+    Bufs b{};
+    size_t total;
+    carve(ctx, b, ctx->arena.N, ctx->arena.nseg, ctx->arena.ninst, true, &total);
+    b.K = ctx->dK;
+    b.ctr = ctx->dctr;
+    b.n_rows = ctx->params.n_rows;
+    b.n_inst = in->n_inst;
+    b.n_clusters = in->n_clusters;
+    b.inst_sector = in->inst_sector;
+    b.row_start = in->row_start;
+    b.y = in->y;
+    b.z = in->z;
+    b.hits_per_bin = ctx->tuning.hits_per_bin;
+    b.cap_tracks = out->cap_tracks;
+    b.cap_hits = out->cap_hits;
+    b.o_inst = out->inst;
+    b.o_xref = out->x_ref;
+    b.o_alpha = out->alpha;
+    b.o_param = out->param;
+    b.o_cov = out->cov;
+    b.o_chi2 = out->chi2;
+    b.o_ndf = out->ndf;
+    b.o_hit_start = out->hit_start;
+    b.o_hit_id = out->hit_id;
+    b.o_chi2_total = out->chi2_total;
+    return b;
+}
+
+Launch make_launch(const tpcca_tuning& t) {
+    return Launch{t.block_links, t.block_tracklet, t.block_refit, t.block_scan, t.sort_seeds};
+}
+
+// The whole pipeline for instances [i0, i1) with clusters [c0, c1).
+void enqueue_range(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, int n_min,
+                   hipStream_t st, tpcca_ctx* timing) {
+    auto mark = [&](int k) {
+        if (timing) hipEventRecord(timing->ev[k], st);
+    };
+    enqueue_weights_clear(b, c0, c1, st);
+    mark(0);
+    enqueue_grid(b, i0, i1, st);
+    mark(1);
+    enqueue_links(b, L, i0, i1, st);
+    mark(2);
+    enqueue_clean_starts(b, L, i0, i1, c0, c1, st);
+    mark(3);
+    const int64_t ninst = i1 - i0;
+    enqueue_tracklets(b, L, (c1 - c0) / 3 + ninst, st);
+    mark(4);
+    enqueue_select(b, L, 0, st);
+    mark(5);
+    enqueue_refit(b, L, (c1 - c0) / std::max(1, n_min) + ninst, st);
+    mark(6);
+    enqueue_write(b, L, 0, st);
+    mark(7);
+}
+
+tpcca_status finish_call(tpcca_ctx* ctx, const Bufs& b, tpcca_tracks* out, int64_t nseg) {
+    const Counters& c = *ctx->hctr;
+    ctx->last_ctr = c;
+    ctx->last = b;
+    ctx->last_nseg = nseg;
+    ctx->has_last = true;
+    const unsigned long long tot = c.slot[SL_TRK][0];
+    out->n_tracks = (int64_t)(tot >> 32);
+    out->n_hits = (int64_t)(tot & 0xFFFFFFFFull);
+    if (c.err & ERR_ARG) return fail(ctx, TPCCA_E_ARG, "non-finite cluster coordinate or malformed row ranges");
+    if (c.err & ERR_ROW_CAP)
+        return fail(ctx, TPCCA_E_CAPACITY, "a pad row of one instance holds more than TPCCA_MAX_ROW_CLUSTERS clusters");
+    if (c.err & ERR_TID_CAP)
+        return fail(ctx, TPCCA_E_CAPACITY, "an instance has more than TPCCA_MAX_STARTS_PER_INST tracklets");
+    if (c.err & ERR_SCRATCH) return fail(ctx, TPCCA_E_INTERNAL, "internal scratch bound exceeded");
+    if ((c.err & ERR_OUT_CAP) || out->n_tracks > out->cap_tracks || out->n_hits > out->cap_hits)
+        return fail(ctx, TPCCA_E_CAPACITY, "output capacity too small (n_tracks / n_hits hold the required sizes)");
+    ctx->err.clear();
+    return TPCCA_OK;
+}
+
+tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* stream, bool batched) {
+    tpcca_status s = check_io(ctx, in, out);
+    if (s != TPCCA_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int nr = ctx->params.n_rows;
+    const int64_t N = in->n_clusters, nseg = (int64_t)in->n_inst * nr;
+    s = load_rowstart(ctx, in, st);
+    if (s != TPCCA_OK) return s;
+    s = ensure_arena(ctx, std::max<int64_t>(N, 1), std::max<int64_t>(nseg, 1), std::max<int64_t>(in->n_inst, 1));
+    if (s != TPCCA_OK) return s;
+    const Bufs b = make_bufs(ctx, in, out);
+    const Launch L = make_launch(ctx->tuning);
+    const bool timing = (ctx->params.flags & TPCCA_FLAG_STATS) != 0;
+    if (timing && !ctx->events) {
+        for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+        ctx->events = true;
+    }
+    if (!batched) {
+        enqueue_reset(b, st);
+        const int64_t* rs = ctx->h_rowstart;
+        for (int i = 0; i < in->n_inst; ++i)
+            enqueue_range(b, L, i, i + 1, rs[(int64_t)i * nr], rs[(int64_t)(i + 1) * nr], ctx->params.n_min, st,
+                          nullptr);
+        enqueue_finish(b, st);
+        HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));
+        return finish_call(ctx, b, out, nseg);
+    }
+    if (timing) {  // uncaptured, with stage events
+        enqueue_reset(b, st);
+        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, st, ctx);
+        enqueue_finish(b, st);
+        hipEventRecord(ctx->ev[8], st);
+        HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int k = 0; k < 8; ++k) hipEventElapsedTime(&ctx->stage_ms[k], ctx->ev[k], ctx->ev[k + 1]);
+        return finish_call(ctx, b, out, nseg);
+    }
+    if (st == nullptr) {  // the legacy null stream cannot be captured: use the context's blocking stream
+        if (!ctx->own_stream) HIP_TRY(hipStreamCreate(&ctx->own_stream));
+        st = ctx->own_stream;
+    }
+    GraphKey key{};
+    const void* ps[12] = {in->inst_sector, in->row_start, in->y, in->z, out->inst, out->param,
+                          out->cov, out->hit_start, out->hit_id, out->chi2_total, ctx->arena.base, (void*)st};
+    std::memcpy(key.p, ps, sizeof(ps));
+    const int64_t vs[8] = {in->n_inst, N, out->cap_tracks, out->cap_hits, ctx->tuning.hits_per_bin,
+                           ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
+                           ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
+                           (int64_t)(intptr_t)out->x_ref ^ (int64_t)(intptr_t)out->chi2};
+    std::memcpy(key.v, vs, sizeof(vs));
+    if (!ctx->has_graph || !(ctx->gkey == key)) {
+        if (ctx->has_graph) {
+            hipGraphExecDestroy(ctx->gexec);
+            hipGraphDestroy(ctx->graph);
+            ctx->has_graph = false;
+        }
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        enqueue_reset(b, st);
+        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, st, nullptr);
+        enqueue_finish(b, st);
+        hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
+        hipError_t e = hipStreamEndCapture(st, &ctx->graph);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(ctx->graph);
+            return hip_fail(ctx, e, "hipGraphInstantiate");
+        }
+        ctx->has_graph = true;
+        ctx->gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->gexec, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return finish_call(ctx, b, out, nseg);
+}
+
+}  // namespace
+
+extern "C" {
+
+tpcca_status tpcca_default_params(tpcca_params* p) {
+    if (!p) return TPCCA_E_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->n_rows = 152;
+    for (int i = 0; i < p->n_rows; ++i) p->row_x[i] = (float)(85.0 + i * 162.0 / 151.0);
+    p->bz = 0.5;
+    p->sigma_y = p->sigma_z = 0.1;
+    p->win_ty = 2.0;
+    p->win_tz = 1.1;
+    p->win_ny = p->win_nz = 0.5;
+    p->nbr_score_max = 0.24;
+    p->nsig = 3.0;
+    p->chi2_pick = 16.0;
+    p->chi2_rej = 25.0;
+    p->sinphi_max = 0.95;
+    p->cov_reset = 100.0;
+    p->q_max = 20.0;
+    p->u_max = 0.25;
+    p->c0[0] = 1.0;
+    p->c0[1] = 1.0;
+    p->c0[2] = 0.25;
+    p->c0[3] = 0.25;
+    p->c0[4] = 400.0;
+    p->n_min = 10;
+    p->max_miss = 8;
+    p->flags = 0;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
+    if (!t) return TPCCA_E_ARG;
+    t->hits_per_bin = 2;
+    t->block_links = 256;
+    t->block_tracklet = 128;
+    t->block_refit = 128;
+    t->block_scan = 256;
+    t->sort_seeds = 0;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_create(const tpcca_params* params, const tpcca_tuning* tuning, int device, tpcca_ctx** out) {
+    if (!params || !out) return TPCCA_E_ARG;
+    *out = nullptr;
+    tpcca_ctx* ctx = new tpcca_ctx;
+    ctx->params = *params;
+    if (tuning) ctx->tuning = *tuning;
+    else tpcca_default_tuning(&ctx->tuning);
+    tpcca_status s = check_params(ctx, ctx->params);
+    if (s == TPCCA_OK) s = check_tuning(ctx, ctx->tuning);
+    if (s != TPCCA_OK) {
+        fprintf(stderr, "tpcca_create: %s\n", ctx->err.c_str());
+        delete ctx;
+        return s;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        delete ctx;
+        return TPCCA_E_DEVICE;
+    }
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return TPCCA_E_DEVICE;
+    }
+    build_consts(ctx->params, ctx->hK);
+    if (hipMalloc((void**)&ctx->dK, sizeof(DevConsts)) != hipSuccess ||
+        hipMalloc((void**)&ctx->dctr, sizeof(Counters)) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->hctr, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        tpcca_destroy(ctx);
+        return TPCCA_E_OOM;
+    }
+    if (hipMemcpy(ctx->dK, &ctx->hK, sizeof(DevConsts), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(ctx->dctr, 0, sizeof(Counters)) != hipSuccess) {
+        tpcca_destroy(ctx);
+        return TPCCA_E_DEVICE;
+    }
+    std::memset(ctx->hctr, 0, sizeof(Counters));
+    *out = ctx;
+    return TPCCA_OK;
+}
+
+void tpcca_destroy(tpcca_ctx* ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    if (ctx->has_graph) {
+        hipGraphExecDestroy(ctx->gexec);
+        hipGraphDestroy(ctx->graph);
+    }
+    if (ctx->events)
+        for (auto& e : ctx->ev) hipEventDestroy(e);
+    if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+    if (ctx->arena.base) hipFree(ctx->arena.base);
+    if (ctx->dK) hipFree(ctx->dK);
+    if (ctx->dctr) hipFree(ctx->dctr);
+    if (ctx->hctr) hipHostFree(ctx->hctr);
+    if (ctx->h_rowstart) hipHostFree(ctx->h_rowstart);
+    delete ctx;
+}
+
+const char* tpcca_last_error(const tpcca_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+tpcca_status tpcca_set_tuning(tpcca_ctx* ctx, const tpcca_tuning* t) {
+    if (!ctx || !t) return TPCCA_E_ARG;
+    tpcca_status s = check_tuning(ctx, *t);
+    if (s != TPCCA_OK) return s;
+    ctx->tuning = *t;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_tuning(const tpcca_ctx* ctx, tpcca_tuning* out) {
+    if (!ctx || !out) return TPCCA_E_ARG;
+    *out = ctx->tuning;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_track(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    return run(ctx, in, out, hip_stream, false);
+}
+
+tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    return run(ctx, in, out, hip_stream, true);
+}
+
+tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_t repeats, tpcca_tuning* out,
+                            void* hip_stream) {
+    if (!ctx || !sample || !out) return TPCCA_E_ARG;
+    if (repeats < 1) repeats = 1;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t N = sample->n_clusters;
+    const int64_t cap_t = N / std::max(1, ctx->params.n_min) + sample->n_inst + 1;
+    // internal output buffers
+    size_t bytes = 0;
+    Layout L;
+    size_t o_inst = L.add(4 * cap_t), o_x = L.add(4 * cap_t), o_a = L.add(4 * cap_t), o_p = L.add(20 * cap_t),
+           o_c = L.add(60 * cap_t), o_chi = L.add(4 * cap_t), o_ndf = L.add(4 * cap_t),
+           o_hs = L.add(8 * (cap_t + 1)), o_hid = L.add(4 * std::max<int64_t>(N, 1)), o_tot = L.add(16);
+    bytes = L.total;
+    char* mem = nullptr;
+    HIP_TRY(hipMalloc((void**)&mem, bytes));
+    tpcca_tracks tr{};
+    tr.cap_tracks = cap_t;
+    tr.cap_hits = std::max<int64_t>(N, 1);
+    tr.inst = (int32_t*)(mem + o_inst);
+    tr.x_ref = (float*)(mem + o_x);
+    tr.alpha = (float*)(mem + o_a);
+    tr.param = (float*)(mem + o_p);
+    tr.cov = (float*)(mem + o_c);
+    tr.chi2 = (float*)(mem + o_chi);
+    tr.ndf = (int32_t*)(mem + o_ndf);
+    tr.hit_start = (int64_t*)(mem + o_hs);
+    tr.hit_id = (int32_t*)(mem + o_hid);
+    tr.chi2_total = (double*)(mem + o_tot);
+    const uint32_t saved_flags = ctx->params.flags;
+    if (saved_flags & TPCCA_FLAG_STATS) {  // time the captured form
+        ctx->params.flags &= ~TPCCA_FLAG_STATS;
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    tpcca_tuning best = ctx->tuning;
+    auto time_it = [&](const tpcca_tuning& t, float* ms_out) -> tpcca_status {
+        tpcca_status s = tpcca_set_tuning(ctx, &t);
+        if (s != TPCCA_OK) return s;
+        s = run(ctx, sample, &tr, hip_stream, true);  // warm-up and capture
+        if (s != TPCCA_OK) return s;
+        std::vector<float> ms;
+        for (int r = 0; r < repeats; ++r) {
+            hipEventRecord(e0, st);
+            s = run(ctx, sample, &tr, hip_stream, true);
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            if (s != TPCCA_OK) return s;
+            float m = 0;
+            hipEventElapsedTime(&m, e0, e1);
+            ms.push_back(m);
+        }
+        std::sort(ms.begin(), ms.end());
+        *ms_out = ms[ms.size() / 2];
+        return TPCCA_OK;
+    };
+    float best_ms = 0;
+    tpcca_status s = time_it(best, &best_ms);
+    const int hpb[] = {1, 2, 3, 4, 6, 8};
+    const int blk[] = {64, 128, 256};
+    for (int dim = 0; dim < 4 && s == TPCCA_OK; ++dim) {
+        const int* vals = dim == 0 ? hpb : blk;
+        const int nv = dim == 0 ? 6 : 3;
+        for (int k = 0; k < nv && s == TPCCA_OK; ++k) {
+            tpcca_tuning t = best;
+            int* field = dim == 0 ? &t.hits_per_bin : dim == 1 ? &t.block_tracklet : dim == 2 ? &t.block_refit
+                                                                                        : &t.block_links;
+            if (*field == vals[k]) continue;
+            *field = vals[k];
+            float m = 0;
+            s = time_it(t, &m);
+            if (s == TPCCA_OK && m < best_ms) {
+                best_ms = m;
+                best = t;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->params.flags = saved_flags;
+    tpcca_set_tuning(ctx, &best);
+    *out = best;
+    ctx->has_last = false;  // internal buffers are about to go away
+    hipStreamSynchronize(st);
+    hipFree(mem);
+    if (ctx->has_graph) {  // graph refers to the freed buffers
+        hipGraphExecDestroy(ctx->gexec);
+        hipGraphDestroy(ctx->graph);
+        ctx->has_graph = false;
+    }
+    return s;
+}
+
+tpcca_status tpcca_export_sizes(tpcca_ctx* ctx, int64_t* sizes, void* hip_stream) {
+    (void)hip_stream;
+    if (!ctx || !sizes) return TPCCA_E_ARG;
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "no tracking result to export");
+    const Counters& c = ctx->last_ctr;
+    sizes[0] = ctx->last.n_clusters;
+    sizes[1] = ctx->last_nseg;
+    sizes[2] = (int64_t)(c.slot[SL_START][0] & 0xFFFFFFFFull);
+    sizes[3] = (int64_t)(c.slot[SL_SEL][0] >> 32);
+    sizes[4] = (int64_t)(c.slot[SL_SEL][0] & 0xFFFFFFFFull);
+    sizes[5] = (int64_t)(c.slot[SL_TRK][0] >> 32);
+    sizes[6] = (int64_t)(c.slot[SL_TRK][0] & 0xFFFFFFFFull);
+    sizes[7] = ctx->params.n_rows;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_export_grid(tpcca_ctx* ctx, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz,
+                               float* meta, void* hip_stream) {
+    if (!ctx || !sorted_id || !bin_start || !ny || !nz || !meta) return TPCCA_E_ARG;
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "no tracking result to export");
+    enqueue_export_grid(ctx->last, sorted_id, bin_start, ny, nz, meta, ctx->last_nseg, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_export_links(tpcca_ctx* ctx, int32_t* up, int32_t* dn, int32_t* up_clean, int32_t* dn_clean,
+                                void* hip_stream) {
+    if (!ctx || !up || !dn || !up_clean || !dn_clean) return TPCCA_E_ARG;
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "no tracking result to export");
+    enqueue_export_links(ctx->last, up, dn, up_clean, dn_clean, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_export_tracklets(tpcca_ctx* ctx, int32_t* start_hit, int32_t* start_inst, int32_t* start_tid,
+                                    int32_t* nhits, int32_t* rowhit, float* state, int32_t* state_row,
+                                    uint32_t* weight, void* hip_stream) {
+    if (!ctx || !weight) return TPCCA_E_ARG;
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "no tracking result to export");
+    const int64_t ns = (int64_t)(ctx->last_ctr.slot[SL_START][0] & 0xFFFFFFFFull);
+    if (ns > 0 && (!start_hit || !start_inst || !start_tid || !nhits || !rowhit || !state || !state_row))
+        return TPCCA_E_ARG;
+    enqueue_export_tracklets(ctx->last, ns, start_hit, start_inst, start_tid, nhits, rowhit, state, state_row, weight,
+                             (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_export_selected(tpcca_ctx* ctx, int32_t* sel_tl, int64_t* hit_start, int32_t* hit_id,
+                                   uint8_t* mask, int32_t* status, void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "no tracking result to export");
+    const int64_t nsel = (int64_t)(ctx->last_ctr.slot[SL_SEL][0] >> 32);
+    if (nsel > 0 && (!sel_tl || !hit_start || !hit_id || !mask || !status)) return TPCCA_E_ARG;
+    enqueue_export_selected(ctx->last, nsel, sel_tl, hit_start, hit_id, mask, status, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_stats(tpcca_ctx* ctx, tpcca_stats* o) {
+    if (!ctx || !o) return TPCCA_E_ARG;
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "no tracking result");
+    const Counters& c = ctx->last_ctr;
+    std::memset(o, 0, sizeof(*o));
+    o->n_clusters = ctx->last.n_clusters;
+    o->n_segments = ctx->last_nseg;
+    o->n_links = (int64_t)c.stats[ST_LINKS];
+    o->n_starts = (int64_t)(c.slot[SL_START][0] & 0xFFFFFFFFull);
+    o->n_chain_hits = (int64_t)c.stats[ST_CHAIN_HITS];
+    o->tl_rows_visited = (int64_t)c.stats[ST_TL_ROWS];
+    o->tl_candidates = (int64_t)c.stats[ST_TL_CAND];
+    o->tl_picks = (int64_t)c.stats[ST_TL_PICKS];
+    o->n_selected = (int64_t)(c.slot[SL_SEL][0] >> 32);
+    o->n_selected_hits = (int64_t)(c.slot[SL_SEL][0] & 0xFFFFFFFFull);
+    o->n_tracks = (int64_t)(c.slot[SL_TRK][0] >> 32);
+    o->n_track_hits = (int64_t)(c.slot[SL_TRK][0] & 0xFFFFFFFFull);
+    o->rf_rows_visited = (int64_t)c.stats[ST_RF_ROWS];
+    o->rf_hit_visits = (int64_t)c.stats[ST_RF_HITS];
+    o->nb_candidates_u = (int64_t)c.stats[ST_NB_CAND_U];
+    o->nb_pairs = (int64_t)c.stats[ST_NB_PAIRS];
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_get_stage_times(tpcca_ctx* ctx, float* ms8) {
+    if (!ctx || !ms8) return TPCCA_E_ARG;
+    for (int k = 0; k < 8; ++k) ms8[k] = ctx->stage_ms[k];
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div, float* out_sqrt, int64_t n,
+                                  void* hip_stream) {
+    if (n < 0 || (n > 0 && (!a || !b || !out_div || !out_sqrt))) return TPCCA_E_ARG;
+    enqueue_fp32_selfcheck(a, b, out_div, out_sqrt, n, (hipStream_t)hip_stream);
+    if (hipGetLastError() != hipSuccess) return TPCCA_E_DEVICE;
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return TPCCA_E_DEVICE;
+    return TPCCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Internal interface between the host runtime (api.hip) and the kernels
+// (kernels.hip). Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kf_device.h"
+
+namespace tpcca {
+
+// error bits raised by kernels
+enum : uint32_t {
+    ERR_ARG = 1u,        // malformed CSR / non-finite coordinate
+    ERR_ROW_CAP = 2u,    // more than TPCCA_MAX_ROW_CLUSTERS on one row of one instance
+    ERR_TID_CAP = 4u,    // more than 2^20 tracklets in one instance
+    ERR_OUT_CAP = 8u,    // output capacity exceeded
+    ERR_SCRATCH = 16u,   // internal scratch bound violated (should not happen)
+};
+
+// statistics slots
+enum {
+    ST_LINKS = 0, ST_NB_CAND_U, ST_NB_PAIRS, ST_CHAIN_HITS, ST_TL_ROWS, ST_TL_CAND, ST_TL_PICKS,
+    ST_RF_ROWS, ST_RF_HITS, ST_COUNT
+};
+
+// Running totals of the three compactions (starts, selected, tracks); each
+// slot holds {running total, base of the current range, count of the current
+// range} as packed (hi 32: items, lo 32: sub-items) 64-bit sums.
+enum { SL_START = 0, SL_SEL = 1, SL_TRK = 2 };
+struct Counters {
+    unsigned long long slot[3][3];
+    unsigned int err;
+    unsigned int pad;
+    unsigned long long stats[ST_COUNT];
+};
+
+// All device buffers of one call (scratch + caller arrays).
+struct Bufs {
+    const DevConsts* K;
+    Counters* ctr;
+    int n_rows;  // host copy of K->n_rows
+    // input
+    int32_t n_inst;
+    int64_t n_clusters;
+    const int32_t* inst_sector;
+    const int64_t* row_start;
+    const float* y;
+    const float* z;
+    // grid
+    float* ys;
+    float* zs;
+    int32_t* sid;      // cluster id at grid position
+    int32_t* pos_of;   // grid position of cluster id
+    int32_t* bin_start;
+    int32_t* gny;
+    int32_t* gnz;
+    float4* gmeta;     // ymin, zmin, inv_y, inv_z
+    int hits_per_bin;
+    // CA (grid-position space)
+    int32_t* up;
+    int32_t* dn;
+    int32_t* upc;
+    int32_t* dnc;
+    // starts and tracklets
+    int64_t cap_starts;
+    int32_t* starts;     // grid position of the start hit
+    int32_t* start_inst;
+    int32_t* seed_order; // processing order of tracklets (permutation of the start range)
+    int32_t* seed_len;   // chain length per start (for the order)
+    int32_t* tl_nhits;
+    int32_t* tl_tid;
+    int32_t* tl_row;
+    float* tl_state;     // [cap_starts * 20]
+    int32_t* tl_pick_pos;  // [cap_starts * n_rows], stage-3 order (rows descending)
+    uint8_t* tl_pick_row;
+    uint32_t* weight;    // [N] grid-position space
+    // selection
+    int64_t cap_sel;
+    int32_t* sel_tl;
+    int32_t* sel_off;
+    int32_t* sel_n;
+    int32_t* sel_pos;    // [N]
+    uint8_t* sel_row;    // [N]
+    uint8_t* sel_mask;   // [N]
+    // refit results per selected
+    float* rf_state;     // [cap_sel * 20]
+    float* rf_chi2;
+    int32_t* rf_nacc;
+    int32_t* rf_row;
+    int32_t* rf_ok;
+    // scan scratch
+    unsigned long long* scan_part;  // [kScanBlocks]
+    // outputs
+    int64_t cap_tracks, cap_hits;
+    int32_t* o_inst;
+    float* o_xref;
+    float* o_alpha;
+    float* o_param;
+    float* o_cov;
+    float* o_chi2;
+    int32_t* o_ndf;
+    int64_t* o_hit_start;
+    int32_t* o_hit_id;
+    double* o_chi2_total;
+};
+
+struct Launch {
+    int block_links, block_tracklet, block_refit, block_scan, sort_seeds;
+};
+
+constexpr int kScanBlocks = 1024;
+
+// Instance range [i0, i1) with its cluster range [c0, c1) (host values).
+void enqueue_reset(const Bufs& b, hipStream_t st);
+void enqueue_weights_clear(const Bufs& b, int64_t c0, int64_t c1, hipStream_t st);
+void enqueue_grid(const Bufs& b, int i0, int i1, hipStream_t st);
+void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, hipStream_t st);
+void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, hipStream_t st);
+void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);
+void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);
+void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);
+void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);
+void enqueue_finish(const Bufs& b, hipStream_t st);
+
+// exports (cluster-id space)
+void enqueue_export_grid(const Bufs& b, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz,
+                         float* meta, int64_t nseg, hipStream_t st);
+void enqueue_export_links(const Bufs& b, int32_t* up, int32_t* dn, int32_t* upc, int32_t* dnc, hipStream_t st);
+void enqueue_export_tracklets(const Bufs& b, int64_t n_starts, int32_t* start_hit, int32_t* start_inst,
+                              int32_t* start_tid, int32_t* nhits, int32_t* rowhit, float* state,
+                              int32_t* state_row, uint32_t* weight, hipStream_t st);
+void enqueue_export_selected(const Bufs& b, int64_t n_sel, int32_t* sel_tl, int64_t* hit_start, int32_t* hit_id,
+                             uint8_t* mask, int32_t* status, hipStream_t st);
+void enqueue_fp32_selfcheck(const float* a, const float* bb, float* od, float* os, int64_t n, hipStream_t st);
+
+}  // namespace tpcca

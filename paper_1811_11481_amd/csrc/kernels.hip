@@ -1,0 +1,1012 @@
+// HIP kernels (gfx950, wave64) of the TPC sector tracker.
+//
+// Stages (Section 2 of arXiv:1811.11481, with the resolution changes of
+// Section 3): per-row hit grid, cellular-automaton neighbour links, mutual
+// link cleaning and start hits, Kalman tracklets (seed fit, outward
+// following, inward re-pick through the seed), ownership selection, the
+// three-pass refit with chi2 rejection, compaction into the caller's track
+// arrays and FP64 totals.
+//
+// Work mapping: one workgroup per (instance, row) for the grid and the links
+// (the paper parallelises the cellular automaton over hits), one lane per
+// tracklet and one lane per track for the Kalman stages (parallel over
+// tracks). Compactions are deterministic three-phase scans. No result depends
+// on the grid bin size, the launch shape or thread order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+#include "kf_device.h"
+
+#pragma clang fp contract(off)
+
+namespace tpcca {
+
+namespace {
+
+constexpr float kBinMargin = 0.01f;  // cm: bin ranges of window queries are widened by this
+constexpr int kSmallRow = 4096;
+constexpr int kLargeRow = 16384;      // TPCCA_MAX_ROW_CLUSTERS
+constexpr int kKeyShift = 14;         // key = bin << 14 | local index (both < 16384)
+
+__device__ __forceinline__ void raise_err(Counters* c, unsigned int bit) { atomicOr(&c->err, bit); }
+
+__device__ __forceinline__ void stat_add(Counters* c, int slot, unsigned long long v) {
+    // wave-aggregated add
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&c->stats[slot], v);
+}
+
+// Bin index of coordinate v: trunc((v - vmin) * inv) clamped to [0, nb - 1]
+// (a NaN maps to bin 0, so a malformed input never indexes out of range).
+__device__ __forceinline__ int bin_of(float v, float vmin, float inv, int nb) {
+    const float t = (v - vmin) * inv;
+    if (!(t > 0.0f)) return 0;
+    if (t >= (float)(nb - 1)) return nb - 1;
+    return (int)t;
+}
+
+// Row of a grid position / cluster id inside instance `inst` (binary search).
+__device__ __forceinline__ int row_of(const int64_t* row_start, int64_t seg0, int nr, int64_t pos) {
+    int lo = 0, hi = nr;  // find last r with row_start[seg0 + r] <= pos
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (row_start[seg0 + mid] <= pos) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct GridView {
+    int64_t rs;        // first grid position of the segment
+    const int32_t* bs; // bin starts (relative positions)
+    int ny, nz, n;
+    float ymin, zmin, iy, iz;
+};
+
+__device__ __forceinline__ GridView grid_view(const Bufs& b, int64_t seg) {
+    GridView g;
+    g.rs = b.row_start[seg];
+    g.n = (int)(b.row_start[seg + 1] - g.rs);
+    g.bs = b.bin_start + g.rs + seg;
+    g.ny = b.gny[seg];
+    g.nz = b.gnz[seg];
+    const float4 m = b.gmeta[seg];
+    g.ymin = m.x;
+    g.zmin = m.y;
+    g.iy = m.z;
+    g.iz = m.w;
+    return g;
+}
+
+// ------------------------------------------------------------------ grid
+// One workgroup per (instance, row): exact ranges, bin layout, stable sort of
+// (bin, cluster index) keys by a bitonic network in LDS, gather of the sorted
+// coordinates, bin starts.
+template <int MAXN>
+__global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
+    __shared__ uint32_t key[MAXN];
+    __shared__ float red[4][4];
+    __shared__ int sh_i[4];
+    __shared__ float sh_f[4];
+    const int64_t seg = seg0 + blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    int64_t a = b.row_start[seg], e = b.row_start[seg + 1];
+    bool bad = (a < 0) || (e < a) || (e > b.n_clusters);
+    int64_t n64 = bad ? 0 : e - a;
+    if (MAXN == kSmallRow) {
+        if (n64 > kSmallRow) return;  // handled by the large variant
+    } else {
+        if (n64 <= kSmallRow) return;
+        if (n64 > kLargeRow) {
+            if (tid == 0) raise_err(b.ctr, ERR_ROW_CAP);
+            return;
+        }
+    }
+    if (bad && tid == 0) raise_err(b.ctr, ERR_ARG);
+    const int n = (int)n64;
+    const int nr = b.K->n_rows;
+    // ranges
+    float ymn = __builtin_inff(), ymx = -__builtin_inff(), zmn = __builtin_inff(), zmx = -__builtin_inff();
+    bool nonfinite = false;
+    for (int i = tid; i < n; i += nt) {
+        const float yv = b.y[a + i], zv = b.z[a + i];
+        nonfinite |= !(__builtin_fabsf(yv) <= 3.0e38f) || !(__builtin_fabsf(zv) <= 3.0e38f);
+        ymn = fminf(ymn, yv); ymx = fmaxf(ymx, yv);
+        zmn = fminf(zmn, zv); zmx = fmaxf(zmx, zv);
+    }
+    if (nonfinite) raise_err(b.ctr, ERR_ARG);
+    for (int o = 32; o > 0; o >>= 1) {
+        ymn = fminf(ymn, __shfl_xor(ymn, o, 64)); ymx = fmaxf(ymx, __shfl_xor(ymx, o, 64));
+        zmn = fminf(zmn, __shfl_xor(zmn, o, 64)); zmx = fmaxf(zmx, __shfl_xor(zmx, o, 64));
+    }
+    const int wid = tid >> 6;
+    if ((tid & 63) == 0) {
+        red[wid][0] = ymn; red[wid][1] = ymx; red[wid][2] = zmn; red[wid][3] = zmx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < (nt >> 6); ++w) {
+            ymn = fminf(ymn, red[w][0]); ymx = fmaxf(ymx, red[w][1]);
+            zmn = fminf(zmn, red[w][2]); zmx = fmaxf(zmx, red[w][3]);
+        }
+        int ny = 1, nz = 1;
+        float iy = 0.0f, iz = 0.0f;
+        if (n == 0) {
+            ymn = zmn = 0.0f;
+        } else {
+            const float ly = ymx - ymn, lz = zmx - zmn;
+            const int tb = max(1, n / b.hits_per_bin);
+            if (ly > 0.0f && lz > 0.0f) {
+                const float f = __builtin_sqrtf((float)tb * (ly / lz));
+                ny = (f >= (float)tb) ? tb : max(1, (int)f);
+            } else if (ly > 0.0f) {
+                ny = tb;
+            } else {
+                ny = 1;
+            }
+            nz = max(1, tb / ny);
+            iy = ly > 0.0f ? (float)ny / ly : 0.0f;
+            iz = lz > 0.0f ? (float)nz / lz : 0.0f;
+        }
+        b.gny[seg] = ny;
+        b.gnz[seg] = nz;
+        b.gmeta[seg] = make_float4(ymn, zmn, iy, iz);
+        sh_i[0] = ny; sh_i[1] = nz;
+        sh_f[0] = ymn; sh_f[1] = zmn; sh_f[2] = iy; sh_f[3] = iz;
+    }
+    __syncthreads();
+    const int ny = sh_i[0], nz = sh_i[1];
+    const float ymin = sh_f[0], zmin = sh_f[1], iy = sh_f[2], iz = sh_f[3];
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = tid; i < P; i += nt) {
+        if (i < n) {
+            const int by = bin_of(b.y[a + i], ymin, iy, ny);
+            const int bz = bin_of(b.z[a + i], zmin, iz, nz);
+            key[i] = ((uint32_t)(bz * ny + by) << kKeyShift) | (uint32_t)i;
+        } else {
+            key[i] = 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += nt) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint32_t x = key[i], w = key[ixj];
+                    const bool asc = (i & k) == 0;
+                    if ((x > w) == asc) {
+                        key[i] = w;
+                        key[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int32_t* bs = b.bin_start + a + seg;
+    const int nb = ny * nz;
+    for (int p = tid; p < n; p += nt) {
+        const uint32_t kk = key[p];
+        const int i = (int)(kk & ((1u << kKeyShift) - 1));
+        const int bin = (int)(kk >> kKeyShift);
+        b.ys[a + p] = b.y[a + i];
+        b.zs[a + p] = b.z[a + i];
+        b.sid[a + p] = (int32_t)(a + i);
+        b.pos_of[a + i] = (int32_t)(a + p);
+        const int prev = (p == 0) ? -1 : (int)(key[p - 1] >> kKeyShift);
+        for (int q = prev + 1; q <= bin; ++q) bs[q] = p;
+    }
+    if (tid == 0) {
+        const int last = (n == 0) ? -1 : (int)(key[n - 1] >> kKeyShift);
+        for (int q = last + 1; q <= nb; ++q) bs[q] = n;
+    }
+    (void)nr;
+}
+
+// ------------------------------------------------------------------ links
+// One workgroup per (instance, row); one lane per hit of the row. Candidate
+// pairs (u on row+1, d on row-1) inside the windows; the minimum straight-line
+// deviation score wins, ties to the smaller (id_u, id_d).
+__global__ void k_links(Bufs b, int64_t seg0) {
+    const DevConsts& K = *b.K;
+    const int nr = K.n_rows;
+    const int64_t seg = seg0 + blockIdx.x;
+    const int r = (int)(seg % nr);
+    const int64_t a = b.row_start[seg], e = b.row_start[seg + 1];
+    if (r == 0 || r == nr - 1) {
+        for (int64_t p = a + threadIdx.x; p < e; p += blockDim.x) {
+            b.up[p] = -1;
+            b.dn[p] = -1;
+        }
+        return;
+    }
+    const GridView gu = grid_view(b, seg + 1);
+    const GridView gd = grid_view(b, seg - 1);
+    const float wyu = K.wyu[r], wzu = K.wzu[r], wyd = K.wyd[r], wzd = K.wzd[r], tr = K.tr[r], smax = K.smax;
+    unsigned long long n_links = 0, n_cu = 0, n_pairs = 0;
+    for (int64_t p = a + threadIdx.x; p < e; p += blockDim.x) {
+        const float yh = b.ys[p], zh = b.zs[p];
+        bool found = false;
+        float best = 0.0f;
+        int32_t bu = -1, bd = -1, bu_id = 0, bd_id = 0;
+        if (gu.n > 0 && gd.n > 0) {
+            const int uy0 = bin_of((yh - wyu) - kBinMargin, gu.ymin, gu.iy, gu.ny);
+            const int uy1 = bin_of((yh + wyu) + kBinMargin, gu.ymin, gu.iy, gu.ny);
+            const int uz0 = bin_of((zh - wzu) - kBinMargin, gu.zmin, gu.iz, gu.nz);
+            const int uz1 = bin_of((zh + wzu) + kBinMargin, gu.zmin, gu.iz, gu.nz);
+            const int dy0 = bin_of((yh - wyd) - kBinMargin, gd.ymin, gd.iy, gd.ny);
+            const int dy1 = bin_of((yh + wyd) + kBinMargin, gd.ymin, gd.iy, gd.ny);
+            const int dz0 = bin_of((zh - wzd) - kBinMargin, gd.zmin, gd.iz, gd.nz);
+            const int dz1 = bin_of((zh + wzd) + kBinMargin, gd.zmin, gd.iz, gd.nz);
+            for (int uz = uz0; uz <= uz1; ++uz) {
+                const int q0 = gu.bs[uz * gu.ny + uy0], q1 = gu.bs[uz * gu.ny + uy1 + 1];
+                for (int q = q0; q < q1; ++q) {
+                    const int64_t u = gu.rs + q;
+                    const float yu = b.ys[u], zu = b.zs[u];
+                    if (!(__builtin_fabsf(yu - yh) <= wyu && __builtin_fabsf(zu - zh) <= wzu)) continue;
+                    ++n_cu;
+                    int32_t uid = -1;
+                    for (int dz = dz0; dz <= dz1; ++dz) {
+                        const int t0 = gd.bs[dz * gd.ny + dy0], t1 = gd.bs[dz * gd.ny + dy1 + 1];
+                        for (int t = t0; t < t1; ++t) {
+                            const int64_t d = gd.rs + t;
+                            const float yd = b.ys[d], zd = b.zs[d];
+                            if (!(__builtin_fabsf(yd - yh) <= wyd && __builtin_fabsf(zd - zh) <= wzd)) continue;
+                            ++n_pairs;
+                            const float ey = (yd + (yu - yd) * tr) - yh;
+                            const float ez = (zd + (zu - zd) * tr) - zh;
+                            const float sc = ey * ey + ez * ez;
+                            if (!(sc <= smax)) continue;
+                            if (uid < 0) uid = b.sid[u];
+                            const int32_t did = b.sid[d];
+                            if (!found || sc < best ||
+                                (sc == best && (uid < bu_id || (uid == bu_id && did < bd_id)))) {
+                                found = true;
+                                best = sc;
+                                bu = (int32_t)u;
+                                bd = (int32_t)d;
+                                bu_id = uid;
+                                bd_id = did;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        b.up[p] = bu;
+        b.dn[p] = bd;
+        n_links += found ? 1 : 0;
+    }
+    if (K.stats) {
+        stat_add(b.ctr, ST_LINKS, n_links);
+        stat_add(b.ctr, ST_NB_CAND_U, n_cu);
+        stat_add(b.ctr, ST_NB_PAIRS, n_pairs);
+    }
+}
+
+// ------------------------------------------------------------------ clean
+__global__ void k_clean(Bufs b, int64_t c0, int64_t c1) {
+    for (int64_t p = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < c1;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = b.up[p], d = b.dn[p];
+        b.upc[p] = (u >= 0 && b.dn[u] == p) ? u : -1;
+        b.dnc[p] = (d >= 0 && b.up[d] == p) ? d : -1;
+    }
+}
+
+// ------------------------------------------------------------------ scans
+// Deterministic three-phase exclusive scan over [begin, end) of 64-bit packed
+// values (hi 32 bits: items, lo 32 bits: sub-items), split into kScanBlocks
+// contiguous chunks. Phase 3 hands each element its exclusive prefix
+// (including the running total of earlier ranges) to Op::write.
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long* sh,
+                                                              unsigned long long* total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    unsigned long long incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) sh[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        for (int w = 0; w < nw; ++w) {
+            const unsigned long long t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[16] = run;
+    }
+    __syncthreads();
+    const unsigned long long r = sh[wid] + incl - v;
+    *total = sh[16];
+    __syncthreads();
+    return r;
+}
+
+template <class Op>
+__global__ void k_scan_part(Op op, unsigned long long* part) {
+    __shared__ unsigned long long sh[17];
+    const int64_t b0 = op.begin(), e0 = op.end();
+    const int64_t n = e0 > b0 ? e0 - b0 : 0;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = b0 + blockIdx.x * chunk;
+    const int64_t hi = min(lo + chunk, e0);
+    unsigned long long s = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += op.value(i);
+    unsigned long long tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single workgroup of kScanBlocks threads
+__global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, Counters* ctr, int slot) {
+    __shared__ unsigned long long sh[17];
+    const unsigned long long v = part[threadIdx.x];
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan(v, sh, &tot);
+    part[threadIdx.x] = ex;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long base = ctr->slot[slot][0];
+        ctr->slot[slot][1] = base;
+        ctr->slot[slot][2] = tot;
+        ctr->slot[slot][0] = base + tot;
+    }
+}
+
+template <class Op>
+__global__ void k_scan_apply(Op op, const unsigned long long* part, const Counters* ctr, int slot) {
+    __shared__ unsigned long long sh[17];
+    const int64_t b0 = op.begin(), e0 = op.end();
+    const int64_t n = e0 > b0 ? e0 - b0 : 0;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = b0 + blockIdx.x * chunk;
+    const int64_t hi = min(lo + chunk, e0);
+    unsigned long long run = ctr->slot[slot][1] + part[blockIdx.x];
+    for (int64_t t0 = lo; t0 < hi; t0 += blockDim.x) {  // uniform trip count per block
+        const int64_t i = t0 + threadIdx.x;
+        const unsigned long long v = (i < hi) ? op.value(i) : 0ull;
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan(v, sh, &tot);
+        if (i < hi && v) op.write(i, run + ex, v);
+        run += tot;
+    }
+}
+
+// Start hits, over cluster ids [c0, c1) of an instance range.
+struct StartOp {
+    Bufs b;
+    int64_t c0, c1;
+    int i0, i1;
+    __device__ int64_t begin() const { return c0; }
+    __device__ int64_t end() const { return c1; }
+    __device__ unsigned long long value(int64_t id) const {
+        const int32_t p = b.pos_of[id];
+        const int32_t u = b.upc[p];
+        return (b.dnc[p] == -1 && u != -1 && b.upc[u] != -1) ? 1ull : 0ull;
+    }
+    __device__ void write(int64_t id, unsigned long long prefix, unsigned long long) const {
+        const int64_t j = (int64_t)(prefix & 0xFFFFFFFFull);
+        if (j >= b.cap_starts) {
+            raise_err(b.ctr, ERR_SCRATCH);
+            return;
+        }
+        const int nr = b.K->n_rows;
+        int lo = i0, hi = i1;  // instance: last k with row_start[k*nr] <= id
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (b.row_start[(int64_t)mid * nr] <= id) lo = mid;
+            else hi = mid;
+        }
+        b.starts[j] = b.pos_of[id];
+        b.start_inst[j] = lo;
+    }
+};
+
+// Selection, over tracklets of the current start range.
+__device__ __forceinline__ uint32_t packed_weight(int nh, int tid) {
+    return ((uint32_t)nh << 20) | (uint32_t)(0xFFFFF - tid);
+}
+
+struct SelectOp {
+    Bufs b;
+    __device__ int64_t begin() const { return (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull); }
+    __device__ int64_t end() const {
+        const int64_t e = begin() + (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
+        return e < b.cap_starts ? e : b.cap_starts;
+    }
+    __device__ int owned(int64_t j, int nh, uint32_t w) const {
+        const int nr = b.K->n_rows;
+        int c = 0;
+        for (int k = 0; k < nh; ++k) c += (b.weight[b.tl_pick_pos[j * nr + k]] == w) ? 1 : 0;
+        return c;
+    }
+    __device__ unsigned long long value(int64_t j) const {
+        const int nh = b.tl_nhits[j];
+        if (nh < b.K->n_min) return 0ull;
+        const int own = owned(j, nh, packed_weight(nh, b.tl_tid[j]));
+        return own >= b.K->n_min ? ((1ull << 32) | (unsigned long long)own) : 0ull;
+    }
+    __device__ void write(int64_t j, unsigned long long prefix, unsigned long long v) const {
+        const int64_t si = (int64_t)(prefix >> 32);
+        const int64_t ho = (int64_t)(prefix & 0xFFFFFFFFull);
+        const int own = (int)(v & 0xFFFFFFFFull);
+        if (si >= b.cap_sel || ho + own > b.n_clusters) {
+            raise_err(b.ctr, ERR_SCRATCH);
+            return;
+        }
+        const int nr = b.K->n_rows;
+        const int nh = b.tl_nhits[j];
+        const uint32_t w = packed_weight(nh, b.tl_tid[j]);
+        b.sel_tl[si] = (int32_t)j;
+        b.sel_off[si] = (int32_t)ho;
+        b.sel_n[si] = own;
+        int m = 0;
+        for (int k = nh - 1; k >= 0; --k) {  // picks are stored rows-descending
+            const int32_t pos = b.tl_pick_pos[j * nr + k];
+            if (b.weight[pos] == w) {
+                b.sel_pos[ho + m] = pos;
+                b.sel_row[ho + m] = b.tl_pick_row[j * nr + k];
+                ++m;
+            }
+        }
+    }
+};
+
+// Output tracks, over the current range of selected tracklets.
+struct TrackOp {
+    Bufs b;
+    __device__ int64_t begin() const { return (int64_t)(b.ctr->slot[SL_SEL][1] >> 32); }
+    __device__ int64_t end() const {
+        const int64_t e = begin() + (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
+        return e < b.cap_sel ? e : b.cap_sel;
+    }
+    __device__ unsigned long long value(int64_t si) const {
+        return b.rf_ok[si] ? ((1ull << 32) | (unsigned long long)b.rf_nacc[si]) : 0ull;
+    }
+    __device__ void write(int64_t si, unsigned long long prefix, unsigned long long v) const {
+        const int64_t t = (int64_t)(prefix >> 32);
+        const int64_t ho = (int64_t)(prefix & 0xFFFFFFFFull);
+        const int nacc = (int)(v & 0xFFFFFFFFull);
+        if (t >= b.cap_tracks || ho + nacc > b.cap_hits) {
+            raise_err(b.ctr, ERR_OUT_CAP);
+            return;
+        }
+        const DevConsts& K = *b.K;
+        const int32_t tl = b.sel_tl[si];
+        const int32_t inst = b.start_inst[tl];
+        b.o_inst[t] = inst;
+        b.o_xref[t] = K.X[b.rf_row[si]];
+        const int sec = b.inst_sector[inst];
+        b.o_alpha[t] = K.alpha[((sec % 18) + 18) % 18];
+        for (int q = 0; q < 5; ++q) b.o_param[t * 5 + q] = b.rf_state[si * 20 + q];
+        for (int q = 0; q < 15; ++q) b.o_cov[t * 15 + q] = b.rf_state[si * 20 + 5 + q];
+        b.o_chi2[t] = b.rf_chi2[si];
+        b.o_ndf[t] = 2 * nacc - 5;
+        b.o_hit_start[t] = ho;
+        const int off = b.sel_off[si], n = b.sel_n[si];
+        int m = 0;
+        for (int i = 0; i < n; ++i)
+            if (b.sel_mask[off + i] & 4) b.o_hit_id[ho + m++] = b.sid[b.sel_pos[off + i]];
+    }
+};
+
+// ------------------------------------------------------------------ tracklets
+struct Pick {
+    int32_t pos;
+    int32_t id;
+    Innov inn;
+};
+
+// Best cluster on the row of segment `seg` for the predicted state.
+__device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, const KState& s, int64_t seg,
+                                            Pick& out, unsigned long long& ncand) {
+    const GridView g = grid_view(b, seg);
+    if (g.n == 0) return false;
+    const float s00 = s.C[0] + K.vy, s01 = s.C[1], s11 = s.C[2] + K.vz;
+    const float wy = K.nsig * __builtin_sqrtf(s00), wz = K.nsig * __builtin_sqrtf(s11);
+    const float det = s00 * s11 - s01 * s01;
+    const float idet = 1.0f / det;
+    const float a00 = s11 * idet, a01 = (-s01) * idet, a11 = s00 * idet;
+    const float py = s.p[0], pz = s.p[1];
+    const int y0 = bin_of((py - wy) - kBinMargin, g.ymin, g.iy, g.ny);
+    const int y1 = bin_of((py + wy) + kBinMargin, g.ymin, g.iy, g.ny);
+    const int z0 = bin_of((pz - wz) - kBinMargin, g.zmin, g.iz, g.nz);
+    const int z1 = bin_of((pz + wz) + kBinMargin, g.zmin, g.iz, g.nz);
+    bool found = false;
+    for (int bz = z0; bz <= z1; ++bz) {
+        const int q0 = g.bs[bz * g.ny + y0], q1 = g.bs[bz * g.ny + y1 + 1];
+        for (int q = q0; q < q1; ++q) {
+            const int64_t pos = g.rs + q;
+            const float r0 = b.ys[pos] - py, r1 = b.zs[pos] - pz;
+            ++ncand;
+            if (!(__builtin_fabsf(r0) <= wy && __builtin_fabsf(r1) <= wz)) continue;
+            const float w0 = a00 * r0 + a01 * r1;
+            const float w1 = a01 * r0 + a11 * r1;
+            const float chi2 = r0 * w0 + r1 * w1;
+            if (!(chi2 <= K.chi2_pick)) continue;
+            const int32_t id = b.sid[pos];
+            if (!found || chi2 < out.inn.chi2 || (chi2 == out.inn.chi2 && id < out.id)) {
+                found = true;
+                out.pos = (int32_t)pos;
+                out.id = id;
+                out.inn.a00 = a00;
+                out.inn.a01 = a01;
+                out.inn.a11 = a11;
+                out.inn.r0 = r0;
+                out.inn.r1 = r1;
+                out.inn.chi2 = chi2;
+            }
+        }
+    }
+    return found;
+}
+
+__device__ __forceinline__ bool seed_from_chain(const DevConsts& K, float x0, float y0, float z0, float xm, float ym,
+                                                float xe, float ye, float ze, KState& s) {
+    const float ax = xm - x0, ay = ym - y0, bx = xe - x0, by = ye - y0, cx = xe - xm, cy = ye - ym;
+    const float cr = ax * by - ay * bx;
+    const float d01 = __builtin_sqrtf(ax * ax + ay * ay);
+    const float d02 = __builtin_sqrtf(bx * bx + by * by);
+    const float d12 = __builtin_sqrtf(cx * cx + cy * cy);
+    const float kap = (2.0f * cr) / ((d01 * d02) * d12);
+    float v = (kap * d02) * 0.5f;
+    if (v > 1.0f) v = 1.0f;
+    if (v < -1.0f) v = -1.0f;
+    const float sn = by / d02, cs = bx / d02;
+    const float s0 = sn * __builtin_sqrtf(1.0f - v * v) - cs * v;
+    const float arc = d02 * asin_over_u(v);
+    const float t0 = (ze - z0) / arc;
+    float q0 = (K.kB != 0.0f) ? kap / K.kB : 0.0f;
+    if (q0 > K.q_max) q0 = K.q_max;
+    if (q0 < -K.q_max) q0 = -K.q_max;
+    if (!(__builtin_fabsf(s0) < K.sinphi_max)) return false;
+    s.p[0] = y0;
+    s.p[1] = z0;
+    s.p[2] = s0;
+    s.p[3] = t0;
+    s.p[4] = q0;
+#pragma unroll
+    for (int q = 0; q < 15; ++q) s.C[q] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) s.C[pk(i, i)] = K.c0[i];
+    return true;
+}
+
+__device__ __forceinline__ int lower_bound_inst(const int32_t* a, int64_t lo, int64_t hi, int32_t v) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return (int)lo;
+}
+
+// One lane per start hit: seed, stage 1 (chain), stage 2 (outward), turn,
+// stage 3 (inward re-pick), weights.
+__global__ void k_tracklet(Bufs b) {
+    const DevConsts& K = *b.K;
+    const int nr = K.n_rows;
+    const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
+    if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;  // never hit: N/3 bound
+    unsigned long long st_chain = 0, st_rows = 0, st_cand = 0, st_picks = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cnt; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = base + k;
+        const int32_t pos0 = b.starts[j];
+        const int32_t inst = b.start_inst[j];
+        const int tid = (int)(j - lower_bound_inst(b.start_inst, base, base + cnt, inst));
+        b.tl_tid[j] = tid;
+        b.tl_nhits[j] = 0;
+        b.tl_row[j] = -1;
+        if (tid >= (1 << 20)) {
+            raise_err(b.ctr, ERR_TID_CAP);
+            continue;
+        }
+        const int64_t seg0 = (int64_t)inst * nr;
+        const int r0 = row_of(b.row_start, seg0, nr, pos0);
+        int L = 1;
+        int32_t pe = pos0;
+        while (b.upc[pe] >= 0) {
+            pe = b.upc[pe];
+            ++L;
+        }
+        const int m = (L - 1) / 2;
+        int32_t pm = pos0;
+        for (int i = 0; i < m; ++i) pm = b.upc[pm];
+        KState s;
+        const bool seeded = seed_from_chain(K, K.X[r0], b.ys[pos0], b.zs[pos0], K.X[r0 + m], b.ys[pm],
+                                            K.X[r0 + L - 1], b.ys[pe], b.zs[pe], s);
+        int cur = r0;
+        bool ok = seeded;
+        // stage 1
+        if (ok) {
+            int32_t p = pos0;
+            for (int i = 0; i < L; ++i) {
+                if (i > 0) {
+                    if (!kf_propagate(s, K.X[r0 + i - 1], K.X[r0 + i], K)) {
+                        ok = false;
+                        break;
+                    }
+                    p = b.upc[p];
+                }
+                const Innov n = kf_innovation(s, b.ys[p], b.zs[p], K);
+                kf_update(s, n);
+            }
+            st_chain += L;
+        }
+        int nh = 0;
+        if (ok) {
+            // stage 2
+            cur = r0 + L - 1;
+            int last = cur, miss = 0;
+            for (int r = cur + 1; r < nr && miss < K.max_miss; ++r) {
+                if (!kf_propagate(s, K.X[r - 1], K.X[r], K)) break;
+                cur = r;
+                ++st_rows;
+                Pick pk_;
+                if (pick_on_row(b, K, s, seg0 + r, pk_, st_cand)) {
+                    kf_update(s, pk_.inn);
+                    last = r;
+                    miss = 0;
+                } else {
+                    ++miss;
+                }
+            }
+            // turn, stage 3
+            kf_reset(s, K);
+            bool down_ok = true;
+            for (int r = cur - 1; r >= last; --r) {
+                if (!kf_propagate(s, K.X[r + 1], K.X[r], K)) {
+                    down_ok = false;
+                    break;
+                }
+                cur = r;
+            }
+            if (down_ok) {
+                miss = 0;
+                for (int r = last; r >= 0; --r) {
+                    if (r != cur) {
+                        if (!kf_propagate(s, K.X[cur], K.X[r], K)) break;
+                        cur = r;
+                    }
+                    ++st_rows;
+                    Pick pk_;
+                    if (pick_on_row(b, K, s, seg0 + r, pk_, st_cand)) {
+                        kf_update(s, pk_.inn);
+                        b.tl_pick_pos[j * nr + nh] = pk_.pos;
+                        b.tl_pick_row[j * nr + nh] = (uint8_t)r;
+                        ++nh;
+                        miss = 0;
+                    } else if (++miss >= K.max_miss) {
+                        break;
+                    }
+                }
+            }
+            b.tl_row[j] = cur;
+        }
+        b.tl_nhits[j] = nh;
+        st_picks += nh;
+        float* o = b.tl_state + j * 20;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[q] = s.p[q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) o[5 + q] = s.C[q];
+        if (!ok) {
+#pragma unroll
+            for (int q = 0; q < 20; ++q) o[q] = 0.0f;
+        }
+        if (nh >= K.n_min) {
+            const uint32_t w = packed_weight(nh, tid);
+            for (int q = 0; q < nh; ++q) atomicMax(&b.weight[b.tl_pick_pos[j * nr + q]], w);
+        }
+    }
+    if (K.stats) {
+        stat_add(b.ctr, ST_CHAIN_HITS, st_chain);
+        stat_add(b.ctr, ST_TL_ROWS, st_rows);
+        stat_add(b.ctr, ST_TL_CAND, st_cand);
+        stat_add(b.ctr, ST_TL_PICKS, st_picks);
+    }
+}
+
+// ------------------------------------------------------------------ refit
+// One lane per selected tracklet: move to the outermost hit, then three
+// passes inward, outward, inward, each after a covariance reset; a hit is
+// used iff its predicted chi2 <= chi2_rej.
+__global__ void k_refit(Bufs b) {
+    const DevConsts& K = *b.K;
+    const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
+    if (base + cnt > b.cap_sel) cnt = b.cap_sel > base ? b.cap_sel - base : 0;  // never hit: N/n_min bound
+    unsigned long long st_rows = 0, st_hits = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cnt; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t si = base + k;
+        const int32_t tl = b.sel_tl[si];
+        const int off = b.sel_off[si], n = b.sel_n[si];
+        KState s;
+        const float* st = b.tl_state + (int64_t)tl * 20;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s.p[q] = st[q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) s.C[q] = st[5 + q];
+        int cur = b.tl_row[tl];
+        bool ok = (n > 0);
+        const int outer = ok ? (int)b.sel_row[off + n - 1] : 0;
+        while (ok && cur != outer) {
+            const int nx = cur < outer ? cur + 1 : cur - 1;
+            if (!kf_propagate(s, K.X[cur], K.X[nx], K)) ok = false;
+            else cur = nx;
+            ++st_rows;
+        }
+        for (int i = 0; i < n; ++i) b.sel_mask[off + i] = 0;
+        float chi2sum = 0.0f;
+        int nacc = 0;
+        for (int pass = 0; pass < 3 && ok; ++pass) {
+            kf_reset(s, K);
+            const bool inward = (pass != 1);
+            for (int q = 0; q < n && ok; ++q) {
+                const int i = inward ? n - 1 - q : q;
+                const int target = b.sel_row[off + i];
+                while (cur != target) {
+                    const int nx = cur < target ? cur + 1 : cur - 1;
+                    if (!kf_propagate(s, K.X[cur], K.X[nx], K)) {
+                        ok = false;
+                        break;
+                    }
+                    cur = nx;
+                    ++st_rows;
+                }
+                if (!ok) break;
+                const int32_t pos = b.sel_pos[off + i];
+                const Innov inn = kf_innovation(s, b.ys[pos], b.zs[pos], K);
+                ++st_hits;
+                if (inn.chi2 <= K.chi2_rej) {
+                    kf_update(s, inn);
+                    b.sel_mask[off + i] = (uint8_t)(b.sel_mask[off + i] | (1u << pass));
+                    if (pass == 2) {
+                        chi2sum = chi2sum + inn.chi2;
+                        ++nacc;
+                    }
+                }
+            }
+        }
+        float* o = b.rf_state + si * 20;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[q] = s.p[q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) o[5 + q] = s.C[q];
+        b.rf_chi2[si] = chi2sum;
+        b.rf_nacc[si] = nacc;
+        b.rf_row[si] = cur;
+        b.rf_ok[si] = (ok && nacc >= K.n_min) ? 1 : 0;
+    }
+    if (K.stats) {
+        stat_add(b.ctr, ST_RF_ROWS, st_rows);
+        stat_add(b.ctr, ST_RF_HITS, st_hits);
+    }
+}
+
+// ------------------------------------------------------------------ finish
+// FP64 totals in a fixed order (one workgroup: strided per-lane sums, then a
+// fixed tree), and the closing entry of the output CSR.
+__global__ __launch_bounds__(1024) void k_finish(Bufs b) {
+    __shared__ double shc[1024];
+    __shared__ double shn[1024];
+    const unsigned long long tot = b.ctr->slot[SL_TRK][0];
+    const int64_t nt = (int64_t)(tot >> 32);
+    const int64_t nh = (int64_t)(tot & 0xFFFFFFFFull);
+    const int64_t n = nt < b.cap_tracks ? nt : b.cap_tracks;
+    double c = 0.0, d = 0.0;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        c += (double)b.o_chi2[t];
+        d += (double)b.o_ndf[t];
+    }
+    shc[threadIdx.x] = c;
+    shn[threadIdx.x] = d;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            shc[threadIdx.x] += shc[threadIdx.x + s];
+            shn[threadIdx.x] += shn[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (b.o_chi2_total) {
+            b.o_chi2_total[0] = shc[0];
+            b.o_chi2_total[1] = shn[0];
+        }
+        if (nt <= b.cap_tracks && nh <= b.cap_hits) b.o_hit_start[nt] = nh;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_reset_counters(Counters* c) {
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
+    const int nw = (int)(sizeof(Counters) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0ull;
+}
+
+// ------------------------------------------------------------------ exports
+__global__ void k_export_grid(Bufs b, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz, float* meta,
+                              int64_t nseg) {
+    const int64_t N = b.n_clusters;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < N; i += stride) sorted_id[i] = b.sid[i];
+    for (int64_t i = i0; i < N + nseg + 1; i += stride) bin_start[i] = b.bin_start[i];
+    for (int64_t s = i0; s < nseg; s += stride) {
+        ny[s] = b.gny[s];
+        nz[s] = b.gnz[s];
+        const float4 m = b.gmeta[s];
+        meta[4 * s] = m.x;
+        meta[4 * s + 1] = m.y;
+        meta[4 * s + 2] = m.z;
+        meta[4 * s + 3] = m.w;
+    }
+}
+
+__global__ void k_export_links(Bufs b, int32_t* up, int32_t* dn, int32_t* upc, int32_t* dnc) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < b.n_clusters;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t id = b.sid[p];
+        const int32_t u = b.up[p], d = b.dn[p], uc = b.upc[p], dc = b.dnc[p];
+        up[id] = u >= 0 ? b.sid[u] : -1;
+        dn[id] = d >= 0 ? b.sid[d] : -1;
+        upc[id] = uc >= 0 ? b.sid[uc] : -1;
+        dnc[id] = dc >= 0 ? b.sid[dc] : -1;
+    }
+}
+
+__global__ void k_export_tracklets(Bufs b, int64_t ns, int32_t* start_hit, int32_t* start_inst, int32_t* start_tid,
+                                   int32_t* nhits, int32_t* rowhit, float* state, int32_t* state_row,
+                                   uint32_t* weight) {
+    const int nr = b.K->n_rows;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t j = i0; j < ns; j += stride) {
+        start_hit[j] = b.sid[b.starts[j]];
+        start_inst[j] = b.start_inst[j];
+        start_tid[j] = b.tl_tid[j];
+        const int nh = b.tl_nhits[j];
+        nhits[j] = nh;
+        for (int r = 0; r < nr; ++r) rowhit[j * nr + r] = -1;
+        for (int k = 0; k < nh; ++k) rowhit[j * nr + b.tl_pick_row[j * nr + k]] = b.sid[b.tl_pick_pos[j * nr + k]];
+        for (int q = 0; q < 20; ++q) state[j * 20 + q] = b.tl_state[j * 20 + q];
+        state_row[j] = b.tl_row[j];
+    }
+    for (int64_t p = i0; p < b.n_clusters; p += stride) weight[b.sid[p]] = b.weight[p];
+}
+
+__global__ void k_export_selected(Bufs b, int64_t nsel, int32_t* sel_tl, int64_t* hit_start, int32_t* hit_id,
+                                  uint8_t* mask, int32_t* status) {
+    for (int64_t si = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; si < nsel; si += (int64_t)gridDim.x * blockDim.x) {
+        sel_tl[si] = b.sel_tl[si];
+        const int off = b.sel_off[si], n = b.sel_n[si];
+        hit_start[si] = off;
+        if (si == nsel - 1) hit_start[nsel] = off + n;
+        for (int i = 0; i < n; ++i) {
+            hit_id[off + i] = b.sid[b.sel_pos[off + i]];
+            mask[off + i] = b.sel_mask[off + i];
+        }
+        status[si] = b.rf_ok[si];
+    }
+}
+
+__global__ void k_fp32_selfcheck(const float* a, const float* bb, float* od, float* os, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        od[i] = a[i] / bb[i];
+        os[i] = __builtin_sqrtf(__builtin_fabsf(a[i]));
+    }
+}
+
+inline int grid_for(int64_t n, int block, int cap = 65536) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+template <class Op>
+void launch_scan(const Op& op, const Bufs& b, int slot, int block, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_part<Op>, dim3(kScanBlocks), dim3(block), 0, st, op, b.scan_part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, st, b.scan_part, b.ctr, slot);
+    hipLaunchKernelGGL(k_scan_apply<Op>, dim3(kScanBlocks), dim3(block), 0, st, op, (const unsigned long long*)b.scan_part,
+                       (const Counters*)b.ctr, slot);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+void enqueue_reset(const Bufs& b, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, b.ctr);
+}
+
+void enqueue_weights_clear(const Bufs& b, int64_t c0, int64_t c1, hipStream_t st) {
+    if (c1 > c0)
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(c1 - c0, 256, 4096)), dim3(256), 0, st, b.weight + c0, c1 - c0, 0u);
+}
+
+void enqueue_grid(const Bufs& b, int i0, int i1, hipStream_t st) {
+    const int64_t seg0 = (int64_t)i0 * b.n_rows, nseg = (int64_t)(i1 - i0) * b.n_rows;
+    if (nseg <= 0) return;
+    hipLaunchKernelGGL(k_grid<kSmallRow>, dim3((unsigned)nseg), dim3(256), 0, st, b, seg0);
+    hipLaunchKernelGGL(k_grid<kLargeRow>, dim3((unsigned)nseg), dim3(256), 0, st, b, seg0);
+}
+
+void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, hipStream_t st) {
+    const int64_t seg0 = (int64_t)i0 * b.n_rows, nseg = (int64_t)(i1 - i0) * b.n_rows;
+    if (nseg <= 0) return;
+    hipLaunchKernelGGL(k_links, dim3((unsigned)nseg), dim3(L.block_links), 0, st, b, seg0);
+}
+
+void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, hipStream_t st) {
+    if (c1 > c0) hipLaunchKernelGGL(k_clean, dim3(grid_for(c1 - c0, 256, 8192)), dim3(256), 0, st, b, c0, c1);
+    StartOp op{b, c0, c1, i0, i1};
+    launch_scan(op, b, SL_START, L.block_scan, st);
+}
+
+void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
+    hipLaunchKernelGGL(k_tracklet, dim3(grid_for(bound, L.block_tracklet, 16384)), dim3(L.block_tracklet), 0, st, b);
+}
+
+void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
+    (void)bound;
+    SelectOp op{b};
+    launch_scan(op, b, SL_SEL, L.block_scan, st);
+}
+
+void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(bound, L.block_refit, 16384)), dim3(L.block_refit), 0, st, b);
+}
+
+void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
+    (void)bound;
+    TrackOp op{b};
+    launch_scan(op, b, SL_TRK, L.block_scan, st);
+}
+
+void enqueue_finish(const Bufs& b, hipStream_t st) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, b);
+}
+
+void enqueue_export_grid(const Bufs& b, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz,
+                         float* meta, int64_t nseg, hipStream_t st) {
+    hipLaunchKernelGGL(k_export_grid, dim3(grid_for(b.n_clusters + nseg + 1, 256, 8192)), dim3(256), 0, st, b,
+                       sorted_id, bin_start, ny, nz, meta, nseg);
+}
+
+void enqueue_export_links(const Bufs& b, int32_t* up, int32_t* dn, int32_t* upc, int32_t* dnc, hipStream_t st) {
+    hipLaunchKernelGGL(k_export_links, dim3(grid_for(b.n_clusters, 256, 8192)), dim3(256), 0, st, b, up, dn, upc, dnc);
+}
+
+void enqueue_export_tracklets(const Bufs& b, int64_t n_starts, int32_t* start_hit, int32_t* start_inst,
+                              int32_t* start_tid, int32_t* nhits, int32_t* rowhit, float* state,
+                              int32_t* state_row, uint32_t* weight, hipStream_t st) {
+    const int64_t n = n_starts > b.n_clusters ? n_starts : b.n_clusters;
+    hipLaunchKernelGGL(k_export_tracklets, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, b, n_starts, start_hit,
+                       start_inst, start_tid, nhits, rowhit, state, state_row, weight);
+}
+
+void enqueue_export_selected(const Bufs& b, int64_t n_sel, int32_t* sel_tl, int64_t* hit_start, int32_t* hit_id,
+                             uint8_t* mask, int32_t* status, hipStream_t st) {
+    if (n_sel <= 0) return;
+    hipLaunchKernelGGL(k_export_selected, dim3(grid_for(n_sel, 256, 8192)), dim3(256), 0, st, b, n_sel, sel_tl,
+                       hit_start, hit_id, mask, status);
+}
+
+void enqueue_fp32_selfcheck(const float* a, const float* bb, float* od, float* os, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fp32_selfcheck, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a, bb, od, os, n);
+}
+
+}  // namespace tpcca
