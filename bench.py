@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X TPC sector tracker on one GPU.
+
+One step = one pass of the whole hot path (grid, CA links, cleaning and
+starts, tracklets, selection, three-pass refit, compaction, FP64 totals) over
+one synthetic central Pb-Pb-like event (36 sectors x 152 pad rows, 8000
+primaries + 800 secondaries, 2 % noise, ~1.37 M clusters), with the clusters
+already resident in device memory. The timed form is the batched one (one
+launch per stage over all sector instances, replayed as a HIP graph); the
+plain form (every stage launched per sector) is timed beside it.
+
+Prints one JSON line (rank 0): clusters/s as `value`, tracks/s, the roofline
+of the dominant kernel (per-stage HIP events measured in this run, and an
+algorithmic byte model fed by the kernels' own work counters) and the oracle
+timed on the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TPC clusters/sec + tracks/sec (CA+Kalman, 1 GPU), % HBM roofline; batched vs plain"
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+WORKLOADS = {
+    "C2": "central Pb-Pb-like event: 36 sectors x 152 pad rows, 8000 primary + 800 secondary helices "
+          "(pT exp(0.5 GeV) in [0.1,10], |eta|<0.9, 0.5 T), sigma 0.1 cm, 2% noise",
+    "C2x8": "eight central Pb-Pb-like events (288 sector instances) in one batch",
+    "C3": "continuous-readout slice: 100 collisions x Exp(800) tracks, drift shift 0-250 cm, 2% noise",
+    "C4": "256 sector instances, log-uniform 50-2000 helices each, 1% noise",
+    "C1": "one sector, 200 helices, 1% noise",
+}
+
+
+def byte_model(stage: str, st: dict, n_clusters: int, n_seg: int, hits_per_bin: int) -> int:
+    """Algorithmic bytes of one launch of a stage."""
+    N = n_clusters
+    if stage == "grid":
+        return 24 * N + 32 * n_seg + 4 * (N // max(1, hits_per_bin) + n_seg)
+    if stage == "links":
+        return 32 * N
+    if stage == "tracklets":
+        return (100 * st["n_starts"] + 12 * st["n_chain_hits"] + 64 * st["tl_rows_visited"]
+                + 8 * st["tl_candidates"] + 13 * st["tl_picks"])
+    if stage == "refit":
+        return 192 * st["n_selected"] + 14 * st["rf_hit_visits"]
+    if stage == "clean_starts":
+        return 24 * N + 12 * st["n_starts"]
+    if stage == "select":
+        return 2 * (8 * st["n_starts"] + 8 * st["tl_picks"]) + 13 * st["n_selected_hits"] + 12 * st["n_selected"]
+    if stage == "write":
+        return 2 * 8 * st["n_selected"] + 108 * st["n_tracks"] + 9 * st["n_selected_hits"]
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick tiling with tpcca_autotune before timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the tracker shards by sector instance with no communication, "
+              "and this build runs on a single MI355X (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1811_11481_amd import DeviceClusters, Tracker, default_params
+    from paper_1811_11481_amd.tpcca import FLAG_STATS, FLAG_TIMING
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    t_gen = time.perf_counter()
+    cs = synth.generate(args.workload)
+    print("[bench] workload %s: %d clusters, %d instances (generated in %.1fs)"
+          % (args.workload, cs.n_clusters, cs.n_inst, time.perf_counter() - t_gen), file=sys.stderr, flush=True)
+    dc = DeviceClusters.from_host(cs)
+    trk = Tracker()
+    tuning_note = "default"
+    if args.autotune:
+        t = trk.autotune(dc, repeats=3)
+        tuning_note = "autotuned %s" % t.as_dict()
+    out = trk.alloc_tracks(dc)
+    for _ in range(args.warmup):
+        trk.track(dc, out, batched=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        trk.track(dc, out, batched=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    n_tracks = out.n_tracks
+    print("[bench] batched: %.3f ms/step, %d tracks" % (ms, n_tracks), file=sys.stderr, flush=True)
+
+    plain_ms = None
+    if not args.no_plain and args.plain_steps > 0:
+        trk.track(dc, out, batched=False)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            trk.track(dc, out, batched=False)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - p0) / args.plain_steps * 1e3
+        assert out.n_tracks == n_tracks
+        print("[bench] plain: %.3f ms/step" % plain_ms, file=sys.stderr, flush=True)
+
+    # per-stage kernel time: HIP events between the stages on the launch stream
+    trk_t = Tracker(params=default_params(flags=FLAG_TIMING), tuning=trk.tuning)
+    outt = trk_t.alloc_tracks(dc)
+    stage_ms = {}
+    for k in range(args.warmup + args.steps):
+        trk_t.track(dc, outt, batched=True)
+        if k >= args.warmup:
+            for name, v in trk_t.stage_times().items():
+                stage_ms.setdefault(name, []).append(v)
+    stage_avg = {k: statistics.mean(v) for k, v in stage_ms.items()}
+    # work counters for the byte model (separate pass: the counters use atomics)
+    trk_s = Tracker(params=default_params(flags=FLAG_STATS), tuning=trk.tuning)
+    trk_s.track(dc, trk_s.alloc_tracks(dc), batched=True)
+    st = trk_s.stats()
+    nseg = cs.n_inst * 152
+    hpb = trk.tuning.hits_per_bin
+    stages = {}
+    for name, t in stage_avg.items():
+        b = byte_model(name, st, cs.n_clusters, nseg, hpb)
+        stages[name] = {"ms": round(t, 4), "alg_bytes": b,
+                        "GBps": round(b / (t * 1e-3) / 1e9, 2) if t > 0 and b else None}
+    dom = max((k for k in stages if k != "finish"), key=lambda k: stages[k]["ms"])
+    dom_bytes = stages[dom]["alg_bytes"]
+    achieved = dom_bytes / (stages[dom]["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": stages[dom]["ms"]}
+    print("[bench] stages (ms): %s" % {k: v["ms"] for k, v in stages.items()}, file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle  # CPU baseline leg only
+        sample = cs
+        note = "full %s workload (%d clusters), binary32 oracle, 1 thread" % (args.workload, cs.n_clusters)
+        if cs.n_clusters > 3_000_000:
+            k = max(1, int(cs.n_inst * 2_000_000 / cs.n_clusters))
+            sample = cs.subset(list(range(k)))
+            note = "first %d of %d instances of %s (%d clusters), binary32 oracle, 1 thread" % (
+                k, cs.n_inst, args.workload, sample.n_clusters)
+        c0 = time.perf_counter()
+        r = oracle.run(sample, 32, threads=1)
+        dt = time.perf_counter() - c0
+        cpu = {"value": round(sample.n_clusters / dt, 1), "unit": "clusters/s", "cores": 1, "kind": "oracle",
+               "sample": note, "seconds": round(dt, 3), "tracks_per_s": round(r.n_tracks / dt, 1)}
+        print("[bench] cpu oracle: %.2fs" % dt, file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": round(cs.n_clusters / (ms * 1e-3), 1),
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "n_clusters": cs.n_clusters,
+                   "n_instances": cs.n_inst, "form": "batched, HIP graph", "tuning": tuning_note},
+        "tracks_per_s": round(n_tracks / (ms * 1e-3), 1),
+        "n_tracks": n_tracks,
+        "plain_ms_per_step": round(plain_ms, 4) if plain_ms else None,
+        "batched_speedup_vs_plain": round(plain_ms / ms, 3) if plain_ms else None,
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,6 +77,7 @@ typedef struct {
 } tpcca_params;
 
 #define TPCCA_FLAG_STATS 1u       /* count work items (rows visited, candidates) for the byte model */
+#define TPCCA_FLAG_TIMING 2u      /* batched form runs uncaptured with HIP events between stages */
 
 /* Launch/tiling choices. They never change results (tested bit-exact). */
 typedef struct {
@@ -178,7 +179,7 @@ tpcca_status tpcca_export_selected(tpcca_ctx* ctx, int32_t* sel_tl, int64_t* hit
 tpcca_status tpcca_get_stats(tpcca_ctx* ctx, tpcca_stats* out); /* host out; syncs */
 /* Stage timing of the last batched call (host out, ms): weights clear + grid, links, clean + starts,
  * tracklets, selection, refit, compaction into the outputs, FP64 totals. Filled only when the
- * context was created with TPCCA_FLAG_STATS (the batched form then runs without graph capture). */
+ * context was created with TPCCA_FLAG_TIMING (the batched form then runs without graph capture). */
 tpcca_status tpcca_get_stage_times(tpcca_ctx* ctx, float* ms8);
 
 /* Arithmetic self-check: out_div[i] = a[i] / b[i], out_sqrt[i] = sqrt(|a[i]|) with the

@@ -88,7 +88,7 @@ def lib():
         L.orc_seed.argtypes = [ctypes.POINTER(Params), i32, vp, vp]
         L.orc_refit.restype = i32
         L.orc_refit.argtypes = [ctypes.POINTER(Params), i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
-        L.orc_replay_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 11
+        L.orc_replay_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 10
         _lib = L
     return _lib
 

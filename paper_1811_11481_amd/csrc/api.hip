@@ -377,7 +377,7 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
     if (s != TPCCA_OK) return s;
     const Bufs b = make_bufs(ctx, in, out);
     const Launch L = make_launch(ctx->tuning);
-    const bool timing = (ctx->params.flags & TPCCA_FLAG_STATS) != 0;
+    const bool timing = (ctx->params.flags & TPCCA_FLAG_TIMING) != 0;
     if (timing && !ctx->events) {
         for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
         ctx->events = true;
@@ -604,9 +604,7 @@ tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_
     tr.hit_id = (int32_t*)(mem + o_hid);
     tr.chi2_total = (double*)(mem + o_tot);
     const uint32_t saved_flags = ctx->params.flags;
-    if (saved_flags & TPCCA_FLAG_STATS) {  // time the captured form
-        ctx->params.flags &= ~TPCCA_FLAG_STATS;
-    }
+    ctx->params.flags &= ~TPCCA_FLAG_TIMING;  // time the captured form
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtpcca.so")
 
 OK, E_ARG, E_CAPACITY, E_DEVICE, E_OOM, E_INTERNAL = range(6)
 FLAG_STATS = 1
+FLAG_TIMING = 2
 MAX_ROW_CLUSTERS = 16384
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_CAPACITY", 3: "E_DEVICE", 4: "E_OOM", 5: "E_INTERNAL"}
 
