@@ -578,11 +578,18 @@ struct RefitOut {
     int row;  // row of the output state (innermost hit)
 };
 
+// The refit carries y and z as offsets from a reference point that moves to
+// each accepted cluster, so that binary32 residuals are formed from small
+// numbers (the paper keeps parameters at coordinates where single precision
+// stays accurate, Section 4).
 template <class T>
 RefitOut<T> refit(const Consts<T>& k, State<T> s, int row, int n, const int32_t* rows, const T* ys, const T* zs,
                   uint8_t* masks, const uint8_t* replay) {
     RefitOut<T> o{};
     o.ok = false;
+    T ref_y = s.p[0], ref_z = s.p[1];
+    s.p[0] = (T)0;
+    s.p[1] = (T)0;
     int cur = row;
     auto move_to = [&](int target) {
         while (cur != target) {
@@ -602,10 +609,14 @@ RefitOut<T> refit(const Consts<T>& k, State<T> s, int row, int n, const int32_t*
         for (int q = 0; q < n; ++q) {
             const int i = inward ? n - 1 - q : q;
             if (!move_to(rows[i])) return o;
-            const Innov<T> in = innovation(s, ys[i], zs[i], k);
+            const Innov<T> in = innovation(s, ys[i] - ref_y, zs[i] - ref_z, k);
             const bool acc = replay ? ((replay[i] >> pass) & 1) != 0 : (in.chi2 <= k.chi2_rej);
             if (acc) {
                 update(s, in);
+                s.p[0] = s.p[0] + (ref_y - ys[i]);  // re-centre on the accepted cluster
+                s.p[1] = s.p[1] + (ref_z - zs[i]);
+                ref_y = ys[i];
+                ref_z = zs[i];
                 masks[i] |= (uint8_t)(1u << pass);
                 if (pass == 2) {
                     chi2sum = chi2sum + in.chi2;
@@ -614,6 +625,8 @@ RefitOut<T> refit(const Consts<T>& k, State<T> s, int row, int n, const int32_t*
             }
         }
     }
+    s.p[0] = ref_y + s.p[0];
+    s.p[1] = ref_z + s.p[1];
     o.ok = true;
     o.s = s;
     o.chi2 = chi2sum;

@@ -734,6 +734,11 @@ __global__ void k_refit(Bufs b) {
         for (int q = 0; q < 5; ++q) s.p[q] = st[q];
 #pragma unroll
         for (int q = 0; q < 15; ++q) s.C[q] = st[5 + q];
+        // y and z are carried as offsets from a reference that moves to each
+        // accepted cluster: binary32 residuals are then formed from small values
+        float ref_y = s.p[0], ref_z = s.p[1];
+        s.p[0] = 0.0f;
+        s.p[1] = 0.0f;
         int cur = b.tl_row[tl];
         bool ok = (n > 0);
         const int outer = ok ? (int)b.sel_row[off + n - 1] : 0;
@@ -763,10 +768,15 @@ __global__ void k_refit(Bufs b) {
                 }
                 if (!ok) break;
                 const int32_t pos = b.sel_pos[off + i];
-                const Innov inn = kf_innovation(s, b.ys[pos], b.zs[pos], K);
+                const float my = b.ys[pos], mz = b.zs[pos];
+                const Innov inn = kf_innovation(s, my - ref_y, mz - ref_z, K);
                 ++st_hits;
                 if (inn.chi2 <= K.chi2_rej) {
                     kf_update(s, inn);
+                    s.p[0] = s.p[0] + (ref_y - my);
+                    s.p[1] = s.p[1] + (ref_z - mz);
+                    ref_y = my;
+                    ref_z = mz;
                     b.sel_mask[off + i] = (uint8_t)(b.sel_mask[off + i] | (1u << pass));
                     if (pass == 2) {
                         chi2sum = chi2sum + inn.chi2;
@@ -775,6 +785,8 @@ __global__ void k_refit(Bufs b) {
                 }
             }
         }
+        s.p[0] = ref_y + s.p[0];
+        s.p[1] = ref_z + s.p[1];
         float* o = b.rf_state + si * 20;
 #pragma unroll
         for (int q = 0; q < 5; ++q) o[q] = s.p[q];
