@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick tiling with tpcca_autotune before timing")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device copy of MIB MiB (reference for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the tracker shards by sector instance with no communication, "
@@ -87,6 +89,14 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_gen = time.perf_counter()
     cs = synth.generate(args.workload)
     print("[bench] workload %s: %d clusters, %d instances (generated in %.1fs)"
