@@ -158,30 +158,26 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     const int64_t cap_s = N / 3 + ninst + 1;
     const int64_t cap_sel = N / std::max(1, ctx->params.n_min) + ninst + 1;
     Layout L;
-    size_t o_ys = L.add(4 * N), o_zs = L.add(4 * N), o_sid = L.add(4 * N), o_pos = L.add(4 * N);
-    size_t o_bs = L.add(4 * (N + nseg + 1)), o_gny = L.add(4 * nseg), o_gnz = L.add(4 * nseg),
-           o_gm = L.add(16 * nseg);
+    size_t o_yz = L.add(8 * N), o_sid = L.add(4 * N), o_pos = L.add(4 * N);
+    size_t o_bs = L.add(4 * (N + nseg + 1)), o_hdr = L.add(sizeof(SegHdr) * nseg);
     size_t o_up = L.add(4 * N), o_dn = L.add(4 * N), o_upc = L.add(4 * N), o_dnc = L.add(4 * N);
     size_t o_st = L.add(4 * cap_s), o_sti = L.add(4 * cap_s), o_so = L.add(4 * cap_s), o_sl = L.add(4 * cap_s);
     size_t o_tn = L.add(4 * cap_s), o_tt = L.add(4 * cap_s), o_tr = L.add(4 * cap_s), o_ts = L.add(80 * cap_s);
     size_t o_tpp = L.add(4 * cap_s * nr), o_tpr = L.add((size_t)cap_s * nr);
     size_t o_w = L.add(4 * N);
     size_t o_sel = L.add(4 * cap_sel), o_soff = L.add(4 * cap_sel), o_sn = L.add(4 * cap_sel);
-    size_t o_spos = L.add(4 * N), o_srow = L.add(N), o_smask = L.add(N);
+    size_t o_spos = L.add(4 * N), o_syz = L.add(8 * N), o_srow = L.add(N), o_smask = L.add(N);
     size_t o_rs = L.add(80 * cap_sel), o_rc = L.add(4 * cap_sel), o_rn = L.add(4 * cap_sel),
            o_rr = L.add(4 * cap_sel), o_rok = L.add(4 * cap_sel);
     size_t o_part = L.add(8 * kScanBlocks);
     *total = L.total;
     if (!really) return;
     char* base = (char*)ctx->arena.base;
-    b.ys = (float*)(base + o_ys);
-    b.zs = (float*)(base + o_zs);
+    b.yz = (float2*)(base + o_yz);
     b.sid = (int32_t*)(base + o_sid);
     b.pos_of = (int32_t*)(base + o_pos);
     b.bin_start = (int32_t*)(base + o_bs);
-    b.gny = (int32_t*)(base + o_gny);
-    b.gnz = (int32_t*)(base + o_gnz);
-    b.gmeta = (float4*)(base + o_gm);
+    b.hdr = (SegHdr*)(base + o_hdr);
     b.up = (int32_t*)(base + o_up);
     b.dn = (int32_t*)(base + o_dn);
     b.upc = (int32_t*)(base + o_upc);
@@ -203,6 +199,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     b.sel_off = (int32_t*)(base + o_soff);
     b.sel_n = (int32_t*)(base + o_sn);
     b.sel_pos = (int32_t*)(base + o_spos);
+    b.sel_yz = (float2*)(base + o_syz);
     b.sel_row = (uint8_t*)(base + o_srow);
     b.sel_mask = (uint8_t*)(base + o_smask);
     b.rf_state = (float*)(base + o_rs);

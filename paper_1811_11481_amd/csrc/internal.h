@@ -34,6 +34,13 @@ struct Counters {
     unsigned long long stats[ST_COUNT];
 };
 
+// Per-(instance, row) grid header, one 32-byte load: first grid position and
+// count of the row's clusters, bin counts, lower corner and inverse bin sizes.
+struct alignas(32) SegHdr {
+    int32_t rs, n, ny, nz;
+    float ymin, zmin, iy, iz;
+};
+
 // All device buffers of one call (scratch + caller arrays).
 struct Bufs {
     const DevConsts* K;
@@ -47,14 +54,11 @@ struct Bufs {
     const float* y;
     const float* z;
     // grid
-    float* ys;
-    float* zs;
+    float2* yz;        // (y, z) at grid position
     int32_t* sid;      // cluster id at grid position
     int32_t* pos_of;   // grid position of cluster id
     int32_t* bin_start;
-    int32_t* gny;
-    int32_t* gnz;
-    float4* gmeta;     // ymin, zmin, inv_y, inv_z
+    SegHdr* hdr;
     int hits_per_bin;
     // CA (grid-position space)
     int32_t* up;
@@ -80,6 +84,7 @@ struct Bufs {
     int32_t* sel_off;
     int32_t* sel_n;
     int32_t* sel_pos;    // [N]
+    float2* sel_yz;      // [N] coordinates of the selected clusters (gathered for the refit)
     uint8_t* sel_row;    // [N]
     uint8_t* sel_mask;   // [N]
     // refit results per selected

@@ -64,20 +64,23 @@ struct GridView {
     float ymin, zmin, iy, iz;
 };
 
-__device__ __forceinline__ GridView grid_view(const Bufs& b, int64_t seg) {
+__device__ __forceinline__ SegHdr load_hdr(const Bufs& b, int64_t seg) { return b.hdr[seg]; }
+
+__device__ __forceinline__ GridView grid_view(const Bufs& b, int64_t seg, const SegHdr& h) {
     GridView g;
-    g.rs = b.row_start[seg];
-    g.n = (int)(b.row_start[seg + 1] - g.rs);
-    g.bs = b.bin_start + g.rs + seg;
-    g.ny = b.gny[seg];
-    g.nz = b.gnz[seg];
-    const float4 m = b.gmeta[seg];
-    g.ymin = m.x;
-    g.zmin = m.y;
-    g.iy = m.z;
-    g.iz = m.w;
+    g.rs = h.rs;
+    g.n = h.n;
+    g.bs = b.bin_start + (int64_t)h.rs + seg;
+    g.ny = h.ny;
+    g.nz = h.nz;
+    g.ymin = h.ymin;
+    g.zmin = h.zmin;
+    g.iy = h.iy;
+    g.iz = h.iz;
     return g;
 }
+
+__device__ __forceinline__ GridView grid_view(const Bufs& b, int64_t seg) { return grid_view(b, seg, load_hdr(b, seg)); }
 
 // ------------------------------------------------------------------ grid
 // One workgroup per (instance, row): exact ranges, bin layout, stable sort of
@@ -149,9 +152,16 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
             iy = ly > 0.0f ? (float)ny / ly : 0.0f;
             iz = lz > 0.0f ? (float)nz / lz : 0.0f;
         }
-        b.gny[seg] = ny;
-        b.gnz[seg] = nz;
-        b.gmeta[seg] = make_float4(ymn, zmn, iy, iz);
+        SegHdr h;
+        h.rs = (int32_t)a;
+        h.n = n;
+        h.ny = ny;
+        h.nz = nz;
+        h.ymin = ymn;
+        h.zmin = zmn;
+        h.iy = iy;
+        h.iz = iz;
+        b.hdr[seg] = h;
         sh_i[0] = ny; sh_i[1] = nz;
         sh_f[0] = ymn; sh_f[1] = zmn; sh_f[2] = iy; sh_f[3] = iz;
     }
@@ -192,8 +202,7 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
         const uint32_t kk = key[p];
         const int i = (int)(kk & ((1u << kKeyShift) - 1));
         const int bin = (int)(kk >> kKeyShift);
-        b.ys[a + p] = b.y[a + i];
-        b.zs[a + p] = b.z[a + i];
+        b.yz[a + p] = make_float2(b.y[a + i], b.z[a + i]);
         b.sid[a + p] = (int32_t)(a + i);
         b.pos_of[a + i] = (int32_t)(a + p);
         const int prev = (p == 0) ? -1 : (int)(key[p - 1] >> kKeyShift);
@@ -228,7 +237,8 @@ __global__ void k_links(Bufs b, int64_t seg0) {
     const float wyu = K.wyu[r], wzu = K.wzu[r], wyd = K.wyd[r], wzd = K.wzd[r], tr = K.tr[r], smax = K.smax;
     unsigned long long n_links = 0, n_cu = 0, n_pairs = 0;
     for (int64_t p = a + threadIdx.x; p < e; p += blockDim.x) {
-        const float yh = b.ys[p], zh = b.zs[p];
+        const float2 ph = b.yz[p];
+        const float yh = ph.x, zh = ph.y;
         bool found = false;
         float best = 0.0f;
         int32_t bu = -1, bd = -1, bu_id = 0, bd_id = 0;
@@ -245,7 +255,8 @@ __global__ void k_links(Bufs b, int64_t seg0) {
                 const int q0 = gu.bs[uz * gu.ny + uy0], q1 = gu.bs[uz * gu.ny + uy1 + 1];
                 for (int q = q0; q < q1; ++q) {
                     const int64_t u = gu.rs + q;
-                    const float yu = b.ys[u], zu = b.zs[u];
+                    const float2 pu = b.yz[u];
+                    const float yu = pu.x, zu = pu.y;
                     if (!(__builtin_fabsf(yu - yh) <= wyu && __builtin_fabsf(zu - zh) <= wzu)) continue;
                     ++n_cu;
                     int32_t uid = -1;
@@ -253,7 +264,8 @@ __global__ void k_links(Bufs b, int64_t seg0) {
                         const int t0 = gd.bs[dz * gd.ny + dy0], t1 = gd.bs[dz * gd.ny + dy1 + 1];
                         for (int t = t0; t < t1; ++t) {
                             const int64_t d = gd.rs + t;
-                            const float yd = b.ys[d], zd = b.zs[d];
+                            const float2 pd = b.yz[d];
+                            const float yd = pd.x, zd = pd.y;
                             if (!(__builtin_fabsf(yd - yh) <= wyd && __builtin_fabsf(zd - zh) <= wzd)) continue;
                             ++n_pairs;
                             const float ey = (yd + (yu - yd) * tr) - yh;
@@ -451,6 +463,7 @@ struct SelectOp {
             const int32_t pos = b.tl_pick_pos[j * nr + k];
             if (b.weight[pos] == w) {
                 b.sel_pos[ho + m] = pos;
+                b.sel_yz[ho + m] = b.yz[pos];
                 b.sel_row[ho + m] = b.tl_pick_row[j * nr + k];
                 ++m;
             }
@@ -505,8 +518,8 @@ struct Pick {
 
 // Best cluster on the row of segment `seg` for the predicted state.
 __device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, const KState& s, int64_t seg,
-                                            Pick& out, unsigned long long& ncand) {
-    const GridView g = grid_view(b, seg);
+                                            const SegHdr& h, Pick& out, unsigned long long& ncand) {
+    const GridView g = grid_view(b, seg, h);
     if (g.n == 0) return false;
     const float s00 = s.C[0] + K.vy, s01 = s.C[1], s11 = s.C[2] + K.vz;
     const float wy = K.nsig * __builtin_sqrtf(s00), wz = K.nsig * __builtin_sqrtf(s11);
@@ -523,7 +536,8 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, c
         const int q0 = g.bs[bz * g.ny + y0], q1 = g.bs[bz * g.ny + y1 + 1];
         for (int q = q0; q < q1; ++q) {
             const int64_t pos = g.rs + q;
-            const float r0 = b.ys[pos] - py, r1 = b.zs[pos] - pz;
+            const float2 c = b.yz[pos];
+            const float r0 = c.x - py, r1 = c.y - pz;
             ++ncand;
             if (!(__builtin_fabsf(r0) <= wy && __builtin_fabsf(r1) <= wz)) continue;
             const float w0 = a00 * r0 + a01 * r1;
@@ -620,8 +634,8 @@ __global__ void k_tracklet(Bufs b) {
         int32_t pm = pos0;
         for (int i = 0; i < m; ++i) pm = b.upc[pm];
         KState s;
-        const bool seeded = seed_from_chain(K, K.X[r0], b.ys[pos0], b.zs[pos0], K.X[r0 + m], b.ys[pm],
-                                            K.X[r0 + L - 1], b.ys[pe], b.zs[pe], s);
+        const float2 c0 = b.yz[pos0], cm = b.yz[pm], ce = b.yz[pe];
+        const bool seeded = seed_from_chain(K, K.X[r0], c0.x, c0.y, K.X[r0 + m], cm.x, K.X[r0 + L - 1], ce.x, ce.y, s);
         int cur = r0;
         bool ok = seeded;
         // stage 1
@@ -635,7 +649,8 @@ __global__ void k_tracklet(Bufs b) {
                     }
                     p = b.upc[p];
                 }
-                const Innov n = kf_innovation(s, b.ys[p], b.zs[p], K);
+                const float2 cp = b.yz[p];
+                const Innov n = kf_innovation(s, cp.x, cp.y, K);
                 kf_update(s, n);
             }
             st_chain += L;
@@ -645,12 +660,17 @@ __global__ void k_tracklet(Bufs b) {
             // stage 2
             cur = r0 + L - 1;
             int last = cur, miss = 0;
+            // the next row's grid header does not depend on the state: load it
+            // one row ahead so that its latency hides behind the propagation
+            SegHdr hn = load_hdr(b, seg0 + min(cur + 1, nr - 1));
             for (int r = cur + 1; r < nr && miss < K.max_miss; ++r) {
+                const SegHdr h = hn;
+                hn = load_hdr(b, seg0 + min(r + 1, nr - 1));
                 if (!kf_propagate(s, K.X[r - 1], K.X[r], K)) break;
                 cur = r;
                 ++st_rows;
                 Pick pk_;
-                if (pick_on_row(b, K, s, seg0 + r, pk_, st_cand)) {
+                if (pick_on_row(b, K, s, seg0 + r, h, pk_, st_cand)) {
                     kf_update(s, pk_.inn);
                     last = r;
                     miss = 0;
@@ -670,14 +690,17 @@ __global__ void k_tracklet(Bufs b) {
             }
             if (down_ok) {
                 miss = 0;
+                SegHdr hn3 = load_hdr(b, seg0 + last);
                 for (int r = last; r >= 0; --r) {
+                    const SegHdr h = hn3;
+                    hn3 = load_hdr(b, seg0 + max(r - 1, 0));
                     if (r != cur) {
                         if (!kf_propagate(s, K.X[cur], K.X[r], K)) break;
                         cur = r;
                     }
                     ++st_rows;
                     Pick pk_;
-                    if (pick_on_row(b, K, s, seg0 + r, pk_, st_cand)) {
+                    if (pick_on_row(b, K, s, seg0 + r, h, pk_, st_cand)) {
                         kf_update(s, pk_.inn);
                         b.tl_pick_pos[j * nr + nh] = pk_.pos;
                         b.tl_pick_row[j * nr + nh] = (uint8_t)r;
@@ -757,6 +780,7 @@ __global__ void k_refit(Bufs b) {
             for (int q = 0; q < n && ok; ++q) {
                 const int i = inward ? n - 1 - q : q;
                 const int target = b.sel_row[off + i];
+                const float2 c = b.sel_yz[off + i];  // issued before the propagation it waits behind
                 while (cur != target) {
                     const int nx = cur < target ? cur + 1 : cur - 1;
                     if (!kf_propagate(s, K.X[cur], K.X[nx], K)) {
@@ -767,8 +791,7 @@ __global__ void k_refit(Bufs b) {
                     ++st_rows;
                 }
                 if (!ok) break;
-                const int32_t pos = b.sel_pos[off + i];
-                const float my = b.ys[pos], mz = b.zs[pos];
+                const float my = c.x, mz = c.y;
                 const Innov inn = kf_innovation(s, my - ref_y, mz - ref_z, K);
                 ++st_hits;
                 if (inn.chi2 <= K.chi2_rej) {
@@ -857,13 +880,13 @@ __global__ void k_export_grid(Bufs b, int32_t* sorted_id, int32_t* bin_start, in
     for (int64_t i = i0; i < N; i += stride) sorted_id[i] = b.sid[i];
     for (int64_t i = i0; i < N + nseg + 1; i += stride) bin_start[i] = b.bin_start[i];
     for (int64_t s = i0; s < nseg; s += stride) {
-        ny[s] = b.gny[s];
-        nz[s] = b.gnz[s];
-        const float4 m = b.gmeta[s];
-        meta[4 * s] = m.x;
-        meta[4 * s + 1] = m.y;
-        meta[4 * s + 2] = m.z;
-        meta[4 * s + 3] = m.w;
+        const SegHdr h = b.hdr[s];
+        ny[s] = h.ny;
+        nz[s] = h.nz;
+        meta[4 * s] = h.ymin;
+        meta[4 * s + 1] = h.zmin;
+        meta[4 * s + 2] = h.iy;
+        meta[4 * s + 3] = h.iz;
     }
 }
 
