@@ -138,6 +138,8 @@ tpcca_status check_tuning(tpcca_ctx* ctx, const tpcca_tuning& t) {
     if (t.hits_per_bin < 1 || t.hits_per_bin > 64) return fail(ctx, TPCCA_E_ARG, "hits_per_bin must be in [1, 64]");
     if (!okb(t.block_links) || !okb(t.block_tracklet) || !okb(t.block_refit) || !okb(t.block_scan))
         return fail(ctx, TPCCA_E_ARG, "block sizes must be multiples of 64 in [64, 1024]");
+    if (t.block_tracklet > 256 || t.block_refit > 256)
+        return fail(ctx, TPCCA_E_ARG, "tracklet and refit blocks hold at most 256 threads");
     return TPCCA_OK;
 }
 

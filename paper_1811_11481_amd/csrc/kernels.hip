@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
 // One workgroup per (instance, row); one lane per hit of the row. Candidate
 // pairs (u on row+1, d on row-1) inside the windows; the minimum straight-line
 // deviation score wins, ties to the smaller (id_u, id_d).
-__global__ void k_links(Bufs b, int64_t seg0) {
+__global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0) {
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
     const int64_t seg = seg0 + blockIdx.x;
@@ -532,30 +532,63 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, c
     const int z0 = bin_of((pz - wz) - kBinMargin, g.zmin, g.iz, g.nz);
     const int z1 = bin_of((pz + wz) + kBinMargin, g.zmin, g.iz, g.nz);
     bool found = false;
+    auto consider = [&](int64_t pos, float2 c) {
+        const float r0 = c.x - py, r1 = c.y - pz;
+        ++ncand;
+        if (!(__builtin_fabsf(r0) <= wy && __builtin_fabsf(r1) <= wz)) return;
+        const float w0 = a00 * r0 + a01 * r1;
+        const float w1 = a01 * r0 + a11 * r1;
+        const float chi2 = r0 * w0 + r1 * w1;
+        if (!(chi2 <= K.chi2_pick)) return;
+        const int32_t id = b.sid[pos];
+        if (!found || chi2 < out.inn.chi2 || (chi2 == out.inn.chi2 && id < out.id)) {
+            found = true;
+            out.pos = (int32_t)pos;
+            out.id = id;
+            out.inn.a00 = a00;
+            out.inn.a01 = a01;
+            out.inn.a11 = a11;
+            out.inn.r0 = r0;
+            out.inn.r1 = r1;
+            out.inn.chi2 = chi2;
+        }
+    };
+    // bin-row ranges of the window: the first two rows' bounds are loaded together
+    const int q00 = g.bs[z0 * g.ny + y0], q01 = g.bs[z0 * g.ny + y1 + 1];
+    int q10 = 0, q11 = 0;
+    if (z1 > z0) {
+        q10 = g.bs[(z0 + 1) * g.ny + y0];
+        q11 = g.bs[(z0 + 1) * g.ny + y1 + 1];
+    }
     for (int bz = z0; bz <= z1; ++bz) {
-        const int q0 = g.bs[bz * g.ny + y0], q1 = g.bs[bz * g.ny + y1 + 1];
-        for (int q = q0; q < q1; ++q) {
-            const int64_t pos = g.rs + q;
-            const float2 c = b.yz[pos];
-            const float r0 = c.x - py, r1 = c.y - pz;
-            ++ncand;
-            if (!(__builtin_fabsf(r0) <= wy && __builtin_fabsf(r1) <= wz)) continue;
-            const float w0 = a00 * r0 + a01 * r1;
-            const float w1 = a01 * r0 + a11 * r1;
-            const float chi2 = r0 * w0 + r1 * w1;
-            if (!(chi2 <= K.chi2_pick)) continue;
-            const int32_t id = b.sid[pos];
-            if (!found || chi2 < out.inn.chi2 || (chi2 == out.inn.chi2 && id < out.id)) {
-                found = true;
-                out.pos = (int32_t)pos;
-                out.id = id;
-                out.inn.a00 = a00;
-                out.inn.a01 = a01;
-                out.inn.a11 = a11;
-                out.inn.r0 = r0;
-                out.inn.r1 = r1;
-                out.inn.chi2 = chi2;
-            }
+        int q0, q1;
+        if (bz == z0) {
+            q0 = q00;
+            q1 = q01;
+        } else if (bz == z0 + 1) {
+            q0 = q10;
+            q1 = q11;
+        } else {
+            q0 = g.bs[bz * g.ny + y0];
+            q1 = g.bs[bz * g.ny + y1 + 1];
+        }
+        int q = q0;
+        for (; q + 4 <= q1; q += 4) {  // four candidates per memory round trip
+            const float2 ca = b.yz[g.rs + q], cb = b.yz[g.rs + q + 1], cc = b.yz[g.rs + q + 2],
+                         cd = b.yz[g.rs + q + 3];
+            consider(g.rs + q, ca);
+            consider(g.rs + q + 1, cb);
+            consider(g.rs + q + 2, cc);
+            consider(g.rs + q + 3, cd);
+        }
+        if (q < q1) {
+            const int rem = q1 - q;
+            const float2 ca = b.yz[g.rs + q];
+            const float2 cb = rem > 1 ? b.yz[g.rs + q + 1] : ca;
+            const float2 cc = rem > 2 ? b.yz[g.rs + q + 2] : ca;
+            consider(g.rs + q, ca);
+            if (rem > 1) consider(g.rs + q + 1, cb);
+            if (rem > 2) consider(g.rs + q + 2, cc);
         }
     }
     return found;
@@ -603,7 +636,7 @@ __device__ __forceinline__ int lower_bound_inst(const int32_t* a, int64_t lo, in
 
 // One lane per start hit: seed, stage 1 (chain), stage 2 (outward), turn,
 // stage 3 (inward re-pick), weights.
-__global__ void k_tracklet(Bufs b) {
+__global__ __launch_bounds__(256) void k_tracklet(Bufs b) {
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
     const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
@@ -624,15 +657,18 @@ __global__ void k_tracklet(Bufs b) {
         }
         const int64_t seg0 = (int64_t)inst * nr;
         const int r0 = row_of(b.row_start, seg0, nr, pos0);
+        // walk the chain once, keeping its positions in the tracklet's pick
+        // buffer (overwritten by stage 3) so that later reads do not chase links
+        int32_t* chain = b.tl_pick_pos + j * nr;
         int L = 1;
         int32_t pe = pos0;
+        chain[0] = pos0;
         while (b.upc[pe] >= 0) {
             pe = b.upc[pe];
-            ++L;
+            chain[L++] = pe;
         }
         const int m = (L - 1) / 2;
-        int32_t pm = pos0;
-        for (int i = 0; i < m; ++i) pm = b.upc[pm];
+        const int32_t pm = chain[m];
         KState s;
         const float2 c0 = b.yz[pos0], cm = b.yz[pm], ce = b.yz[pe];
         const bool seeded = seed_from_chain(K, K.X[r0], c0.x, c0.y, K.X[r0 + m], cm.x, K.X[r0 + L - 1], ce.x, ce.y, s);
@@ -640,16 +676,14 @@ __global__ void k_tracklet(Bufs b) {
         bool ok = seeded;
         // stage 1
         if (ok) {
-            int32_t p = pos0;
+            float2 cn = b.yz[chain[0]];
             for (int i = 0; i < L; ++i) {
-                if (i > 0) {
-                    if (!kf_propagate(s, K.X[r0 + i - 1], K.X[r0 + i], K)) {
-                        ok = false;
-                        break;
-                    }
-                    p = b.upc[p];
+                const float2 cp = cn;
+                if (i + 1 < L) cn = b.yz[chain[i + 1]];  // next hit, loaded ahead
+                if (i > 0 && !kf_propagate(s, K.X[r0 + i - 1], K.X[r0 + i], K)) {
+                    ok = false;
+                    break;
                 }
-                const float2 cp = b.yz[p];
                 const Innov n = kf_innovation(s, cp.x, cp.y, K);
                 kf_update(s, n);
             }
@@ -741,7 +775,7 @@ __global__ void k_tracklet(Bufs b) {
 // One lane per selected tracklet: move to the outermost hit, then three
 // passes inward, outward, inward, each after a covariance reset; a hit is
 // used iff its predicted chi2 <= chi2_rej.
-__global__ void k_refit(Bufs b) {
+__global__ __launch_bounds__(256) void k_refit(Bufs b) {
     const DevConsts& K = *b.K;
     const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
