@@ -166,7 +166,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     size_t o_st = L.add(4 * cap_s), o_sti = L.add(4 * cap_s), o_so = L.add(4 * cap_s), o_sl = L.add(4 * cap_s);
     size_t o_tn = L.add(4 * cap_s), o_tt = L.add(4 * cap_s), o_tr = L.add(4 * cap_s), o_ts = L.add(80 * cap_s);
     size_t o_tpp = L.add(4 * cap_s * nr), o_tpr = L.add((size_t)cap_s * nr);
-    size_t o_w = L.add(4 * N);
+    size_t o_w = L.add(4 * N), o_own = L.add(4 * cap_s), o_ownm = L.add(32 * cap_s);
     size_t o_sel = L.add(4 * cap_sel), o_soff = L.add(4 * cap_sel), o_sn = L.add(4 * cap_sel);
     size_t o_spos = L.add(4 * N), o_syz = L.add(8 * N), o_srow = L.add(N), o_smask = L.add(N);
     size_t o_rs = L.add(80 * cap_sel), o_rc = L.add(4 * cap_sel), o_rn = L.add(4 * cap_sel),
@@ -196,6 +196,8 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     b.tl_pick_pos = (int32_t*)(base + o_tpp);
     b.tl_pick_row = (uint8_t*)(base + o_tpr);
     b.weight = (uint32_t*)(base + o_w);
+    b.tl_own = (int32_t*)(base + o_own);
+    b.tl_ownmask = (uint32_t*)(base + o_ownm);
     b.cap_sel = cap_sel;
     b.sel_tl = (int32_t*)(base + o_sel);
     b.sel_off = (int32_t*)(base + o_soff);
@@ -318,7 +320,7 @@ Launch make_launch(const tpcca_tuning& t) {
 }
 
 // The whole pipeline for instances [i0, i1) with clusters [c0, c1).
-void enqueue_range(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, int n_min,
+void enqueue_range(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, int n_min, int max_row,
                    hipStream_t st, tpcca_ctx* timing) {
     auto mark = [&](int k) {
         if (timing) hipEventRecord(timing->ev[k], st);
@@ -327,14 +329,14 @@ void enqueue_range(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, i
     mark(0);
     enqueue_grid(b, i0, i1, st);
     mark(1);
-    enqueue_links(b, L, i0, i1, st);
+    enqueue_links(b, L, i0, i1, max_row, st);
     mark(2);
     enqueue_clean_starts(b, L, i0, i1, c0, c1, st);
     mark(3);
     const int64_t ninst = i1 - i0;
     enqueue_tracklets(b, L, (c1 - c0) / 3 + ninst, st);
     mark(4);
-    enqueue_select(b, L, 0, st);
+    enqueue_select(b, L, (c1 - c0) / 3 + ninst, st);
     mark(5);
     enqueue_refit(b, L, (c1 - c0) / std::max(1, n_min) + ninst, st);
     mark(6);
@@ -381,12 +383,17 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
         for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
         ctx->events = true;
     }
+    const int64_t* rs = ctx->h_rowstart;
+    auto max_row = [&](int i0, int i1) {
+        int64_t m = 0;
+        for (int64_t g = (int64_t)i0 * nr; g < (int64_t)i1 * nr; ++g) m = std::max(m, rs[g + 1] - rs[g]);
+        return (int)m;
+    };
     if (!batched) {
         enqueue_reset(b, st);
-        const int64_t* rs = ctx->h_rowstart;
         for (int i = 0; i < in->n_inst; ++i)
-            enqueue_range(b, L, i, i + 1, rs[(int64_t)i * nr], rs[(int64_t)(i + 1) * nr], ctx->params.n_min, st,
-                          nullptr);
+            enqueue_range(b, L, i, i + 1, rs[(int64_t)i * nr], rs[(int64_t)(i + 1) * nr], ctx->params.n_min,
+                          max_row(i, i + 1), st, nullptr);
         enqueue_finish(b, st);
         HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipGetLastError());
@@ -395,7 +402,7 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
     }
     if (timing) {  // uncaptured, with stage events
         enqueue_reset(b, st);
-        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, st, ctx);
+        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, max_row(0, in->n_inst), st, ctx);
         enqueue_finish(b, st);
         hipEventRecord(ctx->ev[8], st);
         HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -425,7 +432,7 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
         }
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
         enqueue_reset(b, st);
-        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, st, nullptr);
+        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, max_row(0, in->n_inst), st, nullptr);
         enqueue_finish(b, st);
         hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
         hipError_t e = hipStreamEndCapture(st, &ctx->graph);
@@ -480,7 +487,7 @@ tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
     if (!t) return TPCCA_E_ARG;
     t->hits_per_bin = 2;
     t->block_links = 256;
-    t->block_tracklet = 128;
+    t->block_tracklet = 256;
     t->block_refit = 128;
     t->block_scan = 256;
     t->sort_seeds = 0;

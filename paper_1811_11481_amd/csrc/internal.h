@@ -78,6 +78,8 @@ struct Bufs {
     int32_t* tl_pick_pos;  // [cap_starts * n_rows], stage-3 order (rows descending)
     uint8_t* tl_pick_row;
     uint32_t* weight;    // [N] grid-position space
+    int32_t* tl_own;     // owned clusters per tracklet (0 if it has fewer than n_min hits)
+    uint32_t* tl_ownmask;  // [cap_starts * 8] bit k: pick k is owned
     // selection
     int64_t cap_sel;
     int32_t* sel_tl;
@@ -119,7 +121,7 @@ constexpr int kScanBlocks = 1024;
 void enqueue_reset(const Bufs& b, hipStream_t st);
 void enqueue_weights_clear(const Bufs& b, int64_t c0, int64_t c1, hipStream_t st);
 void enqueue_grid(const Bufs& b, int i0, int i1, hipStream_t st);
-void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, hipStream_t st);
+void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, int max_row, hipStream_t st);
 void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, hipStream_t st);
 void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);
 void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);

@@ -218,8 +218,11 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
 // ------------------------------------------------------------------ links
 // One workgroup per (instance, row); one lane per hit of the row. Candidate
 // pairs (u on row+1, d on row-1) inside the windows; the minimum straight-line
-// deviation score wins, ties to the smaller (id_u, id_d).
-__global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0) {
+// deviation score wins, ties to the smaller (id_u, id_d). When both adjacent
+// rows fit in `cap` clusters, their coordinates and bin starts are staged in
+// LDS once per workgroup and every candidate read is an LDS read.
+__global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int cap) {
+    extern __shared__ unsigned char smem[];
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
     const int64_t seg = seg0 + blockIdx.x;
@@ -234,6 +237,23 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0) {
     }
     const GridView gu = grid_view(b, seg + 1);
     const GridView gd = grid_view(b, seg - 1);
+    const int nbu = gu.ny * gu.nz, nbd = gd.ny * gd.nz;
+    const bool lds = cap > 0 && gu.n <= cap && gd.n <= cap;  // uniform over the workgroup
+    float2* su = reinterpret_cast<float2*>(smem);
+    float2* sd = su + cap;
+    int32_t* sbu = reinterpret_cast<int32_t*>(sd + cap);
+    int32_t* sbd = sbu + cap + 1;
+    if (lds) {
+        for (int i = threadIdx.x; i < gu.n; i += blockDim.x) su[i] = b.yz[gu.rs + i];
+        for (int i = threadIdx.x; i < gd.n; i += blockDim.x) sd[i] = b.yz[gd.rs + i];
+        for (int i = threadIdx.x; i <= nbu; i += blockDim.x) sbu[i] = gu.bs[i];
+        for (int i = threadIdx.x; i <= nbd; i += blockDim.x) sbd[i] = gd.bs[i];
+        __syncthreads();
+    }
+    const float2* cu = lds ? su : b.yz + gu.rs;
+    const float2* cd = lds ? sd : b.yz + gd.rs;
+    const int32_t* bsu = lds ? sbu : gu.bs;
+    const int32_t* bsd = lds ? sbd : gd.bs;
     const float wyu = K.wyu[r], wzu = K.wzu[r], wyd = K.wyd[r], wzd = K.wzd[r], tr = K.tr[r], smax = K.smax;
     unsigned long long n_links = 0, n_cu = 0, n_pairs = 0;
     for (int64_t p = a + threadIdx.x; p < e; p += blockDim.x) {
@@ -241,7 +261,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0) {
         const float yh = ph.x, zh = ph.y;
         bool found = false;
         float best = 0.0f;
-        int32_t bu = -1, bd = -1, bu_id = 0, bd_id = 0;
+        int32_t bu = -1, bd = -1;  // relative positions in rows r+1 and r-1
         if (gu.n > 0 && gd.n > 0) {
             const int uy0 = bin_of((yh - wyu) - kBinMargin, gu.ymin, gu.iy, gu.ny);
             const int uy1 = bin_of((yh + wyu) + kBinMargin, gu.ymin, gu.iy, gu.ny);
@@ -252,19 +272,16 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0) {
             const int dz0 = bin_of((zh - wzd) - kBinMargin, gd.zmin, gd.iz, gd.nz);
             const int dz1 = bin_of((zh + wzd) + kBinMargin, gd.zmin, gd.iz, gd.nz);
             for (int uz = uz0; uz <= uz1; ++uz) {
-                const int q0 = gu.bs[uz * gu.ny + uy0], q1 = gu.bs[uz * gu.ny + uy1 + 1];
+                const int q0 = bsu[uz * gu.ny + uy0], q1 = bsu[uz * gu.ny + uy1 + 1];
                 for (int q = q0; q < q1; ++q) {
-                    const int64_t u = gu.rs + q;
-                    const float2 pu = b.yz[u];
+                    const float2 pu = cu[q];
                     const float yu = pu.x, zu = pu.y;
                     if (!(__builtin_fabsf(yu - yh) <= wyu && __builtin_fabsf(zu - zh) <= wzu)) continue;
                     ++n_cu;
-                    int32_t uid = -1;
                     for (int dz = dz0; dz <= dz1; ++dz) {
-                        const int t0 = gd.bs[dz * gd.ny + dy0], t1 = gd.bs[dz * gd.ny + dy1 + 1];
+                        const int t0 = bsd[dz * gd.ny + dy0], t1 = bsd[dz * gd.ny + dy1 + 1];
                         for (int t = t0; t < t1; ++t) {
-                            const int64_t d = gd.rs + t;
-                            const float2 pd = b.yz[d];
+                            const float2 pd = cd[t];
                             const float yd = pd.x, zd = pd.y;
                             if (!(__builtin_fabsf(yd - yh) <= wyd && __builtin_fabsf(zd - zh) <= wzd)) continue;
                             ++n_pairs;
@@ -272,24 +289,25 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0) {
                             const float ez = (zd + (zu - zd) * tr) - zh;
                             const float sc = ey * ey + ez * ez;
                             if (!(sc <= smax)) continue;
-                            if (uid < 0) uid = b.sid[u];
-                            const int32_t did = b.sid[d];
-                            if (!found || sc < best ||
-                                (sc == best && (uid < bu_id || (uid == bu_id && did < bd_id)))) {
+                            bool take = !found || sc < best;
+                            if (!take && sc == best) {  // ids decide only exact ties
+                                const int32_t uid = b.sid[gu.rs + q], did = b.sid[gd.rs + t];
+                                const int32_t buid = b.sid[gu.rs + bu], bdid = b.sid[gd.rs + bd];
+                                take = uid < buid || (uid == buid && did < bdid);
+                            }
+                            if (take) {
                                 found = true;
                                 best = sc;
-                                bu = (int32_t)u;
-                                bd = (int32_t)d;
-                                bu_id = uid;
-                                bd_id = did;
+                                bu = q;
+                                bd = t;
                             }
                         }
                     }
                 }
             }
         }
-        b.up[p] = bu;
-        b.dn[p] = bd;
+        b.up[p] = found ? (int32_t)(gu.rs + bu) : -1;
+        b.dn[p] = found ? (int32_t)(gd.rs + bd) : -1;
         n_links += found ? 1 : 0;
     }
     if (K.stats) {
@@ -432,16 +450,8 @@ struct SelectOp {
         const int64_t e = begin() + (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
         return e < b.cap_starts ? e : b.cap_starts;
     }
-    __device__ int owned(int64_t j, int nh, uint32_t w) const {
-        const int nr = b.K->n_rows;
-        int c = 0;
-        for (int k = 0; k < nh; ++k) c += (b.weight[b.tl_pick_pos[j * nr + k]] == w) ? 1 : 0;
-        return c;
-    }
     __device__ unsigned long long value(int64_t j) const {
-        const int nh = b.tl_nhits[j];
-        if (nh < b.K->n_min) return 0ull;
-        const int own = owned(j, nh, packed_weight(nh, b.tl_tid[j]));
+        const int own = b.tl_own[j];
         return own >= b.K->n_min ? ((1ull << 32) | (unsigned long long)own) : 0ull;
     }
     __device__ void write(int64_t j, unsigned long long prefix, unsigned long long v) const {
@@ -454,14 +464,14 @@ struct SelectOp {
         }
         const int nr = b.K->n_rows;
         const int nh = b.tl_nhits[j];
-        const uint32_t w = packed_weight(nh, b.tl_tid[j]);
         b.sel_tl[si] = (int32_t)j;
         b.sel_off[si] = (int32_t)ho;
         b.sel_n[si] = own;
+        const uint32_t* mask = b.tl_ownmask + j * 8;
         int m = 0;
         for (int k = nh - 1; k >= 0; --k) {  // picks are stored rows-descending
-            const int32_t pos = b.tl_pick_pos[j * nr + k];
-            if (b.weight[pos] == w) {
+            if ((mask[k >> 5] >> (k & 31)) & 1u) {
+                const int32_t pos = b.tl_pick_pos[j * nr + k];
                 b.sel_pos[ho + m] = pos;
                 b.sel_yz[ho + m] = b.yz[pos];
                 b.sel_row[ho + m] = b.tl_pick_row[j * nr + k];
@@ -470,6 +480,33 @@ struct SelectOp {
         }
     }
 };
+
+// Owned picks of every tracklet of the current range: count and bitmask.
+__global__ void k_own(Bufs b) {
+    const int nr = b.K->n_rows, n_min = b.K->n_min;
+    const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
+    if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;
+    for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k0 < cnt; k0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = base + k0;
+        const int nh = b.tl_nhits[j];
+        uint32_t mk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int own = 0;
+        if (nh >= n_min) {
+            const uint32_t w = packed_weight(nh, b.tl_tid[j]);
+            for (int k = 0; k < nh; ++k) {
+                if (b.weight[b.tl_pick_pos[j * nr + k]] == w) {
+                    mk[k >> 5] |= 1u << (k & 31);
+                    ++own;
+                }
+            }
+        }
+        b.tl_own[j] = own;
+        uint32_t* dst = b.tl_ownmask + j * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dst[q] = mk[q];
+    }
+}
 
 // Output tracks, over the current range of selected tracklets.
 struct TrackOp {
@@ -512,7 +549,6 @@ struct TrackOp {
 // ------------------------------------------------------------------ tracklets
 struct Pick {
     int32_t pos;
-    int32_t id;
     Innov inn;
 };
 
@@ -540,11 +576,10 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, c
         const float w1 = a01 * r0 + a11 * r1;
         const float chi2 = r0 * w0 + r1 * w1;
         if (!(chi2 <= K.chi2_pick)) return;
-        const int32_t id = b.sid[pos];
-        if (!found || chi2 < out.inn.chi2 || (chi2 == out.inn.chi2 && id < out.id)) {
+        // cluster ids decide only exact chi2 ties: load them only then
+        if (!found || chi2 < out.inn.chi2 || (chi2 == out.inn.chi2 && b.sid[pos] < b.sid[out.pos])) {
             found = true;
             out.pos = (int32_t)pos;
-            out.id = id;
             out.inn.a00 = a00;
             out.inn.a01 = a01;
             out.inn.a11 = a11;
@@ -811,10 +846,22 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
         for (int pass = 0; pass < 3 && ok; ++pass) {
             kf_reset(s, K);
             const bool inward = (pass != 1);
+            // the next cluster's row, coordinates and mask are loaded one
+            // iteration ahead, so no row step waits on memory
+            int i_n = inward ? n - 1 : 0;
+            int t_n = b.sel_row[off + i_n];
+            float2 c_n = b.sel_yz[off + i_n];
+            uint8_t m_n = pass ? b.sel_mask[off + i_n] : (uint8_t)0;
             for (int q = 0; q < n && ok; ++q) {
-                const int i = inward ? n - 1 - q : q;
-                const int target = b.sel_row[off + i];
-                const float2 c = b.sel_yz[off + i];  // issued before the propagation it waits behind
+                const int i = i_n, target = t_n;
+                const float2 c = c_n;
+                const uint8_t mprev = m_n;
+                if (q + 1 < n) {
+                    i_n = inward ? n - 2 - q : q + 1;
+                    t_n = b.sel_row[off + i_n];
+                    c_n = b.sel_yz[off + i_n];
+                    m_n = pass ? b.sel_mask[off + i_n] : (uint8_t)0;
+                }
                 while (cur != target) {
                     const int nx = cur < target ? cur + 1 : cur - 1;
                     if (!kf_propagate(s, K.X[cur], K.X[nx], K)) {
@@ -834,7 +881,7 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
                     s.p[1] = s.p[1] + (ref_z - mz);
                     ref_y = my;
                     ref_z = mz;
-                    b.sel_mask[off + i] = (uint8_t)(b.sel_mask[off + i] | (1u << pass));
+                    b.sel_mask[off + i] = (uint8_t)(mprev | (1u << pass));
                     if (pass == 2) {
                         chi2sum = chi2sum + inn.chi2;
                         ++nacc;
@@ -1012,10 +1059,17 @@ void enqueue_grid(const Bufs& b, int i0, int i1, hipStream_t st) {
     hipLaunchKernelGGL(k_grid<kLargeRow>, dim3((unsigned)nseg), dim3(256), 0, st, b, seg0);
 }
 
-void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, hipStream_t st) {
+void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, int max_row, hipStream_t st) {
     const int64_t seg0 = (int64_t)i0 * b.n_rows, nseg = (int64_t)(i1 - i0) * b.n_rows;
     if (nseg <= 0) return;
-    hipLaunchKernelGGL(k_links, dim3((unsigned)nseg), dim3(L.block_links), 0, st, b, seg0);
+    // LDS: two rows of (y, z) and two bin-start arrays (bins <= clusters)
+    int cap = max_row < 1 ? 1 : max_row;
+    size_t bytes = (size_t)cap * 2 * sizeof(float2) + (size_t)(cap + 1) * 2 * sizeof(int32_t);
+    if (bytes > 64 * 1024) {
+        cap = 0;
+        bytes = 0;
+    }
+    hipLaunchKernelGGL(k_links, dim3((unsigned)nseg), dim3(L.block_links), bytes, st, b, seg0, cap);
 }
 
 void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, hipStream_t st) {
@@ -1029,7 +1083,7 @@ void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_
 }
 
 void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
-    (void)bound;
+    hipLaunchKernelGGL(k_own, dim3(grid_for(bound, 256, 16384)), dim3(256), 0, st, b);
     SelectOp op{b};
     launch_scan(op, b, SL_SEL, L.block_scan, st);
 }
