@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick tiling with tpcca_autotune before timing")
+    ap.add_argument("--extra", default="C2x8", help="comma-separated extra workloads timed in the batched form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -161,6 +162,27 @@ def main():
                 "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": stages[dom]["ms"]}
     print("[bench] stages (ms): %s" % {k: v["ms"] for k, v in stages.items()}, file=sys.stderr, flush=True)
 
+    extra = {}
+    for wl in [w for w in args.extra.split(",") if w and w != args.workload]:
+        ecs = synth.generate(wl)
+        edc = DeviceClusters.from_host(ecs)
+        eout = trk.alloc_tracks(edc)
+        for _ in range(max(1, args.warmup)):
+            trk.track(edc, eout, batched=True)
+        torch.cuda.synchronize()
+        e0 = time.perf_counter()
+        ek = max(3, args.steps // 2)
+        for _ in range(ek):
+            trk.track(edc, eout, batched=True)
+        torch.cuda.synchronize()
+        ems = (time.perf_counter() - e0) / ek * 1e3
+        extra[wl] = {"workload": WORKLOADS[wl], "n_clusters": ecs.n_clusters, "n_instances": ecs.n_inst,
+                     "ms_per_step": round(ems, 4), "clusters_per_s": round(ecs.n_clusters / (ems * 1e-3), 1),
+                     "tracks_per_s": round(eout.n_tracks / (ems * 1e-3), 1), "n_tracks": eout.n_tracks,
+                     "steps": ek}
+        print("[bench] %s batched: %.3f ms/step" % (wl, ems), file=sys.stderr, flush=True)
+        del edc, eout
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only
@@ -198,6 +220,7 @@ def main():
         "plain_ms_per_step": round(plain_ms, 4) if plain_ms else None,
         "batched_speedup_vs_plain": round(plain_ms / ms, 3) if plain_ms else None,
         "stages": stages,
+        "extra_workloads": extra,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
