@@ -61,6 +61,31 @@ def byte_model(stage: str, st: dict, n_clusters: int, n_seg: int, hits_per_bin: 
     return 0
 
 
+def kernel_source_sha256() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1811_11481_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(src, "*.hip")) + glob.glob(os.path.join(src, "*.h"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary (FETCH_SIZE
+    and WRITE_SIZE scaled by a copy of known size), or None when there is none
+    for this kernel and workload or the kernels have changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel.replace("k_", ""), workload))
+    if not os.path.exists(path):
+        path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_sha256") != kernel_source_sha256():
+        return None
+    return int(d["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,7 +183,9 @@ def main():
     dom_bytes = stages[dom]["alg_bytes"]
     achieved = dom_bytes / (stages[dom]["ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic("k_" + dom.rstrip("s") if dom == "tracklets" else "k_" + dom,
+                                            args.workload),
                 "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": stages[dom]["ms"]}
     print("[bench] stages (ms): %s" % {k: v["ms"] for k, v in stages.items()}, file=sys.stderr, flush=True)
 
