@@ -89,6 +89,9 @@ def lib():
         L.orc_refit.restype = i32
         L.orc_refit.argtypes = [ctypes.POINTER(Params), i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_replay_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 10
+        L.orc_map_eval.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.orc_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+        L.orc_refit_frozen_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 11
         _lib = L
     return _lib
 
@@ -282,3 +285,104 @@ def replay_f64(st0, row0, hit_start, hit_rows, ys, zs, masks, params=None):
     lib().orc_replay_f64(ctypes.byref(p), n, _ptr(st0), _ptr(row0), _ptr(hit_start), _ptr(hit_rows), _ptr(ys),
                          _ptr(zs), _ptr(masks), _ptr(out), _ptr(chi2), _ptr(ok))
     return ok.astype(bool), out, chi2
+
+
+# ------------------------------------------------------- differentiable refit
+MAP_SHAPE = (3, 16, 16, 32)  # components (delta r, delta r*phi, delta z) x r x phi x z
+MAP_SIZE = 3 * 16 * 16 * 32
+
+
+def map_eval(coef, r, phi, z):
+    """Map components (n, 3) at global (r, phi, z)."""
+    coef = np.ascontiguousarray(np.asarray(coef, np.float64).reshape(-1))
+    r, phi, z = (np.ascontiguousarray(np.asarray(v, np.float64).reshape(-1)) for v in (r, phi, z))
+    out = np.zeros((len(r), 3), np.float64)
+    lib().orc_map_eval(_ptr(coef), len(r), _ptr(r), _ptr(phi), _ptr(z), _ptr(out))
+    return out
+
+
+def correct(coef, alpha, x, y, z):
+    coef = np.ascontiguousarray(np.asarray(coef, np.float64).reshape(-1))
+    a, x, y, z = (np.ascontiguousarray(np.asarray(v, np.float64).reshape(-1)) for v in (alpha, x, y, z))
+    yc, zc = np.zeros(len(y)), np.zeros(len(y))
+    lib().orc_correct(_ptr(coef), len(y), _ptr(a), _ptr(x), _ptr(y), _ptr(z), _ptr(yc), _ptr(zc))
+    return yc, zc
+
+
+def refit_frozen_f64(st0, row0, alpha, hit_start, hit_rows, ys, zs, masks, coef=None, params=None):
+    """Per-track pass-3 chi2 (FP64) of the refit with frozen masks on corrected clusters."""
+    p = params if params is not None else default_params()
+    n = len(row0)
+    st0 = np.ascontiguousarray(np.asarray(st0, np.float64).reshape(n, 20))
+    row0 = np.ascontiguousarray(np.asarray(row0, np.int32))
+    alpha = np.ascontiguousarray(np.asarray(alpha, np.float64))
+    hit_start = np.ascontiguousarray(np.asarray(hit_start, np.int64))
+    hit_rows = np.ascontiguousarray(np.asarray(hit_rows, np.int32))
+    ys = np.ascontiguousarray(np.asarray(ys, np.float64))
+    zs = np.ascontiguousarray(np.asarray(zs, np.float64))
+    masks = np.ascontiguousarray(np.asarray(masks, np.uint8))
+    cf = None if coef is None else np.ascontiguousarray(np.asarray(coef, np.float64).reshape(-1))
+    chi2 = np.zeros(n)
+    ok = np.zeros(n, np.int32)
+    lib().orc_refit_frozen_f64(ctypes.byref(p), n, _ptr(st0), _ptr(row0), _ptr(alpha), _ptr(hit_start),
+                               _ptr(hit_rows), _ptr(ys), _ptr(zs), _ptr(masks), _ptr(cf), _ptr(chi2), _ptr(ok))
+    return ok.astype(bool), chi2
+
+
+def refit_inputs(res: OracleResult, cs, only_ok: bool = True):
+    """Inputs of the frozen-mask refit for the selected tracks of an oracle run:
+    start state (tracklet state), its row, sector angle, hit rows/coordinates and
+    the accept masks the refit took (pass p in bit p)."""
+    status = res.sel_status.astype(bool) if only_ok else np.ones(len(res.sel_tl), bool)
+    idx = np.nonzero(status)[0]
+    hs = res.sel_hit_start
+    lens = (hs[idx + 1] - hs[idx]).astype(np.int64)
+    hit_start = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    pos = np.concatenate([np.arange(hs[i], hs[i + 1]) for i in idx]) if len(idx) else np.zeros(0, np.int64)
+    hits = res.sel_hit[pos]
+    seg = np.searchsorted(cs.row_start, hits, side="right") - 1
+    rows = (seg % res.n_rows).astype(np.int32)
+    inst = res.start_inst[res.sel_tl[idx]]
+    sector = cs.inst_sector[inst]
+    alpha = ((sector % 18) + 0.5) * (20.0 * np.pi / 180.0)
+    return dict(st0=res.tl_state[res.sel_tl[idx]].astype(np.float64), row0=res.tl_row[res.sel_tl[idx]],
+                alpha=alpha, hit_start=hit_start, hit_rows=rows, hit_id=hits.astype(np.int32),
+                ys=cs.y[hits].astype(np.float64), zs=cs.z[hits].astype(np.float64), masks=res.sel_mask[pos],
+                inst=inst.astype(np.int32), sel=idx)
+
+
+def frozen_chi2_grad_fd(inp, coef=None, coef_index=(), h_param=(1e-4, 1e-4, 1e-6, 1e-6, 1e-5), h_coef=1e-4,
+                        params=None):
+    """Reference gradient of the frozen-mask refit chi2 by central differences of
+    the FP64 function: d chi2_t / d params0_t (n x 5, each track's chi2 depends
+    only on its own start state, so one perturbation serves all tracks) and
+    d (sum_t chi2_t) / d coef[k] for the flat coefficient indices in coef_index."""
+    base = np.zeros(MAP_SIZE) if coef is None else np.asarray(coef, np.float64).reshape(-1).copy()
+    use_map = coef is not None or len(coef_index) > 0
+
+    def f(st0, cf):
+        ok, chi2 = refit_frozen_f64(st0, inp["row0"], inp["alpha"], inp["hit_start"], inp["hit_rows"], inp["ys"],
+                                    inp["zs"], inp["masks"], cf if use_map else None, params)
+        return ok, chi2
+
+    st0 = np.asarray(inp["st0"], np.float64)
+    gp = np.zeros((len(st0), 5))
+    ok_all = f(st0, base)[0]
+    for k in range(5):
+        sp, sm = st0.copy(), st0.copy()
+        sp[:, k] += h_param[k]
+        sm[:, k] -= h_param[k]
+        okp, cp = f(sp, base)
+        okm, cm = f(sm, base)
+        ok_all &= okp & okm
+        gp[:, k] = (cp - cm) / (2.0 * h_param[k])
+    gc = np.zeros(len(coef_index))
+    for j, k in enumerate(coef_index):
+        cpl, cmi = base.copy(), base.copy()
+        cpl[k] += h_coef
+        cmi[k] -= h_coef
+        okp, cp = f(st0, cpl)
+        okm, cm = f(st0, cmi)
+        ok_all &= okp & okm
+        gc[j] = (cp[okp & okm].sum() - cm[okp & okm].sum()) / (2.0 * h_coef)
+    return ok_all, gp, gc

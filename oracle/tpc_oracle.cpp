@@ -972,3 +972,115 @@ void orc_replay_f64(const orc_params* p, int64_t n_tracks, const double* st0, co
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Differentiable refit: a smooth space-charge correction map and the refit with
+// frozen accept masks as a function of it (the paper applies calibration
+// corrections between seeding and fitting, Sections 1 and 4).
+//
+// Map: three components (delta r, delta r*phi, delta z) [cm], each a tricubic
+// uniform B-spline with 16 (r) x 16 (phi, periodic) x 32 (z) coefficients,
+// coefficient layout [comp][ir][iphi][iz]. Knots: r_k = 84 + (k - 1) * 168/13,
+// phi_k = k * 2 pi / 16, z_k = -252 + (k - 1) * 504/29, so the data range maps to
+// u in [1, 14) in r and [1, 30) in z and no index is ever clamped.
+namespace {
+constexpr int kMapNr = 16, kMapNphi = 16, kMapNz = 32;
+
+void bspline_basis(double t, double w[4]) {
+    const double t2 = t * t, t3 = t2 * t, s = 1.0 - t;
+    w[0] = s * s * s / 6.0;
+    w[1] = (3.0 * t3 - 6.0 * t2 + 4.0) / 6.0;
+    w[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) / 6.0;
+    w[3] = t3 / 6.0;
+}
+
+struct MapCell {
+    int ir, iphi, iz;  // index of the first of the 4 coefficients per axis
+    double wr[4], wphi[4], wz[4];
+};
+
+MapCell map_cell(double r, double phi, double z) {
+    const double pi2 = 2.0 * 3.14159265358979323846;
+    MapCell c;
+    double ur = 1.0 + (r - 84.0) / (168.0 / 13.0);
+    double uz = 1.0 + (z + 252.0) / (504.0 / 29.0);
+    ur = std::min(std::max(ur, 1.0), 14.0 - 1e-9);
+    uz = std::min(std::max(uz, 1.0), 30.0 - 1e-9);
+    double ph = std::fmod(phi, pi2);
+    if (ph < 0) ph += pi2;
+    const double up = ph / (pi2 / kMapNphi);
+    const int ir = (int)std::floor(ur), iz = (int)std::floor(uz), ip = (int)std::floor(up);
+    bspline_basis(ur - ir, c.wr);
+    bspline_basis(uz - iz, c.wz);
+    bspline_basis(up - ip, c.wphi);
+    c.ir = ir - 1;
+    c.iz = iz - 1;
+    c.iphi = ip - 1;
+    return c;
+}
+
+inline int64_t map_index(int comp, int ir, int iphi, int iz) {
+    iphi = ((iphi % kMapNphi) + kMapNphi) % kMapNphi;
+    return (((int64_t)comp * kMapNr + ir) * kMapNphi + iphi) * kMapNz + iz;
+}
+
+double map_value(const double* coef, int comp, const MapCell& c) {
+    double v = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int d = 0; d < 4; ++d)
+                v += c.wr[a] * c.wphi[b] * c.wz[d] * coef[map_index(comp, c.ir + a, c.iphi + b, c.iz + d)];
+    return v;
+}
+
+// Cluster on the row plane x with local (y, z) in a sector of angle alpha,
+// corrected by the map inside its pad-row plane.
+void correct_cluster(const double* coef, double alpha, double x, double y, double z, double* yc, double* zc) {
+    const double r = std::sqrt(x * x + y * y);
+    const double phi = alpha + std::atan2(y, x);
+    const MapCell c = map_cell(r, phi, z);
+    const double dr = map_value(coef, 0, c), drphi = map_value(coef, 1, c), dz = map_value(coef, 2, c);
+    *yc = y - (dr * y + drphi * x) / r;
+    *zc = z - dz;
+}
+}  // namespace
+
+extern "C" {
+
+void orc_map_eval(const double* coef, int64_t n, const double* r, const double* phi, const double* z, double* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        const MapCell c = map_cell(r[i], phi[i], z[i]);
+        for (int comp = 0; comp < 3; ++comp) out[3 * i + comp] = map_value(coef, comp, c);
+    }
+}
+
+void orc_correct(const double* coef, int64_t n, const double* alpha, const double* x, const double* y,
+                 const double* z, double* yc, double* zc) {
+    for (int64_t i = 0; i < n; ++i) correct_cluster(coef, alpha[i], x[i], y[i], z[i], yc + i, zc + i);
+}
+
+// Pass-3 chi2 of the three-pass refit with frozen accept masks, in FP64, on
+// clusters corrected by `coef` (NULL: uncorrected), per track.
+void orc_refit_frozen_f64(const orc_params* p, int64_t n_tracks, const double* st0, const int32_t* row0,
+                          const double* alpha, const int64_t* hit_start, const int32_t* hit_rows, const double* ys,
+                          const double* zs, const uint8_t* masks, const double* coef, double* chi2_out,
+                          int32_t* ok_out) {
+    Consts<double> k(*p);
+    for (int64_t t = 0; t < n_tracks; ++t) {
+        State<double> s;
+        load_state(st0 + 20 * t, s);
+        const int64_t a = hit_start[t];
+        const int n = (int)(hit_start[t + 1] - a);
+        std::vector<double> yc(n), zc(n);
+        for (int i = 0; i < n; ++i) {
+            if (coef) correct_cluster(coef, alpha[t], k.X[hit_rows[a + i]], ys[a + i], zs[a + i], &yc[i], &zc[i]);
+            else { yc[i] = ys[a + i]; zc[i] = zs[a + i]; }
+        }
+        std::vector<uint8_t> m(n);
+        RefitOut<double> o = refit(k, s, row0[t], n, hit_rows + a, yc.data(), zc.data(), m.data(), masks + a);
+        ok_out[t] = o.ok ? 1 : 0;
+        chi2_out[t] = o.ok ? o.chi2 : 0.0;
+    }
+}
+
+}  // extern "C"

@@ -17,6 +17,9 @@ Named workloads (seed = 1000 * config + event):
   j mod 36 with round(exp(U(ln 50, ln 2000))) helices, 1 % noise.
 * ``C2x8`` eight central events (seeds 2000..2007 law, one generator call) in
   288 instances.
+* ``C5``  twelve central events whose clusters are displaced by a smooth
+  synthetic space-charge map (amplitude 0.5 cm) before the smear: the input
+  of the differentiable refit.
 
 Common law: pT exponential with mean 0.5 GeV truncated (resampled) to
 [0.1, 10] GeV, random charge, Gaussian smear sigma_y = sigma_z = 0.1 cm, one
@@ -63,6 +66,7 @@ class _Config(ctypes.Structure):
         ("ex_tanl", ctypes.c_void_p),
         ("ex_phi0", ctypes.c_void_p),
         ("ex_q", ctypes.c_void_p),
+        ("distort", ctypes.c_int32),
     ]
 
 
@@ -140,7 +144,7 @@ class ClusterSet:
 
 def generate_raw(mode, n_units, unit_ntracks, unit_sector=None, *, bz=0.5, pt_mean=0.5, pt_min=0.1,
                  pt_max=10.0, eta_max=0.9, sec_frac=0.0, sec_rmax=50.0, noise_frac=0.0,
-                 sigma=0.1, zshift_max=0.0, shuffle=True, seed=0, explicit=None,
+                 sigma=0.1, zshift_max=0.0, shuffle=True, seed=0, explicit=None, distort=False,
                  name="") -> ClusterSet:
     lib = _load()
     cfg = _Config()
@@ -154,6 +158,7 @@ def generate_raw(mode, n_units, unit_ntracks, unit_sector=None, *, bz=0.5, pt_me
     cfg.eta_max, cfg.sec_frac, cfg.sec_rmax = eta_max, sec_frac, sec_rmax
     cfg.noise_frac, cfg.sigma_y, cfg.sigma_z = noise_frac, sigma, sigma
     cfg.zshift_max, cfg.shuffle, cfg.seed = zshift_max, int(shuffle), seed
+    cfg.distort = int(bool(distort))
     keep = [nt, sec]
     if explicit is not None:
         cols = [np.ascontiguousarray(np.asarray(explicit[k], dtype=np.float64))
@@ -185,7 +190,7 @@ def generate_raw(mode, n_units, unit_ntracks, unit_sector=None, *, bz=0.5, pt_me
 
 def generate(config: str, event: int = 0) -> ClusterSet:
     """One of the named workloads, seeded with 1000 * config + event."""
-    cfgno = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C2x8": 2}[config]
+    cfgno = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C2x8": 2, "C5": 5}[config]
     seed = 1000 * cfgno + event
     if config == "C1":
         return generate_raw(0, 1, [200], [0], noise_frac=0.01, seed=seed, name="C1")
@@ -193,6 +198,9 @@ def generate(config: str, event: int = 0) -> ClusterSet:
         return generate_raw(1, 1, [8000], sec_frac=0.1, noise_frac=0.02, seed=seed, name="C2")
     if config == "C2x8":
         return generate_raw(1, 8, [8000] * 8, sec_frac=0.1, noise_frac=0.02, seed=seed, name="C2x8")
+    if config == "C5":
+        # twelve central events with the synthetic space-charge displacement
+        return generate_raw(1, 12, [8000] * 12, sec_frac=0.1, noise_frac=0.02, seed=seed, distort=True, name="C5")
     if config == "C3":
         rng = np.random.default_rng(seed)
         mult = np.rint(rng.exponential(800.0, size=100)).astype(np.int32)

@@ -171,6 +171,15 @@ void trace(const Helix& h, double bz, std::vector<Hit>& out, int only_phi_sector
     std::sort(out.begin(), out.end(), [](const Hit& a, const Hit& b) { return a.tau < b.tau; });
 }
 
+// Smooth synthetic space-charge displacement (cm) at global (r, phi, z):
+// components along r, along r*phi and along z, amplitude <= 0.5 cm.
+void true_distortion(double r, double phi, double z, double* dr, double* drphi, double* dz) {
+    const double a = kPi * (r - 85.0) / 166.0, zz = z / kDrift;
+    *dr = 0.5 * std::sin(a) * (0.6 + 0.4 * std::cos(phi)) * (1.0 - zz * zz);
+    *drphi = 0.3 * std::cos(2.0 * a) * std::sin(2.0 * phi) * zz;
+    *dz = 0.2 * std::sin(kPi * zz) * std::cos(a);
+}
+
 double sample_pt(Rng& rng, double mean, double lo, double hi) {
     // Exponential law truncated to [lo, hi] by resampling.
     for (;;) {
@@ -214,6 +223,9 @@ typedef struct {
     const double* ex_vx; const double* ex_vy; const double* ex_vz;
     const double* ex_pt; const double* ex_tanl; const double* ex_phi0;
     const int32_t* ex_q;
+    // 1: displace every cluster by the smooth "true" space-charge map below
+    // (before the smear), keeping it on its pad-row plane
+    int32_t distort;
 } syn_config;
 
 typedef struct {
@@ -318,8 +330,17 @@ syn_result* syn_generate(const syn_config* cfg) {
                 inst = 36 * track_unit[t] + h.sector;
             }
             double side = h.sector < 18 ? 1.0 : -1.0;
-            double y = h.y + cfg->sigma_y * rng.normal();
-            double z = h.z + cfg->sigma_z * rng.normal() - side * track_dz[t];
+            double yt = h.y, zt = h.z;
+            if (cfg->distort) {
+                const double X = row_x(h.row), r = std::hypot(X, h.y);
+                const double phi = ((h.sector % 18) + 0.5) * 20.0 * kPi / 180.0 + std::atan2(h.y, X);
+                double dr, drphi, dz;
+                true_distortion(r, phi, h.z, &dr, &drphi, &dz);
+                yt += (dr * h.y + drphi * X) / r;  // local-y component of the displacement
+                zt += dz;
+            }
+            double y = yt + cfg->sigma_y * rng.normal();
+            double z = zt + cfg->sigma_z * rng.normal() - side * track_dz[t];
             cls.push_back({inst, h.row, (int32_t)t, (float)y, (float)z});
         }
     }

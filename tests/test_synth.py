@@ -56,3 +56,24 @@ def test_generator_is_seeded():
     c = synth.generate("C1", event=1)
     assert np.array_equal(a.y, b.y) and np.array_equal(a.z, b.z)
     assert a.n_clusters != c.n_clusters or not np.array_equal(a.y, c.y)
+
+
+def test_distortion_displaces_clusters_by_the_stated_field():
+    """Same seed with and without the space-charge displacement: the clusters
+    move by the local-y and z components of the stated smooth field."""
+    a = synth.generate_raw(0, 1, [200], [0], noise_frac=0.0, seed=7, shuffle=False)
+    b = synth.generate_raw(0, 1, [200], [0], noise_frac=0.0, seed=7, shuffle=False, distort=True)
+    assert np.array_equal(a.label, b.label) and np.array_equal(a.row, b.row)
+    x = synth.row_plane_x(a.row)
+    y = a.y.astype(np.float64)
+    z = a.z.astype(np.float64)
+    r = np.hypot(x, y)
+    phi = 0.5 * 20.0 * np.pi / 180.0 + np.arctan2(y, x)
+    ang, zz = np.pi * (r - 85.0) / 166.0, z / 250.0
+    dr = 0.5 * np.sin(ang) * (0.6 + 0.4 * np.cos(phi)) * (1.0 - zz * zz)
+    drphi = 0.3 * np.cos(2.0 * ang) * np.sin(2.0 * phi) * zz
+    dz = 0.2 * np.sin(np.pi * zz) * np.cos(ang)
+    # evaluated at the smeared position: error ~ field gradient x smear
+    assert np.abs((b.y - a.y) - (dr * y + drphi * x) / r).max() < 3e-3
+    assert np.abs((b.z - a.z) - dz).max() < 3e-3
+    assert np.abs(b.z - a.z).max() > 0.1
