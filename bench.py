@@ -37,6 +37,8 @@ WORKLOADS = {
     "C3": "continuous-readout slice: 100 collisions x Exp(800) tracks, drift shift 0-250 cm, 2% noise",
     "C4": "256 sector instances, log-uniform 50-2000 helices each, 1% noise",
     "C1": "one sector, 200 helices, 1% noise",
+    "C5": "twelve central Pb-Pb-like events (432 sector instances) with a smooth synthetic space-charge "
+          "displacement (amplitude 0.5 cm) applied before the smear",
 }
 
 
@@ -86,6 +88,43 @@ def measured_traffic(kernel: str, workload: str):
     return int(d["traffic_bytes_per_launch"])
 
 
+def diff_leg(args, torch, np, synth):
+    """Differentiable refit: chi2 of the frozen-mask three-pass refit of the
+    first tracks found in C5, as a function of the start states and a
+    correction map, forward and reverse sweep (binary32 and binary64 adjoint)."""
+    from paper_1811_11481_amd import FLAG_ADJOINT_F64, DeviceClusters, RefitSet, Tracker, default_params
+
+    cs = synth.generate("C5")
+    dc = DeviceClusters.from_host(cs)
+    trk = Tracker()
+    out = trk.track(dc, batched=True)
+    rs = RefitSet.from_tracker(trk).head(args.diff_tracks)
+    coef = (0.1 * torch.randn((3, 16, 16, 32), generator=torch.Generator().manual_seed(5))).float().cuda()
+    w = torch.ones(rs.n_tracks, dtype=torch.float32, device="cuda")
+    res = {"workload": "C5: " + WORKLOADS["C5"], "n_clusters": cs.n_clusters, "n_tracks_found": out.n_tracks,
+           "n_tracks": rs.n_tracks, "n_hits": rs.n_hits, "map": "random smooth B-spline map, sigma 0.1 cm"}
+    for name, flags in (("f32", 0), ("f64", FLAG_ADJOINT_F64)):
+        t = Tracker(params=default_params(flags=flags)) if flags else trk
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        fw, bw = [], []
+        for k in range(args.warmup + max(3, args.steps // 2)):
+            ev[0].record()
+            t.refit_forward(dc, rs, coef=coef)
+            ev[1].record()
+            t.refit_backward(w)
+            ev[2].record()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                fw.append(ev[0].elapsed_time(ev[1]))
+                bw.append(ev[1].elapsed_time(ev[2]))
+        f, b = statistics.median(fw), statistics.median(bw)
+        res[name] = {"fwd_ms": round(f, 4), "bwd_ms": round(b, 4),
+                     "tracks_per_s_fwd_bwd": round(rs.n_tracks / ((f + b) * 1e-3), 1)}
+        print("[bench] differentiable refit %s: fwd %.3f ms, bwd %.3f ms (%d tracks)" % (name, f, b, rs.n_tracks),
+              file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +136,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick tiling with tpcca_autotune before timing")
     ap.add_argument("--extra", default="C2x8", help="comma-separated extra workloads timed in the batched form")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiable-refit leg (C5)")
+    ap.add_argument("--diff-tracks", type=int, default=100000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -210,6 +251,10 @@ def main():
         print("[bench] %s batched: %.3f ms/step" % (wl, ems), file=sys.stderr, flush=True)
         del edc, eout
 
+    diff = None
+    if not args.no_diff:
+        diff = diff_leg(args, torch, np, synth)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only
@@ -250,6 +295,7 @@ def main():
         "extra_workloads": extra,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "differentiable_refit": diff,
     }
     print(json.dumps(line), flush=True)
 

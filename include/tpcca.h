@@ -182,6 +182,66 @@ tpcca_status tpcca_get_stats(tpcca_ctx* ctx, tpcca_stats* out); /* host out; syn
  * context was created with TPCCA_FLAG_TIMING (the batched form then runs without graph capture). */
 tpcca_status tpcca_get_stage_times(tpcca_ctx* ctx, float* ms8);
 
+/* ---- Differentiable refit ----
+ * The paper applies calibration corrections to the clusters between seeding
+ * and the final fit (Sections 1 and 4). Here the chi2 of the three-pass refit
+ * (Section 3) with FROZEN accept masks is a function of each track's start
+ * state and of a smooth space-charge correction map; tpcca_refit_fwd evaluates
+ * it and tpcca_refit_bwd returns its gradient (reverse mode, hand-written
+ * adjoints of the row step, covariance reset and cluster update).
+ *
+ * Correction map: TPCCA_MAP_SIZE binary32 coefficients [comp][ir][iphi][iz]
+ * (comp 0: delta r, 1: delta r*phi, 2: delta z, in cm), each component a
+ * tricubic uniform B-spline with knots r_k = 84 + (k-1)*168/13 (k = 0..15),
+ * phi_k = k*2pi/16 (periodic), z_k = -252 + (k-1)*504/29 (k = 0..31). A cluster
+ * of row r with local (y, z) in a sector of angle alpha is corrected inside
+ * its pad-row plane x = row_x[r]: R = sqrt(x^2 + y^2), phi = alpha + atan2(y, x),
+ * y' = y - (dr*y + drphi*x)/R, z' = z - dz, with (dr, drphi, dz) the map at
+ * (R, phi, z) (R and z clamped to the knot range).
+ *
+ * Refit per track (the refit of tpcca_track with masks given): start state
+ * params0/cov0 at row0, step row by row to the outermost cluster, then passes
+ * inward, outward, inward, each opening with a covariance reset; cluster i is
+ * used in pass p iff bit p of hit_mask[i] is set. chi2 = sum of the predicted
+ * chi2 of the clusters used in the last pass. A track whose row step leaves
+ * the |sin phi| guard has chi2 0, track_ok 0 and zero gradient. */
+#define TPCCA_MAP_SIZE (3 * 16 * 16 * 32)
+#define TPCCA_FLAG_ADJOINT_F64 4u /* tpcca_refit_bwd: adjoint arithmetic in binary64 (default binary32) */
+
+typedef struct {
+    int64_t n_tracks;         /* host */
+    int64_t n_hits;           /* host: hit_start[n_tracks] */
+    const float* params0;     /* [n_tracks * 5] start state y, z, sin phi, tan lambda, q/pT */
+    const float* cov0;        /* [n_tracks * 15] packed lower-triangular start covariance */
+    const int32_t* row0;      /* [n_tracks] row of the start state, 0..n_rows-1 */
+    const int32_t* inst;      /* [n_tracks] instance of the track's clusters */
+    const int64_t* hit_start; /* [n_tracks + 1] CSR into hit_id; hit_start[0] = 0, at most n_rows per track */
+    const int32_t* hit_id;    /* [n_hits] cluster ids of instance inst[t], rows strictly increasing */
+    const uint8_t* hit_mask;  /* [n_hits] accept bits, bit p = used in pass p (p = 0, 1, 2) */
+} tpcca_refit_set;
+
+/* Forward. map_coef: device [TPCCA_MAP_SIZE] binary32, or NULL (no
+ * correction). Outputs: chi2_track [n_tracks] (binary32), track_ok
+ * [n_tracks] (1/0, may be NULL), chi2_total [1] (FP64 sum, fixed order).
+ * Validates the set on the device (ranges, cluster ids inside their
+ * instance, strictly increasing rows): TPCCA_E_ARG otherwise. Synchronises
+ * the stream once. Keeps checkpoints of every track in the context for the
+ * next tpcca_refit_bwd; the clusters, the set and map_coef must stay
+ * unchanged until then. */
+tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* clusters, const tpcca_refit_set* set,
+                             const float* map_coef, float* chi2_track, int32_t* track_ok, double* chi2_total,
+                             void* hip_stream);
+
+/* Backward of the last tpcca_refit_fwd on this context, for the loss
+ * L = sum_t grad_chi2[t] * chi2_track[t]. grad_chi2: device [n_tracks]
+ * binary32. Outputs (FP64, device): grad_params0 [n_tracks * 5] = dL/dparams0;
+ * grad_map [TPCCA_MAP_SIZE] = dL/dcoef (may be NULL; evaluated at the
+ * forward's map, zero map if it was NULL; accumulated with FP64 atomics, so the
+ * last bits depend on the order of accumulation); grad_hit_yz [n_hits * 2] =
+ * dL/d(y', z') of each corrected cluster (may be NULL). Asynchronous. */
+tpcca_status tpcca_refit_bwd(tpcca_ctx* ctx, const float* grad_chi2, double* grad_params0, double* grad_map,
+                             double* grad_hit_yz, void* hip_stream);
+
 /* Arithmetic self-check: out_div[i] = a[i] / b[i], out_sqrt[i] = sqrt(|a[i]|) with the
  * library's binary32 operations (for bit comparison with a CPU). Synchronous. */
 tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div, float* out_sqrt, int64_t n,

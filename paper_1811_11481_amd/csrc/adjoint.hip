@@ -1,0 +1,753 @@
+// Differentiable refit (gfx950): the chi2 of the three-pass Kalman refit with
+// frozen accept masks, as a function of each track's start state and of a
+// smooth space-charge correction map applied to the clusters between seeding
+// and fitting (the paper applies such calibration corrections there,
+// Sections 1 and 4), and its hand-written reverse-mode adjoint.
+//
+// Forward (binary32, the refit's own arithmetic): one lane per track. The
+// refit is a sequence of operations (row step, covariance reset, cluster
+// update) produced by a small iterator; every kCk operations the lane stores a
+// checkpoint (iterator, state, reference point).
+// Backward: the lane walks its segments last to first, recomputes each
+// segment from its checkpoint into a per-track tape (covariance and operands
+// before every operation), then applies the adjoints of the recorded
+// operations in reverse, in binary32 or binary64.
+//
+// Map: components (delta r, delta r*phi, delta z), each a tricubic uniform
+// B-spline with 16 x 16 (periodic in phi) x 32 coefficients [comp][r][phi][z],
+// knots r_k = 84 + (k - 1) 168/13, phi_k = k 2 pi/16, z_k = -252 + (k - 1) 504/29.
+// A cluster on pad-row plane x with local (y, z) is corrected inside that
+// plane: y' = y - (dr y + drphi x) / r, z' = z - dz, with r = sqrt(x^2 + y^2)
+// and the map taken at (r, alpha + atan2(y, x), z).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adjoint.h"
+
+#pragma clang fp contract(off)
+
+namespace tpcca {
+
+namespace {
+
+constexpr int kMapNr = 16, kMapNphi = 16, kMapNz = 32;
+
+// ------------------------------------------------------------ map
+__device__ __forceinline__ void bspline_basis(float t, float w[4]) {
+    const float t2 = t * t, t3 = t2 * t, s = 1.0f - t;
+    w[0] = (s * s * s) * (1.0f / 6.0f);
+    w[1] = ((3.0f * t3 - 6.0f * t2) + 4.0f) * (1.0f / 6.0f);
+    w[2] = (((-3.0f * t3 + 3.0f * t2) + 3.0f * t) + 1.0f) * (1.0f / 6.0f);
+    w[3] = t3 * (1.0f / 6.0f);
+}
+
+struct MapCell {
+    int ir, iphi, iz;  // first of the four coefficients along each axis
+    float wr[4], wphi[4], wz[4];
+};
+
+__device__ __forceinline__ MapCell map_cell(float r, float phi, float z) {
+    const float pi2 = 6.2831853071795865f;
+    MapCell c;
+    float ur = 1.0f + (r - 84.0f) * (13.0f / 168.0f);
+    float uz = 1.0f + (z + 252.0f) * (29.0f / 504.0f);
+    ur = fminf(fmaxf(ur, 1.0f), 13.999999f);
+    uz = fminf(fmaxf(uz, 1.0f), 29.999998f);
+    float ph = fmodf(phi, pi2);
+    if (ph < 0.0f) ph += pi2;
+    float up = ph * ((float)kMapNphi / pi2);
+    if (!(up < (float)kMapNphi)) up = 0.0f;
+    if (!(up >= 0.0f)) up = 0.0f;
+    const int ir = (int)ur, iz = (int)uz, ip = (int)up;
+    bspline_basis(ur - (float)ir, c.wr);
+    bspline_basis(uz - (float)iz, c.wz);
+    bspline_basis(up - (float)ip, c.wphi);
+    c.ir = ir - 1;
+    c.iz = iz - 1;
+    c.iphi = ip - 1;
+    return c;
+}
+
+__device__ __forceinline__ int map_index(int comp, int ir, int iphi, int iz) {
+    iphi = (iphi + kMapNphi) % kMapNphi;
+    return ((comp * kMapNr + ir) * kMapNphi + iphi) * kMapNz + iz;
+}
+
+struct ClusterGeo {
+    float x, r, phi;
+};
+
+__device__ __forceinline__ ClusterGeo cluster_geo(const AdjBufs& a, int row, int32_t inst, float y) {
+    const DevConsts& K = *a.K;
+    ClusterGeo g;
+    g.x = K.X[row];
+    g.r = __builtin_sqrtf(g.x * g.x + y * y);
+    const int sec = a.inst_sector[inst];
+    g.phi = K.alpha[((sec % 18) + 18) % 18] + atan2f(y, g.x);
+    return g;
+}
+
+// ------------------------------------------------------------ op iterator
+enum : int { OP_END = 0, OP_PROP = 1, OP_RESET = 2, OP_UPD = 3 };
+
+struct OpIt {
+    int phase;  // 0: move to the outermost cluster, 1: the three passes, 2: done
+    int pass, q, cur;
+};
+
+struct Op {
+    int kind, from, to, hit, pass;
+};
+
+// Next operation of the frozen-mask refit: move to the outermost cluster,
+// then three passes (inward, outward, inward), each opening with a covariance
+// reset, stepping row by row to every cluster and updating where the pass's
+// mask bit is set.
+__device__ __forceinline__ Op next_op(OpIt& it, int n, const uint8_t* rows, const uint8_t* masks) {
+    Op op{OP_END, 0, 0, 0, 0};
+    for (;;) {
+        if (it.phase == 2) return op;
+        if (it.phase == 0) {
+            const int outer = rows[n - 1];
+            if (it.cur != outer) {
+                op.kind = OP_PROP;
+                op.from = it.cur;
+                op.to = it.cur < outer ? it.cur + 1 : it.cur - 1;
+                it.cur = op.to;
+                return op;
+            }
+            it.phase = 1;
+            it.pass = 0;
+            it.q = 0;
+            op.kind = OP_RESET;
+            return op;
+        }
+        if (it.q == n) {
+            ++it.pass;
+            it.q = 0;
+            if (it.pass == 3) {
+                it.phase = 2;
+                return op;
+            }
+            op.kind = OP_RESET;
+            return op;
+        }
+        const int i = it.pass != 1 ? n - 1 - it.q : it.q;
+        const int target = rows[i];
+        if (it.cur != target) {
+            op.kind = OP_PROP;
+            op.from = it.cur;
+            op.to = it.cur < target ? it.cur + 1 : it.cur - 1;
+            it.cur = op.to;
+            return op;
+        }
+        ++it.q;
+        if ((masks[i] >> it.pass) & 1u) {
+            op.kind = OP_UPD;
+            op.hit = i;
+            op.pass = it.pass;
+            return op;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t op_word(const Op& op) {
+    return (uint32_t)op.kind | ((uint32_t)op.pass << 2) | ((uint32_t)op.from << 4) | ((uint32_t)op.to << 12) |
+           ((uint32_t)op.hit << 20);
+}
+
+// One operation on (state, reference point); an update also returns its
+// residual. Returns false when a row step fails (the refit then stops, as the
+// refit itself does).
+__device__ __forceinline__ bool apply_op(const Op& op, KState& s, float& ref_y, float& ref_z, float& chi2,
+                                         const DevConsts& K, const float2* yz, float* r0, float* r1) {
+    if (op.kind == OP_PROP) return kf_propagate(s, K.X[op.from], K.X[op.to], K);
+    if (op.kind == OP_RESET) {
+        kf_reset(s, K);
+        return true;
+    }
+    const float2 m = yz[op.hit];
+    const Innov inn = kf_innovation(s, m.x - ref_y, m.y - ref_z, K);
+    *r0 = inn.r0;
+    *r1 = inn.r1;
+    kf_update(s, inn);
+    s.p[0] = s.p[0] + (ref_y - m.x);
+    s.p[1] = s.p[1] + (ref_z - m.y);
+    ref_y = m.x;
+    ref_z = m.y;
+    if (op.pass == 2) chi2 = chi2 + inn.chi2;
+    return true;
+}
+
+// ------------------------------------------------------------ dual numbers
+// value and derivatives with respect to (sin phi, tan lambda, q/pT) before a row step
+template <class A>
+struct D3 {
+    A v, d0, d1, d2;
+};
+template <class A>
+__device__ __forceinline__ D3<A> dc(A v) {
+    return D3<A>{v, A(0), A(0), A(0)};
+}
+template <class A>
+__device__ __forceinline__ D3<A> operator+(D3<A> a, D3<A> b) {
+    return D3<A>{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2};
+}
+template <class A>
+__device__ __forceinline__ D3<A> operator-(D3<A> a, D3<A> b) {
+    return D3<A>{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2};
+}
+template <class A>
+__device__ __forceinline__ D3<A> operator*(D3<A> a, D3<A> b) {
+    return D3<A>{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
+}
+template <class A>
+__device__ __forceinline__ D3<A> operator*(D3<A> a, A k) {
+    return D3<A>{a.v * k, a.d0 * k, a.d1 * k, a.d2 * k};
+}
+template <class A>
+__device__ __forceinline__ D3<A> operator/(D3<A> a, D3<A> b) {
+    const A q = a.v / b.v, ib = A(1) / b.v;
+    return D3<A>{q, (a.d0 - q * b.d0) * ib, (a.d1 - q * b.d1) * ib, (a.d2 - q * b.d2) * ib};
+}
+template <class A>
+__device__ __forceinline__ D3<A> dsqrt(D3<A> a) {
+    const A s = sqrt(a.v), h = A(0.5) / s;
+    return D3<A>{s, a.d0 * h, a.d1 * h, a.d2 * h};
+}
+
+// asin(u)/u and its derivative, the same truncated Maclaurin series as the refit
+template <class A>
+__device__ __forceinline__ D3<A> g_series(D3<A> u) {
+    const D3<A> w = u * u;
+    D3<A> h = dc(A(231.0 / 13312.0));
+    h = dc(A(63.0 / 2816.0)) + w * h;
+    h = dc(A(35.0 / 1152.0)) + w * h;
+    h = dc(A(5.0 / 112.0)) + w * h;
+    h = dc(A(3.0 / 40.0)) + w * h;
+    h = dc(A(1.0 / 6.0)) + w * h;
+    return dc(A(1)) + w * h;
+}
+template <class A>
+__device__ __forceinline__ D3<A> gp_series(D3<A> u) {
+    const D3<A> w = u * u;
+    D3<A> h = dc(A(2772.0 / 13312.0));
+    h = dc(A(630.0 / 2816.0)) + w * h;
+    h = dc(A(280.0 / 1152.0)) + w * h;
+    h = dc(A(30.0 / 112.0)) + w * h;
+    h = dc(A(12.0 / 40.0)) + w * h;
+    h = dc(A(2.0 / 6.0)) + w * h;
+    return u * h;
+}
+
+// The variable Jacobian entries of one row step, F02, F04, F12, F13, F14, F24,
+// with their derivatives with respect to (sin phi, tan lambda, q/pT).
+template <class A>
+__device__ __forceinline__ void step_jacobian(A s1v, A tv, A qv, A dx, A kB, D3<A> f[6]) {
+    const D3<A> s1{s1v, A(1), A(0), A(0)}, t{tv, A(0), A(1), A(0)}, q{qv, A(0), A(0), A(1)};
+    const D3<A> one = dc(A(1));
+    const D3<A> kq = q * kB;
+    const D3<A> s2 = s1 + kq * dx;
+    const D3<A> c1 = dsqrt(one - s1 * s1), c2 = dsqrt(one - s2 * s2);
+    const D3<A> tt = (s1 + s2) / (c1 + c2);
+    const D3<A> w = one + tt * tt;
+    const D3<A> lc = dsqrt(w) * dx;
+    const D3<A> u = (kq * lc) * A(0.5);
+    const D3<A> g = g_series(u), gp = gp_series(u);
+    f[0] = ((w * dx) * (one / c1 + one / c2)) * A(0.5);
+    f[1] = ((w * dx) * (dc(kB * dx) / c2)) * A(0.5);
+    f[2] = t * ((tt * dx) / (c1 * c2));
+    f[3] = lc * g;
+    const D3<A> dlc = ((lc * (kB * dx)) * tt) / (c2 * A(2));
+    const D3<A> du = (lc * kB + kq * dlc) * A(0.5);
+    f[4] = t * (dlc * g + (lc * gp) * du);
+    f[5] = dc(kB * dx);
+}
+
+// v <- F^T v for the row-step Jacobian F (identity plus the six entries)
+template <class A>
+__device__ __forceinline__ void ft_apply(A v[5], const A f[6]) {
+    const A v0 = v[0], v1 = v[1], v2 = v[2];
+    v[2] = v2 + f[0] * v0 + f[2] * v1;
+    v[3] = v[3] + f[3] * v1;
+    v[4] = v[4] + f[1] * v0 + f[4] * v1 + f[5] * v2;
+}
+
+// v <- F v
+template <class A>
+__device__ __forceinline__ void f_apply(A v[5], const A f[6]) {
+    v[0] = v[0] + f[0] * v[2] + f[1] * v[4];
+    v[1] = v[1] + f[2] * v[2] + f[3] * v[3] + f[4] * v[4];
+    v[2] = v[2] + f[5] * v[4];
+}
+
+// Adjoint of a row step with input (sin phi, tan lambda, q/pT) and covariance
+// C: pbar <- F^T pbar + 2 sum_bc M_bc dF_bc/dp (M = Cbar F C), Cbar <- F^T Cbar F.
+template <class A>
+__device__ __forceinline__ void adj_prop(const float C[15], float s1, float t, float q, float dx, A pb[5], A Cb[15],
+                                         const DevConsts& K) {
+    D3<A> fd[6];
+    step_jacobian<A>(A(s1), A(t), A(q), A(dx), A(K.kB), fd);
+    A f[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) f[e] = fd[e].v;
+    // columns 2..4 of B = F C
+    A B[3][5];  // B[c - 2][k]
+#pragma unroll
+    for (int c = 2; c < 5; ++c) {
+        A col[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) col[k] = A(C[pk(k, c)]);
+        f_apply(col, f);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) B[c - 2][k] = col[k];
+    }
+    // M_bc = sum_k Cbar_bk B_kc at the six variable entries
+    auto M = [&](int b, int c) {
+        A acc = A(0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) acc = acc + Cb[pk(b, k)] * B[c - 2][k];
+        return acc;
+    };
+    const A m02 = M(0, 2), m04 = M(0, 4), m12 = M(1, 2), m13 = M(1, 3), m14 = M(1, 4), m24 = M(2, 4);
+    const A g0 = m02 * fd[0].d0 + m04 * fd[1].d0 + m12 * fd[2].d0 + m13 * fd[3].d0 + m14 * fd[4].d0 + m24 * fd[5].d0;
+    const A g1 = m02 * fd[0].d1 + m04 * fd[1].d1 + m12 * fd[2].d1 + m13 * fd[3].d1 + m14 * fd[4].d1 + m24 * fd[5].d1;
+    const A g2 = m02 * fd[0].d2 + m04 * fd[1].d2 + m12 * fd[2].d2 + m13 * fd[3].d2 + m14 * fd[4].d2 + m24 * fd[5].d2;
+    ft_apply(pb, f);
+    pb[2] = pb[2] + A(2) * g0;
+    pb[3] = pb[3] + A(2) * g1;
+    pb[4] = pb[4] + A(2) * g2;
+    // Cbar <- F^T Cbar F: F^T on every column, then on every row
+    A X[5][5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        A col[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) col[k] = Cb[pk(k, j)];
+        ft_apply(col, f);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) X[k][j] = col[k];
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        ft_apply(X[i], f);
+#pragma unroll
+        for (int j = 0; j <= i; ++j) Cb[pk(i, j)] = X[i][j];
+    }
+}
+
+// Adjoint of a covariance reset: variances scaled, correlations dropped.
+template <class A>
+__device__ __forceinline__ void adj_reset(A Cb[15], const DevConsts& K) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j < i; ++j) Cb[pk(i, j)] = A(0);
+        Cb[pk(i, i)] = Cb[pk(i, i)] * A(K.cov_reset);
+    }
+}
+
+// Adjoint of a cluster update with covariance C and residual r = m - (y, z):
+// with G = C H^T (columns 0, 1 of C), A = S^-1, S = H C H^T + V,
+// p+ = p + G A r, C+ = C - G A G^T, chi2 = r^T A r (weight cb):
+//   rbar = A (G^T pbar+ + 2 cb r)      -> measurement, and -H^T rbar -> pbar
+//   Gbar = pbar+ (A r)^T - 2 Cbar+ G A
+//   Abar = (G^T pbar+) r^T - G^T Cbar+ G + cb r r^T,  Sbar = -A Abar A
+//   Cbar = Cbar+ + sym(H^T Sbar H) + sym(Gbar H)
+template <class A>
+__device__ __forceinline__ void adj_upd(const float C[15], float r0f, float r1f, A pb[5], A Cb[15], A& mb0, A& mb1,
+                                        A cb, const DevConsts& K) {
+    const A r0 = A(r0f), r1 = A(r1f);
+    const A s00 = A(C[0]) + A(K.vy), s01 = A(C[1]), s11 = A(C[2]) + A(K.vz);
+    const A idet = A(1) / (s00 * s11 - s01 * s01);
+    const A a00 = s11 * idet, a01 = -s01 * idet, a11 = s00 * idet;
+    A G0[5], G1[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        G0[i] = A(C[pk(i, 0)]);
+        G1[i] = A(C[pk(i, 1)]);
+    }
+    const A v0 = a00 * r0 + a01 * r1, v1 = a01 * r0 + a11 * r1;
+    A gp0 = A(0), gp1 = A(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        gp0 = gp0 + G0[i] * pb[i];
+        gp1 = gp1 + G1[i] * pb[i];
+    }
+    const A b0 = gp0 + A(2) * cb * r0, b1 = gp1 + A(2) * cb * r1;
+    const A rb0 = a00 * b0 + a01 * b1, rb1 = a01 * b0 + a11 * b1;
+    mb0 = mb0 + rb0;
+    mb1 = mb1 + rb1;
+    A CG0[5], CG1[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        A x0 = A(0), x1 = A(0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            x0 = x0 + Cb[pk(i, k)] * G0[k];
+            x1 = x1 + Cb[pk(i, k)] * G1[k];
+        }
+        CG0[i] = x0;
+        CG1[i] = x1;
+    }
+    A Gb0[5], Gb1[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        Gb0[i] = pb[i] * v0 - A(2) * (CG0[i] * a00 + CG1[i] * a01);
+        Gb1[i] = pb[i] * v1 - A(2) * (CG0[i] * a01 + CG1[i] * a11);
+    }
+    A q00 = A(0), q01 = A(0), q10 = A(0), q11 = A(0);  // G^T Cbar+ G
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        q00 = q00 + G0[i] * CG0[i];
+        q01 = q01 + G0[i] * CG1[i];
+        q10 = q10 + G1[i] * CG0[i];
+        q11 = q11 + G1[i] * CG1[i];
+    }
+    const A ab00 = gp0 * r0 - q00 + cb * r0 * r0;
+    const A ab01 = gp0 * r1 - q01 + cb * r0 * r1;
+    const A ab10 = gp1 * r0 - q10 + cb * r1 * r0;
+    const A ab11 = gp1 * r1 - q11 + cb * r1 * r1;
+    const A t00 = ab00 * a00 + ab01 * a01, t01 = ab00 * a01 + ab01 * a11;
+    const A t10 = ab10 * a00 + ab11 * a01, t11 = ab10 * a01 + ab11 * a11;
+    const A sb00 = -(a00 * t00 + a01 * t10);
+    const A sb01 = -(a00 * t01 + a01 * t11);
+    const A sb10 = -(a01 * t00 + a11 * t10);
+    const A sb11 = -(a01 * t01 + a11 * t11);
+    // symmetric part of Gbar H (Gbar in columns 0 and 1)
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            const A eij = j == 0 ? Gb0[i] : (j == 1 ? Gb1[i] : A(0));
+            const A eji = i == 0 ? Gb0[j] : (i == 1 ? Gb1[j] : A(0));
+            Cb[pk(i, j)] = Cb[pk(i, j)] + A(0.5) * (eij + eji);
+        }
+    Cb[0] = Cb[0] + sb00;
+    Cb[1] = Cb[1] + A(0.5) * (sb01 + sb10);
+    Cb[2] = Cb[2] + sb11;
+    pb[0] = pb[0] - rb0;
+    pb[1] = pb[1] - rb1;
+}
+
+// ------------------------------------------------------------ kernels
+__device__ __forceinline__ void set_err(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
+
+// Per track: validate the refit set, tag every cluster slot with its instance.
+__global__ void k_adj_prep(AdjBufs a) {
+    const int nr = a.n_rows;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.n_tracks;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t h0 = a.hit_start[t], h1 = a.hit_start[t + 1];
+        const int32_t inst = a.inst[t], row0 = a.row0[t];
+        bool ok = h0 >= 0 && h0 <= h1 && h1 <= a.n_hits && h1 - h0 <= nr && inst >= 0 && inst < a.n_inst &&
+                  row0 >= 0 && row0 < nr;
+        if (t == 0 && h0 != 0) ok = false;
+        if (t == a.n_tracks - 1 && h1 != a.n_hits) ok = false;
+        if (!ok) {
+            set_err(a.err, AERR_RANGE);
+            continue;
+        }
+        const int64_t lo = a.row_start[(int64_t)inst * nr], hi = a.row_start[(int64_t)(inst + 1) * nr];
+        if (!(lo >= 0 && lo <= hi && hi <= a.n_clusters)) {
+            set_err(a.err, AERR_RANGE);
+            continue;
+        }
+        for (int64_t h = h0; h < h1; ++h) {
+            const int32_t id = a.hit_id[h];
+            if (id < lo || id >= hi) set_err(a.err, AERR_HIT);
+            a.hit_inst[h] = inst;
+        }
+    }
+}
+
+// Per cluster slot: pad row (search in the instance's row ranges) and the
+// corrected coordinates.
+__global__ void k_map_correct(AdjBufs a) {
+    if (*a.err) return;
+    const int nr = a.n_rows;
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < a.n_hits;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t id = a.hit_id[h];
+        const int32_t inst = a.hit_inst[h];
+        const int64_t* rs = a.row_start + (int64_t)inst * nr;
+        int lo = 0, hi = nr;  // rs[lo] <= id < rs[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rs[mid] <= id) lo = mid;
+            else hi = mid;
+        }
+        a.hit_row[h] = (uint8_t)lo;
+        float y = a.y[id], z = a.z[id];
+        if (a.coef) {
+            const ClusterGeo g = cluster_geo(a, lo, inst, y);
+            const MapCell c = map_cell(g.r, g.phi, z);
+            float d[3];
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                float acc = 0.0f;
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        const float wij = c.wr[i] * c.wphi[j];
+                        const float* cf = a.coef + map_index(comp, c.ir + i, c.iphi + j, c.iz);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc = acc + (wij * c.wz[e]) * cf[e];
+                    }
+                d[comp] = acc;
+            }
+            y = y - (d[0] * y + d[1] * g.x) / g.r;
+            z = z - d[2];
+        }
+        a.hit_yz[h] = make_float2(y, z);
+    }
+}
+
+__device__ __forceinline__ void put_word(uint32_t* base, int64_t slot, int words, int64_t n, int64_t t, int f,
+                                         uint32_t v) {
+    base[(slot * words + f) * n + t] = v;
+}
+__device__ __forceinline__ uint32_t get_word(const uint32_t* base, int64_t slot, int words, int64_t n, int64_t t,
+                                             int f) {
+    return base[(slot * words + f) * n + t];
+}
+
+__global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a) {
+    if (*a.err) return;
+    const DevConsts& K = *a.K;
+    const int64_t N = a.n_tracks;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t off = a.hit_start[t];
+        const int n = (int)(a.hit_start[t + 1] - off);
+        const uint8_t* rows = a.hit_row + off;
+        const uint8_t* masks = a.hit_mask + off;
+        const float2* yz = a.hit_yz + off;
+        bool ok = n > 0;
+        for (int i = 1; i < n; ++i)
+            if (rows[i] <= rows[i - 1]) {
+                set_err(a.err, AERR_ROWS);
+                ok = false;
+                break;
+            }
+        KState s;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s.p[q] = a.params0[t * 5 + q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) s.C[q] = a.cov0[t * 15 + q];
+        float ref_y = s.p[0], ref_z = s.p[1];
+        s.p[0] = 0.0f;
+        s.p[1] = 0.0f;
+        OpIt it{0, 0, 0, a.row0[t]};
+        float chi2 = 0.0f, r0, r1;
+        int nops = 0;
+        while (ok) {
+            const OpIt it0 = it;
+            const Op op = next_op(it, n, rows, masks);
+            if (op.kind == OP_END) break;
+            if (nops % kCk == 0) {
+                const int64_t sg = nops / kCk;
+                if (sg >= a.max_ck) {
+                    set_err(a.err, AERR_CKPT);
+                    ok = false;
+                    break;
+                }
+                uint32_t w[kCkWords];
+                w[0] = (uint32_t)it0.phase;
+                w[1] = (uint32_t)it0.pass;
+                w[2] = (uint32_t)it0.q;
+                w[3] = (uint32_t)it0.cur;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) w[4 + q] = __float_as_uint(s.p[q]);
+#pragma unroll
+                for (int q = 0; q < 15; ++q) w[9 + q] = __float_as_uint(s.C[q]);
+                w[24] = __float_as_uint(ref_y);
+                w[25] = __float_as_uint(ref_z);
+#pragma unroll
+                for (int f = 0; f < kCkWords; ++f) put_word(a.ckpt, sg, kCkWords, N, t, f, w[f]);
+            }
+            if (!apply_op(op, s, ref_y, ref_z, chi2, K, yz, &r0, &r1)) ok = false;
+            ++nops;
+        }
+        a.nops[t] = ok ? nops : -1;
+        a.chi2_track[t] = ok ? chi2 : 0.0f;
+        if (a.track_ok) a.track_ok[t] = ok ? 1 : 0;
+    }
+}
+
+template <class A>
+__global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a) {
+    const DevConsts& K = *a.K;
+    const int64_t N = a.n_tracks;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t off = a.hit_start[t];
+        const int n = (int)(a.hit_start[t + 1] - off);
+        double2* gm = a.hit_grad + off;
+        for (int i = 0; i < n; ++i) gm[i] = make_double2(0.0, 0.0);
+        const int nops = a.nops[t];
+        double* gp = a.grad_params + t * 5;
+        if (nops <= 0) {
+            for (int q = 0; q < 5; ++q) gp[q] = 0.0;
+            continue;
+        }
+        const uint8_t* rows = a.hit_row + off;
+        const uint8_t* masks = a.hit_mask + off;
+        const float2* yz = a.hit_yz + off;
+        const A cb = A(a.grad_chi2[t]);
+        A pb[5], Cb[15];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) pb[q] = A(0);
+#pragma unroll
+        for (int q = 0; q < 15; ++q) Cb[q] = A(0);
+        const int nseg = (nops + kCk - 1) / kCk;
+        for (int sg = nseg - 1; sg >= 0; --sg) {
+            uint32_t w[kCkWords];
+#pragma unroll
+            for (int f = 0; f < kCkWords; ++f) w[f] = get_word(a.ckpt, sg, kCkWords, N, t, f);
+            OpIt it{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+            KState s;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) s.p[q] = __uint_as_float(w[4 + q]);
+#pragma unroll
+            for (int q = 0; q < 15; ++q) s.C[q] = __uint_as_float(w[9 + q]);
+            float ref_y = __uint_as_float(w[24]), ref_z = __uint_as_float(w[25]), chi2 = 0.0f;
+            const int len = min(kCk, nops - sg * kCk);
+            // recompute the segment, recording each operation's inputs:
+            // covariance, then (sin phi, tan lambda, q/pT) of a row step or the
+            // residual of an update
+            for (int k = 0; k < len; ++k) {
+                const Op op = next_op(it, n, rows, masks);
+#pragma unroll
+                for (int q = 0; q < 15; ++q) put_word(a.tape, k, kTapeWords, N, t, q, __float_as_uint(s.C[q]));
+                float o0 = s.p[2], o1 = s.p[3];
+                const float o2 = s.p[4];
+                apply_op(op, s, ref_y, ref_z, chi2, K, yz, &o0, &o1);
+                put_word(a.tape, k, kTapeWords, N, t, 15, __float_as_uint(o0));
+                put_word(a.tape, k, kTapeWords, N, t, 16, __float_as_uint(o1));
+                put_word(a.tape, k, kTapeWords, N, t, 17, __float_as_uint(o2));
+                put_word(a.tape, k, kTapeWords, N, t, 18, op_word(op));
+            }
+            // reverse sweep
+            for (int k = len - 1; k >= 0; --k) {
+                const uint32_t ow = get_word(a.tape, k, kTapeWords, N, t, 18);
+                const int kind = (int)(ow & 3u);
+                if (kind == OP_RESET) {
+                    adj_reset(Cb, K);
+                    continue;
+                }
+                float C[15];
+#pragma unroll
+                for (int q = 0; q < 15; ++q) C[q] = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, q));
+                const float o0 = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, 15));
+                const float o1 = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, 16));
+                if (kind == OP_PROP) {
+                    const float o2 = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, 17));
+                    const int from = (int)((ow >> 4) & 255u), to = (int)((ow >> 12) & 255u);
+                    adj_prop<A>(C, o0, o1, o2, K.X[to] - K.X[from], pb, Cb, K);
+                } else {
+                    const int hit = (int)((ow >> 20) & 255u), pass = (int)((ow >> 2) & 3u);
+                    A mb0 = A(0), mb1 = A(0);
+                    adj_upd<A>(C, o0, o1, pb, Cb, mb0, mb1, pass == 2 ? cb : A(0), K);
+                    double2 g = gm[hit];
+                    g.x += (double)mb0;
+                    g.y += (double)mb1;
+                    gm[hit] = g;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gp[q] = (double)pb[q];
+    }
+}
+
+// d loss / d coef: each cluster slot adds its (d/dy', d/dz') times the
+// derivative of (y', z') with respect to the coefficients of its map cell.
+__global__ void k_map_grad(AdjBufs a) {
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < a.n_hits;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        const double2 g = a.hit_grad[h];
+        if (g.x == 0.0 && g.y == 0.0) continue;
+        const int32_t id = a.hit_id[h];
+        const float y = a.y[id], z = a.z[id];
+        const ClusterGeo geo = cluster_geo(a, a.hit_row[h], a.hit_inst[h], y);
+        const MapCell c = map_cell(geo.r, geo.phi, z);
+        const double gc[3] = {-g.x * (double)y / (double)geo.r, -g.x * (double)geo.x / (double)geo.r, -g.y};
+        for (int comp = 0; comp < 3; ++comp) {
+            if (gc[comp] == 0.0) continue;
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    const double wij = gc[comp] * (double)c.wr[i] * (double)c.wphi[j];
+                    double* dst = a.grad_map + map_index(comp, c.ir + i, c.iphi + j, c.iz);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) unsafeAtomicAdd(dst + e, wij * (double)c.wz[e]);
+                }
+        }
+    }
+}
+
+// Total chi2 in FP64, one block, fixed order.
+__global__ void k_sum_chi2(AdjBufs a) {
+    __shared__ double sh[1024];
+    double acc = 0.0;
+    for (int64_t t = threadIdx.x; t < a.n_tracks; t += blockDim.x) acc += (double)a.chi2_track[t];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.chi2_total[0] = sh[0];
+}
+
+__global__ void k_fill_f64(double* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_clear_err(uint32_t* err) {
+    if (threadIdx.x == 0) err[0] = 0u;
+}
+
+inline int blocks_for(int64_t n, int block, int cap) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+int64_t adj_max_ops(int n_rows) {
+    // strictly increasing cluster rows: at most n_rows - 1 row steps to reach
+    // the outermost cluster and per pass, n_rows updates per pass, 3 resets
+    return 4 * (int64_t)(n_rows - 1) + 3 * (int64_t)n_rows + 3;
+}
+
+void enqueue_adj_clear(const AdjBufs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, st, a.err);
+}
+
+void enqueue_refit_fwd(const AdjBufs& a, hipStream_t st) {
+    if (a.n_tracks > 0) {
+        hipLaunchKernelGGL(k_adj_prep, dim3(blocks_for(a.n_tracks, 256, 16384)), dim3(256), 0, st, a);
+        if (a.n_hits > 0)
+            hipLaunchKernelGGL(k_map_correct, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_refit_fwd, dim3(blocks_for(a.n_tracks, 128, 16384)), dim3(128), 0, st, a);
+    }
+    hipLaunchKernelGGL(k_sum_chi2, dim3(1), dim3(1024), 0, st, a);
+}
+
+void enqueue_refit_bwd(const AdjBufs& a, hipStream_t st) {
+    if (a.n_tracks > 0) {
+        if (a.adj_f64)
+            hipLaunchKernelGGL(k_refit_bwd<double>, dim3(blocks_for(a.n_tracks, 128, 16384)), dim3(128), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_refit_bwd<float>, dim3(blocks_for(a.n_tracks, 128, 16384)), dim3(128), 0, st, a);
+    }
+    if (a.grad_map) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(kMapSize, 256, 1024)), dim3(256), 0, st, a.grad_map,
+                           (int64_t)kMapSize);
+        if (a.n_hits > 0)
+            hipLaunchKernelGGL(k_map_grad, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a);
+    }
+}
+
+}  // namespace tpcca

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/tpcca.h"
+#include "adjoint.h"
 #include "internal.h"
 
 using namespace tpcca;
@@ -67,6 +68,13 @@ struct tpcca_ctx {
     hipStream_t own_stream = nullptr;
     bool events = false;
     float stage_ms[8] = {};
+    // differentiable refit: scratch, error word, last forward
+    void* adj_base = nullptr;
+    size_t adj_bytes = 0;
+    int64_t adj_cap_t = -1, adj_cap_h = -1;
+    uint32_t* h_adj_err = nullptr;  // pinned
+    AdjBufs adj{};
+    bool adj_valid = false;
 };
 
 namespace {
@@ -452,6 +460,52 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
 
 }  // namespace
 
+// ---------------------------------------------------------------- differentiable refit
+namespace {
+
+struct AdjLayout {
+    size_t o_inst, o_row, o_yz, o_grad, o_nops, o_ckpt, o_tape, o_err, total;
+};
+
+AdjLayout adj_layout(int64_t cap_t, int64_t cap_h, int n_rows) {
+    const int64_t max_ck = (adj_max_ops(n_rows) + kCk - 1) / kCk;
+    Layout L;
+    AdjLayout a;
+    a.o_inst = L.add(4 * cap_h);
+    a.o_row = L.add(cap_h);
+    a.o_yz = L.add(8 * cap_h);
+    a.o_grad = L.add(16 * cap_h);
+    a.o_nops = L.add(4 * cap_t);
+    a.o_ckpt = L.add((size_t)4 * kCkWords * max_ck * cap_t);
+    a.o_tape = L.add((size_t)4 * kTapeWords * kCk * cap_t);
+    a.o_err = L.add(256);
+    a.total = L.total;
+    return a;
+}
+
+tpcca_status ensure_adj_arena(tpcca_ctx* ctx, int64_t nt, int64_t nh) {
+    if (ctx->adj_base && nt <= ctx->adj_cap_t && nh <= ctx->adj_cap_h) return TPCCA_OK;
+    const int64_t ct = std::max(nt, ctx->adj_cap_t), ch = std::max(nh, ctx->adj_cap_h);
+    const AdjLayout L = adj_layout(ct, ch, ctx->params.n_rows);
+    if (ctx->adj_base) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(ctx->adj_base));
+        ctx->adj_base = nullptr;
+        ctx->adj_cap_t = ctx->adj_cap_h = -1;
+    }
+    hipError_t e = hipMalloc(&ctx->adj_base, L.total);
+    if (e != hipSuccess) {
+        ctx->adj_base = nullptr;
+        return hip_fail(ctx, e, "refit scratch allocation");
+    }
+    ctx->adj_bytes = L.total;
+    ctx->adj_cap_t = ct;
+    ctx->adj_cap_h = ch;
+    return TPCCA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 tpcca_status tpcca_default_params(tpcca_params* p) {
@@ -547,6 +601,8 @@ void tpcca_destroy(tpcca_ctx* ctx) {
         for (auto& e : ctx->ev) hipEventDestroy(e);
     if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
     if (ctx->arena.base) hipFree(ctx->arena.base);
+    if (ctx->adj_base) hipFree(ctx->adj_base);
+    if (ctx->h_adj_err) hipHostFree(ctx->h_adj_err);
     if (ctx->dK) hipFree(ctx->dK);
     if (ctx->dctr) hipFree(ctx->dctr);
     if (ctx->hctr) hipHostFree(ctx->hctr);
@@ -767,6 +823,98 @@ tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div
     enqueue_fp32_selfcheck(a, b, out_div, out_sqrt, n, (hipStream_t)hip_stream);
     if (hipGetLastError() != hipSuccess) return TPCCA_E_DEVICE;
     if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return TPCCA_E_DEVICE;
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_refit_set* set,
+                             const float* map_coef, float* chi2_track, int32_t* track_ok, double* chi2_total,
+                             void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    ctx->adj_valid = false;
+    if (!in || !set || !chi2_total) return fail(ctx, TPCCA_E_ARG, "null clusters, refit set or chi2_total");
+    const int64_t nt = set->n_tracks, nh = set->n_hits;
+    if (nt < 0 || nh < 0 || nt >= ((int64_t)1 << 31) || nh >= ((int64_t)1 << 31))
+        return fail(ctx, TPCCA_E_ARG, "refit set sizes must be in [0, 2^31)");
+    if (in->n_inst < 0 || in->n_clusters < 0) return fail(ctx, TPCCA_E_ARG, "negative cluster sizes");
+    if (nt > 0 && (!set->params0 || !set->cov0 || !set->row0 || !set->inst || !set->hit_start || !chi2_track))
+        return fail(ctx, TPCCA_E_ARG, "null refit-set array or chi2_track");
+    if (nt > 0 && (in->n_inst == 0 || !in->row_start || !in->inst_sector))
+        return fail(ctx, TPCCA_E_ARG, "tracks given without cluster instances");
+    if (nh > 0 && (!set->hit_id || !set->hit_mask || !in->y || !in->z))
+        return fail(ctx, TPCCA_E_ARG, "null hit_id, hit_mask or cluster coordinates");
+    if (nt == 0 && nh != 0) return fail(ctx, TPCCA_E_ARG, "clusters given without tracks");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!ctx->h_adj_err) HIP_TRY(hipHostMalloc((void**)&ctx->h_adj_err, 256, hipHostMallocDefault));
+    tpcca_status s = ensure_adj_arena(ctx, std::max<int64_t>(nt, 1), std::max<int64_t>(nh, 1));
+    if (s != TPCCA_OK) return s;
+    const AdjLayout L = adj_layout(ctx->adj_cap_t, ctx->adj_cap_h, ctx->params.n_rows);
+    char* base = (char*)ctx->adj_base;
+    AdjBufs a{};
+    a.K = ctx->dK;
+    a.n_rows = ctx->params.n_rows;
+    a.n_inst = in->n_inst;
+    a.n_clusters = in->n_clusters;
+    a.inst_sector = in->inst_sector;
+    a.row_start = in->row_start;
+    a.y = in->y;
+    a.z = in->z;
+    a.n_tracks = nt;
+    a.n_hits = nh;
+    a.params0 = set->params0;
+    a.cov0 = set->cov0;
+    a.row0 = set->row0;
+    a.inst = set->inst;
+    a.hit_start = set->hit_start;
+    a.hit_id = set->hit_id;
+    a.hit_mask = set->hit_mask;
+    a.coef = map_coef;
+    a.hit_inst = (int32_t*)(base + L.o_inst);
+    a.hit_row = (uint8_t*)(base + L.o_row);
+    a.hit_yz = (float2*)(base + L.o_yz);
+    a.hit_grad = (double2*)(base + L.o_grad);
+    a.nops = (int32_t*)(base + L.o_nops);
+    a.ckpt = (uint32_t*)(base + L.o_ckpt);
+    a.tape = (uint32_t*)(base + L.o_tape);
+    a.max_ck = (int32_t)((adj_max_ops(ctx->params.n_rows) + kCk - 1) / kCk);
+    a.err = (uint32_t*)(base + L.o_err);
+    a.chi2_track = chi2_track;
+    a.track_ok = track_ok;
+    a.chi2_total = chi2_total;
+    a.adj_f64 = (ctx->params.flags & TPCCA_FLAG_ADJOINT_F64) ? 1 : 0;
+    enqueue_adj_clear(a, st);
+    enqueue_refit_fwd(a, st);
+    HIP_TRY(hipMemcpyAsync(ctx->h_adj_err, a.err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    const uint32_t err = ctx->h_adj_err[0];
+    if (err & AERR_RANGE)
+        return fail(ctx, TPCCA_E_ARG, "refit set: hit_start, instance, start row or row_start out of range");
+    if (err & AERR_HIT) return fail(ctx, TPCCA_E_ARG, "refit set: a cluster id lies outside its track's instance");
+    if (err & AERR_ROWS) return fail(ctx, TPCCA_E_ARG, "refit set: cluster rows of a track not strictly increasing");
+    if (err) return fail(ctx, TPCCA_E_INTERNAL, "refit checkpoint bound exceeded");
+    ctx->adj = a;
+    ctx->adj_valid = true;
+    ctx->err.clear();
+    return TPCCA_OK;
+}
+
+tpcca_status tpcca_refit_bwd(tpcca_ctx* ctx, const float* grad_chi2, double* grad_params0, double* grad_map,
+                             double* grad_hit_yz, void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    if (!ctx->adj_valid) return fail(ctx, TPCCA_E_ARG, "no successful tpcca_refit_fwd to differentiate");
+    AdjBufs a = ctx->adj;
+    if (a.n_tracks > 0 && (!grad_chi2 || !grad_params0))
+        return fail(ctx, TPCCA_E_ARG, "null grad_chi2 or grad_params0");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    a.grad_chi2 = grad_chi2;
+    a.grad_params = grad_params0;
+    a.grad_map = grad_map;
+    enqueue_refit_bwd(a, st);
+    if (grad_hit_yz && a.n_hits > 0)
+        HIP_TRY(hipMemcpyAsync(grad_hit_yz, a.hit_grad, 16 * (size_t)a.n_hits, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
     return TPCCA_OK;
 }
 

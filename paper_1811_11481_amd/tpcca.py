@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libtpcca.so")
 OK, E_ARG, E_CAPACITY, E_DEVICE, E_OOM, E_INTERNAL = range(6)
 FLAG_STATS = 1
 FLAG_TIMING = 2
+FLAG_ADJOINT_F64 = 4
+MAP_SHAPE = (3, 16, 16, 32)  # (delta r, delta r*phi, delta z) x r x phi x z
+MAP_SIZE = 3 * 16 * 16 * 32
 MAX_ROW_CLUSTERS = 16384
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_CAPACITY", 3: "E_DEVICE", 4: "E_OOM", 5: "E_INTERNAL"}
 
@@ -28,6 +31,7 @@ EXPORTED = [
     "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_track", "tpcca_track_batched", "tpcca_autotune",
     "tpcca_export_sizes", "tpcca_export_grid", "tpcca_export_links", "tpcca_export_tracklets",
     "tpcca_export_selected", "tpcca_get_stats", "tpcca_get_stage_times", "tpcca_fp32_selfcheck",
+    "tpcca_refit_fwd", "tpcca_refit_bwd",
 ]
 
 
@@ -107,6 +111,20 @@ class TracksC(ctypes.Structure):
     ]
 
 
+class RefitSetC(ctypes.Structure):
+    _fields_ = [
+        ("n_tracks", ctypes.c_int64),
+        ("n_hits", ctypes.c_int64),
+        ("params0", ctypes.c_void_p),
+        ("cov0", ctypes.c_void_p),
+        ("row0", ctypes.c_void_p),
+        ("inst", ctypes.c_void_p),
+        ("hit_start", ctypes.c_void_p),
+        ("hit_id", ctypes.c_void_p),
+        ("hit_mask", ctypes.c_void_p),
+    ]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_clusters", "n_segments", "n_links", "n_starts", "n_chain_hits", "tl_rows_visited", "tl_candidates",
@@ -126,6 +144,11 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libtpcca.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+        # torch first: its HIP runtime then satisfies the library's runtime
+        # dependency, so both share one runtime (streams, synchronisation,
+        # device memory). Loaded the other way round the process would hold
+        # two runtimes and the second could not open the device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         st = ctypes.c_int
@@ -165,6 +188,10 @@ def load():
         L.tpcca_get_stage_times.argtypes = [vp, vp]
         L.tpcca_fp32_selfcheck.restype = st
         L.tpcca_fp32_selfcheck.argtypes = [vp, vp, vp, vp, i64, vp]
+        L.tpcca_refit_fwd.restype = st
+        L.tpcca_refit_fwd.argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(RefitSetC), vp, vp, vp, vp, vp]
+        L.tpcca_refit_bwd.restype = st
+        L.tpcca_refit_bwd.argtypes = [vp] * 6
         _lib = L
     return _lib
 
@@ -414,6 +441,136 @@ class Tracker:
         self._check(self.lib.tpcca_get_stage_times(self.h, ctypes.c_void_p(a.ctypes.data)))
         return dict(zip(("grid", "links", "clean_starts", "tracklets", "select", "refit", "write", "finish"),
                         a.tolist()))
+
+    # ---- differentiable refit ---------------------------------------------
+    def refit_forward(self, clusters: DeviceClusters, rset: "RefitSet", params0=None, coef=None, stream=None):
+        """chi2 per track (float32), track ok flags, FP64 total of the refit with
+        frozen masks; params0 (n, 5) float32 overrides rset.params0, coef is
+        the (3, 16, 16, 32) float32 correction map or None."""
+        torch = _torch()
+        n = rset.n_tracks
+        dev = clusters.y.device
+        p0 = rset.params0 if params0 is None else params0
+        for name, t, dt in (("params0", p0, torch.float32), ("coef", coef, torch.float32)):
+            if t is not None and (t.dtype != dt or not t.is_contiguous()):
+                raise TypeError("%s must be a contiguous float32 tensor" % name)
+        if coef is not None and coef.numel() != MAP_SIZE:
+            raise ValueError("coef must hold %d coefficients" % MAP_SIZE)
+        chi2 = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+        ok = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        total = torch.empty(1, dtype=torch.float64, device=dev)
+        cin, cset = clusters.c_struct(), rset.c_struct(p0)
+        self._check(self.lib.tpcca_refit_fwd(self.h, ctypes.byref(cin), ctypes.byref(cset), _ptr(coef), _ptr(chi2),
+                                             _ptr(ok), _ptr(total), _stream(stream)))
+        self._adj_gen = getattr(self, "_adj_gen", 0) + 1
+        self._adj_hits = rset.n_hits
+        return chi2[:n], ok[:n], total
+
+    def refit_backward(self, grad_chi2, want_map=True, want_hits=False, stream=None):
+        """Gradients (FP64) of sum_t grad_chi2[t] * chi2[t] of the last refit_forward:
+        d/dparams0 (n, 5), d/dcoef (3, 16, 16, 32) or None, d/d(y', z') per cluster slot or None."""
+        torch = _torch()
+        n = int(grad_chi2.numel())
+        dev = grad_chi2.device
+        if grad_chi2.dtype != torch.float32 or not grad_chi2.is_contiguous():
+            raise TypeError("grad_chi2 must be a contiguous float32 tensor")
+        gp = torch.empty((max(n, 1), 5), dtype=torch.float64, device=dev)
+        gm = torch.empty(MAP_SHAPE, dtype=torch.float64, device=dev) if want_map else None
+        nh = getattr(self, "_adj_hits", 0)
+        gh = torch.empty((max(nh, 1), 2), dtype=torch.float64, device=dev) if want_hits else None
+        self._check(self.lib.tpcca_refit_bwd(self.h, _ptr(grad_chi2), _ptr(gp), _ptr(gm), _ptr(gh),
+                                             _stream(stream)))
+        return gp[:n], gm, (gh[:nh] if gh is not None else None)
+
+
+@dataclass
+class RefitSet:
+    """Tracks to refit (device tensors): start state and covariance at row0,
+    instance, CSR of cluster ids (rows strictly increasing) and accept masks."""
+
+    params0: "object"  # float32 [n, 5]
+    cov0: "object"  # float32 [n, 15]
+    row0: "object"  # int32 [n]
+    inst: "object"  # int32 [n]
+    hit_start: "object"  # int64 [n + 1]
+    hit_id: "object"  # int32 [n_hits]
+    hit_mask: "object"  # uint8 [n_hits]
+
+    @property
+    def n_tracks(self) -> int:
+        return int(self.row0.shape[0])
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.hit_id.shape[0])
+
+    def c_struct(self, params0=None) -> RefitSetC:
+        c = RefitSetC()
+        c.n_tracks, c.n_hits = self.n_tracks, self.n_hits
+        c.params0 = _ptr(self.params0 if params0 is None else params0)
+        c.cov0, c.row0, c.inst = _ptr(self.cov0), _ptr(self.row0), _ptr(self.inst)
+        c.hit_start, c.hit_id, c.hit_mask = _ptr(self.hit_start), _ptr(self.hit_id), _ptr(self.hit_mask)
+        return c
+
+    def head(self, n: int) -> "RefitSet":
+        """The first n tracks (views)."""
+        n = min(int(n), self.n_tracks)
+        nh = int(self.hit_start[n])
+        return RefitSet(self.params0[:n], self.cov0[:n], self.row0[:n], self.inst[:n], self.hit_start[:n + 1],
+                        self.hit_id[:nh], self.hit_mask[:nh])
+
+    @classmethod
+    def from_arrays(cls, st0, row0, inst, hit_start, hit_id, hit_mask, device="cuda"):
+        torch = _torch()
+        st0 = np.asarray(st0, np.float32).reshape(-1, 20)
+        return cls(torch.as_tensor(np.ascontiguousarray(st0[:, :5]), device=device),
+                   torch.as_tensor(np.ascontiguousarray(st0[:, 5:]), device=device),
+                   torch.as_tensor(np.asarray(row0, np.int32), device=device),
+                   torch.as_tensor(np.asarray(inst, np.int32), device=device),
+                   torch.as_tensor(np.asarray(hit_start, np.int64), device=device),
+                   torch.as_tensor(np.asarray(hit_id, np.int32), device=device),
+                   torch.as_tensor(np.asarray(hit_mask, np.uint8), device=device))
+
+    @classmethod
+    def from_tracker(cls, tracker: Tracker, device="cuda"):
+        """The output tracks of the tracker's last call: tracklet state at its
+        row as the start, the owned clusters and the masks the refit took."""
+        tl, sel = tracker.export_tracklets(), tracker.export_selected()
+        idx = np.nonzero(sel["status"])[0]
+        hs = sel["hit_start"]
+        lens = hs[idx + 1] - hs[idx]
+        pos = np.concatenate([np.arange(hs[i], hs[i + 1]) for i in idx]) if len(idx) else np.zeros(0, np.int64)
+        tli = sel["sel_tl"][idx]
+        return cls.from_arrays(tl["state"][tli], tl["state_row"][tli], tl["start_inst"][tli],
+                               np.concatenate([[0], np.cumsum(lens)]), sel["hit_id"][pos], sel["mask"][pos],
+                               device=device)
+
+
+def refit_chi2(tracker: Tracker, clusters: DeviceClusters, rset: RefitSet, params0, coef=None):
+    """chi2 per track of the frozen-mask refit as a differentiable torch function
+    of params0 (n, 5) and of the correction map coef (3, 16, 16, 32) or None."""
+    torch = _torch()
+
+    class _RefitChi2(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, p, c):
+            p32 = p.detach().to(torch.float32).contiguous()
+            c32 = None if c is None else c.detach().to(torch.float32).contiguous()
+            chi2, ok, _ = tracker.refit_forward(clusters, rset, p32, c32)
+            fctx.p32, fctx.c32, fctx.gen = p32, c32, tracker._adj_gen
+            fctx.p_shape, fctx.c_shape = p.shape, None if c is None else c.shape
+            fctx.mark_non_differentiable(ok)
+            return chi2.clone(), ok
+
+        @staticmethod
+        def backward(fctx, g, _gok):
+            if tracker._adj_gen != fctx.gen:  # another forward ran since: recompute the checkpoints
+                tracker.refit_forward(clusters, rset, fctx.p32, fctx.c32)
+                fctx.gen = tracker._adj_gen
+            gp, gm, _ = tracker.refit_backward(g.to(torch.float32).contiguous(), want_map=fctx.needs_input_grad[1])
+            return gp.reshape(fctx.p_shape), None if gm is None else gm.reshape(fctx.c_shape)
+
+    return _RefitChi2.apply(params0, coef)
 
 
 def fp32_selfcheck(a, b, stream=None):

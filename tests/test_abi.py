@@ -39,15 +39,17 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tpcca.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tpcca.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %d\\n",'
                    'sizeof(tpcca_params),sizeof(tpcca_tuning),sizeof(tpcca_clusters),sizeof(tpcca_tracks),'
-                   'sizeof(tpcca_stats),offsetof(tpcca_params,bz),offsetof(tpcca_tracks,n_tracks));return 0;}\n')
+                   'sizeof(tpcca_stats),offsetof(tpcca_params,bz),offsetof(tpcca_tracks,n_tracks),'
+                   'sizeof(tpcca_refit_set),offsetof(tpcca_refit_set,hit_mask),TPCCA_MAP_SIZE);return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     from paper_1811_11481_amd import tpcca as T
     want = [ctypes.sizeof(T.Params), ctypes.sizeof(T.Tuning), ctypes.sizeof(T.Clusters), ctypes.sizeof(T.TracksC),
-            ctypes.sizeof(T.Stats), T.Params.bz.offset, T.TracksC.n_tracks.offset]
+            ctypes.sizeof(T.Stats), T.Params.bz.offset, T.TracksC.n_tracks.offset, ctypes.sizeof(T.RefitSetC),
+            T.RefitSetC.hit_mask.offset, T.MAP_SIZE]
     assert got == want
 
 
