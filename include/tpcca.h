@@ -86,7 +86,11 @@ typedef struct {
     int32_t block_tracklet;   /* threads per block of the tracklet kernel (64..256), default 256 */
     int32_t block_refit;      /* threads per block of the refit kernel (64..256), default 128 */
     int32_t block_scan;       /* threads per block of scans/compactions, default 256 */
-    int32_t sort_seeds;       /* 1: process seeds in an order grouped by chain length (default 1) */
+    int32_t sort_seeds;       /* 1: process seeds in an order grouped by chain length (default 0) */
+    int32_t tape_mb;          /* device memory for the differentiable refit's tape [MiB], default 32768;
+                                 a larger set is recomputed batch by batch in tpcca_refit_bwd */
+    int32_t xcd_remap;        /* 1: workgroups renumbered so that each of the 8 XCDs (own L2) works on
+                                 contiguous instances (neighbour and tracklet kernels), default 1 */
 } tpcca_tuning;
 
 /* Input clusters (device pointers, caller-owned). */
@@ -221,24 +225,31 @@ typedef struct {
 } tpcca_refit_set;
 
 /* Forward. map_coef: device [TPCCA_MAP_SIZE] binary32, or NULL (no
- * correction). Outputs: chi2_track [n_tracks] (binary32), track_ok
+ * correction). Outputs: chi2_track [n_tracks] (binary32, the refit's own
+ * arithmetic: without a map it equals the tracker's chi2 bit for bit), track_ok
  * [n_tracks] (1/0, may be NULL), chi2_total [1] (FP64 sum, fixed order).
- * Validates the set on the device (ranges, cluster ids inside their
- * instance, strictly increasing rows): TPCCA_E_ARG otherwise. Synchronises
- * the stream once. Keeps checkpoints of every track in the context for the
- * next tpcca_refit_bwd; the clusters, the set and map_coef must stay
- * unchanged until then. */
+ * Validates the set on the device (ranges, cluster ids inside their instance,
+ * strictly increasing rows): TPCCA_E_ARG otherwise. Synchronises the stream
+ * twice (validation and operation counts, then errors).
+ * record = 1 keeps what tpcca_refit_bwd needs: a tape of every operation's
+ * inputs (covariance and operands, 76 bytes per operation, ~80 KB per track),
+ * or, when the set's tape exceeds tuning.tape_mb, only the operation counts
+ * (the backward then re-runs the forward batch by batch). The clusters, the set
+ * and map_coef must then stay unchanged until tpcca_refit_bwd. record = 0:
+ * forward only. */
 tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* clusters, const tpcca_refit_set* set,
                              const float* map_coef, float* chi2_track, int32_t* track_ok, double* chi2_total,
-                             void* hip_stream);
+                             int32_t record, void* hip_stream);
 
-/* Backward of the last tpcca_refit_fwd on this context, for the loss
+/* Backward of the last recorded tpcca_refit_fwd on this context, for the loss
  * L = sum_t grad_chi2[t] * chi2_track[t]. grad_chi2: device [n_tracks]
  * binary32. Outputs (FP64, device): grad_params0 [n_tracks * 5] = dL/dparams0;
  * grad_map [TPCCA_MAP_SIZE] = dL/dcoef (may be NULL; evaluated at the
  * forward's map, zero map if it was NULL; accumulated with FP64 atomics, so the
  * last bits depend on the order of accumulation); grad_hit_yz [n_hits * 2] =
- * dL/d(y', z') of each corrected cluster (may be NULL). Asynchronous. */
+ * dL/d(y', z') of each corrected cluster (may be NULL). Tracks whose refit
+ * failed get zero gradients. Asynchronous; may be called again (another
+ * grad_chi2) while the recorded forward stays valid. */
 tpcca_status tpcca_refit_bwd(tpcca_ctx* ctx, const float* grad_chi2, double* grad_params0, double* grad_map,
                              double* grad_hit_yz, void* hip_stream);
 

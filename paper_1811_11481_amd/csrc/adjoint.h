@@ -8,15 +8,20 @@
 namespace tpcca {
 
 constexpr int kMapSize = 3 * 16 * 16 * 32;
-constexpr int kCk = 32;         // refit operations per checkpoint segment
-constexpr int kCkWords = 26;    // iterator (4) + state (5) + covariance (15) + reference point (2)
-constexpr int kTapeWords = 19;  // covariance (15) + three operands + operation word
+constexpr int kTapeWords = 20;  // per operation: covariance (15), three operands, operation word, pad
+constexpr int64_t kTapeBytesPerOp = 4 * kTapeWords;
 
 enum : uint32_t {
     AERR_RANGE = 1u,  // hit_start, instance or start row out of range
     AERR_HIT = 2u,    // a cluster id outside its track's instance
     AERR_ROWS = 4u,   // cluster rows of a track not strictly increasing
-    AERR_CKPT = 8u,   // checkpoint bound exceeded (never with valid rows)
+    AERR_TAPE = 8u,   // operation count above the tape stride (never with valid rows)
+};
+
+// words of the small status block (device): error bits, max operation count
+struct AdjStatus {
+    uint32_t err;
+    int32_t max_ops;
 };
 
 struct AdjBufs {
@@ -38,16 +43,15 @@ struct AdjBufs {
     const int32_t* hit_id;
     const uint8_t* hit_mask;
     const float* coef;  // may be null: no correction
-    // scratch (SoA over tracks: word f of slot k of track t at (k * words + f) * n_tracks + t)
-    int32_t* hit_inst;
-    uint8_t* hit_row;
-    float2* hit_yz;
-    double2* hit_grad;
-    int32_t* nops;
-    uint32_t* ckpt;
-    uint32_t* tape;
-    int32_t max_ck;
-    uint32_t* err;
+    // scratch
+    int32_t* hit_inst;    // [n_hits]
+    uint8_t* hit_row;     // [n_hits]
+    float2* hit_yz;       // [n_hits] corrected coordinates
+    double2* hit_grad;    // [3][n_hits] d/d(y', z') per pass
+    int32_t* nops;        // [n_tracks] operations of the last recorded forward (-1: failed)
+    uint32_t* tape;       // operation k of batch track b at word (b * tape_ops + k) * kTapeWords
+    int32_t tape_ops;     // operations per track the tape holds (the set's maximum)
+    AdjStatus* status;
     // outputs
     float* chi2_track;
     int32_t* track_ok;
@@ -59,9 +63,20 @@ struct AdjBufs {
     int32_t adj_f64;
 };
 
-int64_t adj_max_ops(int n_rows);
-void enqueue_adj_clear(const AdjBufs& a, hipStream_t st);
-void enqueue_refit_fwd(const AdjBufs& a, hipStream_t st);
-void enqueue_refit_bwd(const AdjBufs& a, hipStream_t st);
+// Enqueue validation, corrected coordinates and operation counts (status
+// block: error bits and the largest operation count, for the host to size
+// the tape).
+void enqueue_refit_prepare(const AdjBufs& a, hipStream_t st);
+// Forward over tracks [t0, t1): chi2 per track (when `outputs`), operation
+// counts, and the tape of those tracks when a.tape is set.
+void enqueue_refit_forward(const AdjBufs& a, int64_t t0, int64_t t1, bool outputs, hipStream_t st);
+void enqueue_refit_total(const AdjBufs& a, hipStream_t st);
+// Reverse sweep over the taped tracks [t0, t1).
+void enqueue_refit_reverse(const AdjBufs& a, int64_t t0, int64_t t1, hipStream_t st);
+// Map gradient (grad_map) and per-cluster gradient (sum over passes) from the
+// reverse sweeps; the map gradient uses map_grad_scratch_bytes(n_hits) of scratch.
+size_t map_grad_scratch_bytes(int64_t n_hits);
+void enqueue_refit_map_grad(const AdjBufs& a, void* scratch, hipStream_t st);
+void enqueue_refit_hit_grad(const AdjBufs& a, double* out, hipStream_t st);
 
 }  // namespace tpcca

@@ -4,14 +4,16 @@
 // and fitting (the paper applies such calibration corrections there,
 // Sections 1 and 4), and its hand-written reverse-mode adjoint.
 //
-// Forward (binary32, the refit's own arithmetic): one lane per track. The
-// refit is a sequence of operations (row step, covariance reset, cluster
-// update) produced by a small iterator; every kCk operations the lane stores a
-// checkpoint (iterator, state, reference point).
-// Backward: the lane walks its segments last to first, recomputes each
-// segment from its checkpoint into a per-track tape (covariance and operands
-// before every operation), then applies the adjoints of the recorded
-// operations in reverse, in binary32 or binary64.
+// Forward (binary32, the refit's own arithmetic and operation order): one lane
+// per track. Every operation (row step, covariance reset, cluster update)
+// records its inputs on a tape in HBM: the covariance before it and its
+// operands, 76 bytes, stored structure-of-arrays over the tracks of a batch so
+// that a wave's stores coalesce. A 1e5-track set needs ~8 GB of tape, which
+// the 288 GB of HBM3E hold without recomputation; a set above the tape budget
+// is recomputed batch by batch in the backward call.
+// Backward: each lane reads its tape last operation first, prefetching one
+// operation ahead, and applies the adjoints of the recorded operations in
+// binary32 or binary64.
 //
 // Map: components (delta r, delta r*phi, delta z), each a tricubic uniform
 // B-spline with 16 x 16 (periodic in phi) x 32 coefficients [comp][r][phi][z],
@@ -87,96 +89,12 @@ __device__ __forceinline__ ClusterGeo cluster_geo(const AdjBufs& a, int row, int
     return g;
 }
 
-// ------------------------------------------------------------ op iterator
-enum : int { OP_END = 0, OP_PROP = 1, OP_RESET = 2, OP_UPD = 3 };
+// ------------------------------------------------------------ tape
+enum : int { OP_PROP = 1, OP_RESET = 2, OP_UPD = 3 };
 
-struct OpIt {
-    int phase;  // 0: move to the outermost cluster, 1: the three passes, 2: done
-    int pass, q, cur;
-};
-
-struct Op {
-    int kind, from, to, hit, pass;
-};
-
-// Next operation of the frozen-mask refit: move to the outermost cluster,
-// then three passes (inward, outward, inward), each opening with a covariance
-// reset, stepping row by row to every cluster and updating where the pass's
-// mask bit is set.
-__device__ __forceinline__ Op next_op(OpIt& it, int n, const uint8_t* rows, const uint8_t* masks) {
-    Op op{OP_END, 0, 0, 0, 0};
-    for (;;) {
-        if (it.phase == 2) return op;
-        if (it.phase == 0) {
-            const int outer = rows[n - 1];
-            if (it.cur != outer) {
-                op.kind = OP_PROP;
-                op.from = it.cur;
-                op.to = it.cur < outer ? it.cur + 1 : it.cur - 1;
-                it.cur = op.to;
-                return op;
-            }
-            it.phase = 1;
-            it.pass = 0;
-            it.q = 0;
-            op.kind = OP_RESET;
-            return op;
-        }
-        if (it.q == n) {
-            ++it.pass;
-            it.q = 0;
-            if (it.pass == 3) {
-                it.phase = 2;
-                return op;
-            }
-            op.kind = OP_RESET;
-            return op;
-        }
-        const int i = it.pass != 1 ? n - 1 - it.q : it.q;
-        const int target = rows[i];
-        if (it.cur != target) {
-            op.kind = OP_PROP;
-            op.from = it.cur;
-            op.to = it.cur < target ? it.cur + 1 : it.cur - 1;
-            it.cur = op.to;
-            return op;
-        }
-        ++it.q;
-        if ((masks[i] >> it.pass) & 1u) {
-            op.kind = OP_UPD;
-            op.hit = i;
-            op.pass = it.pass;
-            return op;
-        }
-    }
-}
-
-__device__ __forceinline__ uint32_t op_word(const Op& op) {
-    return (uint32_t)op.kind | ((uint32_t)op.pass << 2) | ((uint32_t)op.from << 4) | ((uint32_t)op.to << 12) |
-           ((uint32_t)op.hit << 20);
-}
-
-// One operation on (state, reference point); an update also returns its
-// residual. Returns false when a row step fails (the refit then stops, as the
-// refit itself does).
-__device__ __forceinline__ bool apply_op(const Op& op, KState& s, float& ref_y, float& ref_z, float& chi2,
-                                         const DevConsts& K, const float2* yz, float* r0, float* r1) {
-    if (op.kind == OP_PROP) return kf_propagate(s, K.X[op.from], K.X[op.to], K);
-    if (op.kind == OP_RESET) {
-        kf_reset(s, K);
-        return true;
-    }
-    const float2 m = yz[op.hit];
-    const Innov inn = kf_innovation(s, m.x - ref_y, m.y - ref_z, K);
-    *r0 = inn.r0;
-    *r1 = inn.r1;
-    kf_update(s, inn);
-    s.p[0] = s.p[0] + (ref_y - m.x);
-    s.p[1] = s.p[1] + (ref_z - m.y);
-    ref_y = m.x;
-    ref_z = m.y;
-    if (op.pass == 2) chi2 = chi2 + inn.chi2;
-    return true;
+__device__ __forceinline__ uint32_t op_word(int kind, int pass, int from, int to, int hit) {
+    return (uint32_t)kind | ((uint32_t)pass << 2) | ((uint32_t)from << 4) | ((uint32_t)to << 12) |
+           ((uint32_t)hit << 20);
 }
 
 // ------------------------------------------------------------ dual numbers
@@ -431,7 +349,7 @@ __device__ __forceinline__ void adj_upd(const float C[15], float r0f, float r1f,
 }
 
 // ------------------------------------------------------------ kernels
-__device__ __forceinline__ void set_err(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
+__device__ __forceinline__ void set_err(AdjStatus* st, uint32_t bit) { atomicOr(&st->err, bit); }
 
 // Per track: validate the refit set, tag every cluster slot with its instance.
 __global__ void k_adj_prep(AdjBufs a) {
@@ -445,17 +363,17 @@ __global__ void k_adj_prep(AdjBufs a) {
         if (t == 0 && h0 != 0) ok = false;
         if (t == a.n_tracks - 1 && h1 != a.n_hits) ok = false;
         if (!ok) {
-            set_err(a.err, AERR_RANGE);
+            set_err(a.status, AERR_RANGE);
             continue;
         }
         const int64_t lo = a.row_start[(int64_t)inst * nr], hi = a.row_start[(int64_t)(inst + 1) * nr];
         if (!(lo >= 0 && lo <= hi && hi <= a.n_clusters)) {
-            set_err(a.err, AERR_RANGE);
+            set_err(a.status, AERR_RANGE);
             continue;
         }
         for (int64_t h = h0; h < h1; ++h) {
             const int32_t id = a.hit_id[h];
-            if (id < lo || id >= hi) set_err(a.err, AERR_HIT);
+            if (id < lo || id >= hi) set_err(a.status, AERR_HIT);
             a.hit_inst[h] = inst;
         }
     }
@@ -464,7 +382,7 @@ __global__ void k_adj_prep(AdjBufs a) {
 // Per cluster slot: pad row (search in the instance's row ranges) and the
 // corrected coordinates.
 __global__ void k_map_correct(AdjBufs a) {
-    if (*a.err) return;
+    if (a.status->err) return;
     const int nr = a.n_rows;
     for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < a.n_hits;
          h += (int64_t)gridDim.x * blockDim.x) {
@@ -502,32 +420,70 @@ __global__ void k_map_correct(AdjBufs a) {
     }
 }
 
-__device__ __forceinline__ void put_word(uint32_t* base, int64_t slot, int words, int64_t n, int64_t t, int f,
-                                         uint32_t v) {
-    base[(slot * words + f) * n + t] = v;
-}
-__device__ __forceinline__ uint32_t get_word(const uint32_t* base, int64_t slot, int words, int64_t n, int64_t t,
-                                             int f) {
-    return base[(slot * words + f) * n + t];
+// Per track: rows strictly increasing, and the number of operations of its
+// refit: |row0 - outermost row| row steps and a reset, then per pass the row
+// span in steps, one update per set mask bit and (passes 2 and 3) a reset.
+__global__ void k_adj_count(AdjBufs a) {
+    if (a.status->err) return;
+    int32_t m = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.n_tracks;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t off = a.hit_start[t];
+        const int n = (int)(a.hit_start[t + 1] - off);
+        if (n <= 0) continue;
+        const uint8_t* rows = a.hit_row + off;
+        int used = 0;
+        bool inc = true;
+        for (int i = 0; i < n; ++i) {
+            if (i > 0 && rows[i] <= rows[i - 1]) inc = false;
+            const uint8_t mk = a.hit_mask[off + i];
+            used += (mk & 1u) + ((mk >> 1) & 1u) + ((mk >> 2) & 1u);
+        }
+        if (!inc) {
+            set_err(a.status, AERR_ROWS);
+            continue;
+        }
+        const int span = rows[n - 1] - rows[0];
+        const int d0 = a.row0[t] - rows[n - 1];
+        m = max(m, (d0 < 0 ? -d0 : d0) + 3 + 3 * span + used);
+    }
+    if (m > 0) atomicMax(&a.status->max_ops, m);
 }
 
-__global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a) {
-    if (*a.err) return;
+// Record operation k of a track: five 16-byte words (covariance before it in
+// the first 15 floats, three operands, the operation word); the covariance is
+// skipped for a reset.
+__device__ __forceinline__ void rec_op(uint4* tp, int k, const float* C, bool cov, float o0, float o1, float o2,
+                                       uint32_t ow) {
+    uint4* p = tp + (int64_t)k * (kTapeWords / 4);
+    if (cov) {
+        p[0] = make_uint4(__float_as_uint(C[0]), __float_as_uint(C[1]), __float_as_uint(C[2]), __float_as_uint(C[3]));
+        p[1] = make_uint4(__float_as_uint(C[4]), __float_as_uint(C[5]), __float_as_uint(C[6]), __float_as_uint(C[7]));
+        p[2] = make_uint4(__float_as_uint(C[8]), __float_as_uint(C[9]), __float_as_uint(C[10]),
+                          __float_as_uint(C[11]));
+        p[3] = make_uint4(__float_as_uint(C[12]), __float_as_uint(C[13]), __float_as_uint(C[14]),
+                          __float_as_uint(o0));
+    }
+    p[4] = make_uint4(__float_as_uint(o1), __float_as_uint(o2), ow, 0u);
+}
+
+// The refit of the tracker with given masks, on corrected clusters, over
+// tracks [t0, t1): row steps to the outermost cluster, then three passes
+// (inward, outward, inward) each opening with a covariance reset; the next
+// cluster's row, coordinates and mask are loaded one cluster ahead.
+template <bool kTape>
+__global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_t t1, int outputs) {
+    if (a.status->err) return;
     const DevConsts& K = *a.K;
-    const int64_t N = a.n_tracks;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+    const int cap = a.tape_ops;
+    for (int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t1;
+         t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t off = a.hit_start[t];
         const int n = (int)(a.hit_start[t + 1] - off);
         const uint8_t* rows = a.hit_row + off;
         const uint8_t* masks = a.hit_mask + off;
         const float2* yz = a.hit_yz + off;
-        bool ok = n > 0;
-        for (int i = 1; i < n; ++i)
-            if (rows[i] <= rows[i - 1]) {
-                set_err(a.err, AERR_ROWS);
-                ok = false;
-                break;
-            }
+        uint4* tp = kTape ? (uint4*)a.tape + (t - t0) * (int64_t)cap * (kTapeWords / 4) : nullptr;
         KState s;
 #pragma unroll
         for (int q = 0; q < 5; ++q) s.p[q] = a.params0[t * 5 + q];
@@ -536,121 +492,125 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a) {
         float ref_y = s.p[0], ref_z = s.p[1];
         s.p[0] = 0.0f;
         s.p[1] = 0.0f;
-        OpIt it{0, 0, 0, a.row0[t]};
-        float chi2 = 0.0f, r0, r1;
-        int nops = 0;
-        while (ok) {
-            const OpIt it0 = it;
-            const Op op = next_op(it, n, rows, masks);
-            if (op.kind == OP_END) break;
-            if (nops % kCk == 0) {
-                const int64_t sg = nops / kCk;
-                if (sg >= a.max_ck) {
-                    set_err(a.err, AERR_CKPT);
-                    ok = false;
-                    break;
+        int cur = a.row0[t], k = 0;
+        bool ok = n > 0;
+        float chi2 = 0.0f;
+        auto step_to = [&](int target) {
+            while (ok && cur != target) {
+                const int nx = cur < target ? cur + 1 : cur - 1;
+                if (kTape) {
+                    if (k < cap) rec_op(tp, k, s.C, true, s.p[2], s.p[3], s.p[4], op_word(OP_PROP, 0, cur, nx, 0));
+                    else set_err(a.status, AERR_TAPE);
                 }
-                uint32_t w[kCkWords];
-                w[0] = (uint32_t)it0.phase;
-                w[1] = (uint32_t)it0.pass;
-                w[2] = (uint32_t)it0.q;
-                w[3] = (uint32_t)it0.cur;
-#pragma unroll
-                for (int q = 0; q < 5; ++q) w[4 + q] = __float_as_uint(s.p[q]);
-#pragma unroll
-                for (int q = 0; q < 15; ++q) w[9 + q] = __float_as_uint(s.C[q]);
-                w[24] = __float_as_uint(ref_y);
-                w[25] = __float_as_uint(ref_z);
-#pragma unroll
-                for (int f = 0; f < kCkWords; ++f) put_word(a.ckpt, sg, kCkWords, N, t, f, w[f]);
+                ++k;
+                if (!kf_propagate(s, K.X[cur], K.X[nx], K)) ok = false;
+                else cur = nx;
             }
-            if (!apply_op(op, s, ref_y, ref_z, chi2, K, yz, &r0, &r1)) ok = false;
-            ++nops;
+        };
+        if (ok) step_to(rows[n - 1]);
+        for (int pass = 0; pass < 3 && ok; ++pass) {
+            if (kTape) {
+                if (k < cap) rec_op(tp, k, s.C, false, 0.0f, 0.0f, 0.0f, op_word(OP_RESET, pass, 0, 0, 0));
+                else set_err(a.status, AERR_TAPE);
+            }
+            ++k;
+            kf_reset(s, K);
+            const bool inward = pass != 1;
+            int i_n = inward ? n - 1 : 0;
+            int t_n = rows[i_n];
+            float2 c_n = yz[i_n];
+            uint8_t m_n = masks[i_n];
+            for (int q = 0; q < n && ok; ++q) {
+                const int i = i_n, target = t_n;
+                const float2 c = c_n;
+                const uint8_t mk = m_n;
+                if (q + 1 < n) {
+                    i_n = inward ? n - 2 - q : q + 1;
+                    t_n = rows[i_n];
+                    c_n = yz[i_n];
+                    m_n = masks[i_n];
+                }
+                step_to(target);
+                if (!ok || !((mk >> pass) & 1u)) continue;
+                const Innov inn = kf_innovation(s, c.x - ref_y, c.y - ref_z, K);
+                if (kTape) {
+                    if (k < cap) rec_op(tp, k, s.C, true, inn.r0, inn.r1, 0.0f, op_word(OP_UPD, pass, 0, 0, i));
+                    else set_err(a.status, AERR_TAPE);
+                }
+                ++k;
+                kf_update(s, inn);
+                s.p[0] = s.p[0] + (ref_y - c.x);
+                s.p[1] = s.p[1] + (ref_z - c.y);
+                ref_y = c.x;
+                ref_z = c.y;
+                if (pass == 2) chi2 = chi2 + inn.chi2;
+            }
         }
-        a.nops[t] = ok ? nops : -1;
-        a.chi2_track[t] = ok ? chi2 : 0.0f;
-        if (a.track_ok) a.track_ok[t] = ok ? 1 : 0;
+        a.nops[t] = ok ? k : -1;
+        if (outputs) {
+            a.chi2_track[t] = ok ? chi2 : 0.0f;
+            if (a.track_ok) a.track_ok[t] = ok ? 1 : 0;
+        }
     }
 }
 
+__device__ __forceinline__ void load_op(const uint4* tp, int k, uint4 w[kTapeWords / 4]) {
+    const uint4* p = tp + (int64_t)k * (kTapeWords / 4);
+#pragma unroll
+    for (int f = 0; f < kTapeWords / 4; ++f) w[f] = p[f];
+}
+
+// Reverse sweep over the taped tracks [t0, t1), one lane per track.
 template <class A>
-__global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a) {
+__global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_t t1) {
     const DevConsts& K = *a.K;
-    const int64_t N = a.n_tracks;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t NH = a.n_hits;
+    for (int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t1;
+         t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t off = a.hit_start[t];
         const int n = (int)(a.hit_start[t + 1] - off);
-        double2* gm = a.hit_grad + off;
-        for (int i = 0; i < n; ++i) gm[i] = make_double2(0.0, 0.0);
+        for (int p = 0; p < 3; ++p)
+            for (int i = 0; i < n; ++i) a.hit_grad[p * NH + off + i] = make_double2(0.0, 0.0);
         const int nops = a.nops[t];
         double* gp = a.grad_params + t * 5;
         if (nops <= 0) {
             for (int q = 0; q < 5; ++q) gp[q] = 0.0;
             continue;
         }
-        const uint8_t* rows = a.hit_row + off;
-        const uint8_t* masks = a.hit_mask + off;
-        const float2* yz = a.hit_yz + off;
+        const uint4* tp = (const uint4*)a.tape + (t - t0) * (int64_t)a.tape_ops * (kTapeWords / 4);
         const A cb = A(a.grad_chi2[t]);
         A pb[5], Cb[15];
 #pragma unroll
         for (int q = 0; q < 5; ++q) pb[q] = A(0);
 #pragma unroll
         for (int q = 0; q < 15; ++q) Cb[q] = A(0);
-        const int nseg = (nops + kCk - 1) / kCk;
-        for (int sg = nseg - 1; sg >= 0; --sg) {
-            uint32_t w[kCkWords];
+        uint4 nxt[kTapeWords / 4];
+        load_op(tp, nops - 1, nxt);
+        for (int k = nops - 1; k >= 0; --k) {
+            uint4 v[kTapeWords / 4];
 #pragma unroll
-            for (int f = 0; f < kCkWords; ++f) w[f] = get_word(a.ckpt, sg, kCkWords, N, t, f);
-            OpIt it{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-            KState s;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) s.p[q] = __uint_as_float(w[4 + q]);
-#pragma unroll
-            for (int q = 0; q < 15; ++q) s.C[q] = __uint_as_float(w[9 + q]);
-            float ref_y = __uint_as_float(w[24]), ref_z = __uint_as_float(w[25]), chi2 = 0.0f;
-            const int len = min(kCk, nops - sg * kCk);
-            // recompute the segment, recording each operation's inputs:
-            // covariance, then (sin phi, tan lambda, q/pT) of a row step or the
-            // residual of an update
-            for (int k = 0; k < len; ++k) {
-                const Op op = next_op(it, n, rows, masks);
-#pragma unroll
-                for (int q = 0; q < 15; ++q) put_word(a.tape, k, kTapeWords, N, t, q, __float_as_uint(s.C[q]));
-                float o0 = s.p[2], o1 = s.p[3];
-                const float o2 = s.p[4];
-                apply_op(op, s, ref_y, ref_z, chi2, K, yz, &o0, &o1);
-                put_word(a.tape, k, kTapeWords, N, t, 15, __float_as_uint(o0));
-                put_word(a.tape, k, kTapeWords, N, t, 16, __float_as_uint(o1));
-                put_word(a.tape, k, kTapeWords, N, t, 17, __float_as_uint(o2));
-                put_word(a.tape, k, kTapeWords, N, t, 18, op_word(op));
+            for (int f = 0; f < kTapeWords / 4; ++f) v[f] = nxt[f];
+            if (k > 0) load_op(tp, k - 1, nxt);  // in flight while this operation is differentiated
+            const uint32_t ow = v[4].z;
+            const int kind = (int)(ow & 3u);
+            if (kind == OP_RESET) {
+                adj_reset(Cb, K);
+                continue;
             }
-            // reverse sweep
-            for (int k = len - 1; k >= 0; --k) {
-                const uint32_t ow = get_word(a.tape, k, kTapeWords, N, t, 18);
-                const int kind = (int)(ow & 3u);
-                if (kind == OP_RESET) {
-                    adj_reset(Cb, K);
-                    continue;
-                }
-                float C[15];
-#pragma unroll
-                for (int q = 0; q < 15; ++q) C[q] = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, q));
-                const float o0 = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, 15));
-                const float o1 = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, 16));
-                if (kind == OP_PROP) {
-                    const float o2 = __uint_as_float(get_word(a.tape, k, kTapeWords, N, t, 17));
-                    const int from = (int)((ow >> 4) & 255u), to = (int)((ow >> 12) & 255u);
-                    adj_prop<A>(C, o0, o1, o2, K.X[to] - K.X[from], pb, Cb, K);
-                } else {
-                    const int hit = (int)((ow >> 20) & 255u), pass = (int)((ow >> 2) & 3u);
-                    A mb0 = A(0), mb1 = A(0);
-                    adj_upd<A>(C, o0, o1, pb, Cb, mb0, mb1, pass == 2 ? cb : A(0), K);
-                    double2 g = gm[hit];
-                    g.x += (double)mb0;
-                    g.y += (double)mb1;
-                    gm[hit] = g;
-                }
+            const float C[15] = {__uint_as_float(v[0].x), __uint_as_float(v[0].y), __uint_as_float(v[0].z),
+                                 __uint_as_float(v[0].w), __uint_as_float(v[1].x), __uint_as_float(v[1].y),
+                                 __uint_as_float(v[1].z), __uint_as_float(v[1].w), __uint_as_float(v[2].x),
+                                 __uint_as_float(v[2].y), __uint_as_float(v[2].z), __uint_as_float(v[2].w),
+                                 __uint_as_float(v[3].x), __uint_as_float(v[3].y), __uint_as_float(v[3].z)};
+            const float o0 = __uint_as_float(v[3].w), o1 = __uint_as_float(v[4].x);
+            if (kind == OP_PROP) {
+                const int from = (int)((ow >> 4) & 255u), to = (int)((ow >> 12) & 255u);
+                adj_prop<A>(C, o0, o1, __uint_as_float(v[4].y), K.X[to] - K.X[from], pb, Cb, K);
+            } else {
+                const int hit = (int)((ow >> 20) & 255u), pass = (int)((ow >> 2) & 3u);
+                A mb0 = A(0), mb1 = A(0);
+                adj_upd<A>(C, o0, o1, pb, Cb, mb0, mb1, pass == 2 ? cb : A(0), K);
+                a.hit_grad[pass * NH + off + hit] = make_double2((double)mb0, (double)mb1);
             }
         }
 #pragma unroll
@@ -658,28 +618,159 @@ __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a) {
     }
 }
 
+__device__ __forceinline__ double2 hit_grad_sum(const AdjBufs& a, int64_t h) {
+    const double2 g0 = a.hit_grad[h], g1 = a.hit_grad[a.n_hits + h], g2 = a.hit_grad[2 * a.n_hits + h];
+    return make_double2((g0.x + g1.x) + g2.x, (g0.y + g1.y) + g2.y);
+}
+
+__global__ void k_hit_grad_out(AdjBufs a, double2* out) {
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < a.n_hits;
+         h += (int64_t)gridDim.x * blockDim.x)
+        out[h] = hit_grad_sum(a, h);
+}
+
 // d loss / d coef: each cluster slot adds its (d/dy', d/dz') times the
-// derivative of (y', z') with respect to the coefficients of its map cell.
-__global__ void k_map_grad(AdjBufs a) {
+// derivative of (y', z') with respect to the 3 x 64 coefficients of its map
+// cell. Two kernels:
+// * k_grad_cells, one lane per cluster slot: cell, the 12 B-spline weights and
+//   the three component factors into an 80-byte record (cell -1: no gradient);
+// * k_map_scatter, kMapScatterHits slots per workgroup: the box of coefficients
+//   the slots touch (r, phi relative to the first slot's cell, z) accumulates
+//   in LDS, cut into z slabs when it exceeds kMapGradLds doubles; each wave
+//   stages 64 records in LDS with one coalesced load, then takes one slot at
+//   a time and its 64 lanes add the slot's 4 x 4 x 4 cube (lane = (i, j, e)),
+//   so a wave's LDS atomics never share an address; the box's non-zero
+//   entries then go to the global gradient with FP64 atomics.
+// Tracks of one sector touch ~5 of 16 phi and half of the z coefficients: the
+// global atomics drop from 192 per cluster to about one box per workgroup.
+constexpr int kMapScatterHits = 4096;
+constexpr int kMapScatterThreads = 256;
+constexpr int kMapGradLds = 7168;  // doubles (56 KB; with the staging buffer two workgroups fit a CU)
+
+struct GradRec {  // 80 bytes
+    int32_t cell;  // ir | iphi << 8 | iz << 16 (first coefficient along each axis, iphi + 1 in 0..15), -1: none
+    float wr[4], wphi[4], wz[4];
+    int32_t pad;
+    double gc[3];
+};
+
+__global__ void k_grad_cells(AdjBufs a, GradRec* rec) {
     for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < a.n_hits;
          h += (int64_t)gridDim.x * blockDim.x) {
-        const double2 g = a.hit_grad[h];
-        if (g.x == 0.0 && g.y == 0.0) continue;
-        const int32_t id = a.hit_id[h];
-        const float y = a.y[id], z = a.z[id];
-        const ClusterGeo geo = cluster_geo(a, a.hit_row[h], a.hit_inst[h], y);
-        const MapCell c = map_cell(geo.r, geo.phi, z);
-        const double gc[3] = {-g.x * (double)y / (double)geo.r, -g.x * (double)geo.x / (double)geo.r, -g.y};
-        for (int comp = 0; comp < 3; ++comp) {
-            if (gc[comp] == 0.0) continue;
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) {
-                    const double wij = gc[comp] * (double)c.wr[i] * (double)c.wphi[j];
-                    double* dst = a.grad_map + map_index(comp, c.ir + i, c.iphi + j, c.iz);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) unsafeAtomicAdd(dst + e, wij * (double)c.wz[e]);
-                }
+        const double2 g = hit_grad_sum(a, h);
+        GradRec r;
+        if (g.x == 0.0 && g.y == 0.0) {
+            r.cell = -1;
+            for (int i = 0; i < 4; ++i) r.wr[i] = r.wphi[i] = r.wz[i] = 0.0f;
+            r.gc[0] = r.gc[1] = r.gc[2] = 0.0;
+        } else {
+            const int32_t id = a.hit_id[h];
+            const float y = a.y[id], z = a.z[id];
+            const ClusterGeo geo = cluster_geo(a, a.hit_row[h], a.hit_inst[h], y);
+            const MapCell c = map_cell(geo.r, geo.phi, z);
+            r.cell = c.ir | ((c.iphi + 1) << 8) | (c.iz << 16);
+            for (int i = 0; i < 4; ++i) {
+                r.wr[i] = c.wr[i];
+                r.wphi[i] = c.wphi[i];
+                r.wz[i] = c.wz[i];
+            }
+            // y' = y - (dr y + drphi x) / r, z' = z - dz
+            r.gc[0] = -g.x * (double)y / (double)geo.r;
+            r.gc[1] = -g.x * (double)geo.x / (double)geo.r;
+            r.gc[2] = -g.y;
         }
+        r.pad = 0;
+        rec[h] = r;
+    }
+}
+
+__device__ __forceinline__ int wrap_dphi(int ip, int ref) {
+    return ((ip - ref + 2 * kMapNphi + kMapNphi / 2) % kMapNphi) - kMapNphi / 2;  // in [-8, 8)
+}
+
+__global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, const GradRec* rec) {
+    __shared__ double acc[kMapGradLds];
+    __shared__ GradRec stage[kMapScatterThreads / 64][64];
+    __shared__ int lo[3], hi[3], ref;
+    const int64_t h0 = (int64_t)blockIdx.x * kMapScatterHits;
+    const int64_t h1 = min(h0 + (int64_t)kMapScatterHits, a.n_hits);
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = 1 << 30;
+            hi[d] = -(1 << 30);
+        }
+        ref = -1;
+    }
+    __syncthreads();
+    // reference phi cell: that of the first slot with a gradient (any one would do)
+    for (int64_t h = h0 + threadIdx.x; h < h1; h += blockDim.x)
+        if (rec[h].cell >= 0) {
+            if (ref < 0) atomicCAS(&ref, -1, (rec[h].cell >> 8) & 255);
+            break;
+        }
+    __syncthreads();
+    const int rf = ref;
+    if (rf < 0) return;  // no slot with a gradient (uniform)
+    for (int64_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
+        const int cell = rec[h].cell;
+        if (cell < 0) continue;
+        const int ir = cell & 255, ip = (cell >> 8) & 255, iz = cell >> 16;
+        const int dp = wrap_dphi(ip, rf);
+        atomicMin(&lo[0], ir);
+        atomicMax(&hi[0], ir + 3);
+        atomicMin(&lo[1], dp - 1);
+        atomicMax(&hi[1], dp + 2);
+        atomicMin(&lo[2], iz);
+        atomicMax(&hi[2], iz + 3);
+    }
+    __syncthreads();
+    const int lr = lo[0], nr = hi[0] - lo[0] + 1;
+    const bool full_phi = hi[1] - lo[1] + 1 >= kMapNphi;
+    const int lp = full_phi ? 0 : lo[1], np = full_phi ? kMapNphi : hi[1] - lo[1] + 1;
+    const int lz = lo[2], hz = hi[2];
+    const int slab = 3 * nr * np;        // <= 3 * 16 * 16 = 768
+    const int nzt = kMapGradLds / slab;  // >= 9
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int li = lane >> 4, lj = (lane >> 2) & 3, le = lane & 3;
+    for (int z0 = lz; z0 <= hz; z0 += nzt) {
+        const int nz = min(nzt, hz - z0 + 1);
+        const int size = slab * nz;
+        for (int i = threadIdx.x; i < size; i += blockDim.x) acc[i] = 0.0;
+        __syncthreads();
+        // each wave stages 64 records with one coalesced load, then adds
+        // them one at a time from LDS
+        for (int64_t hw = h0 + (int64_t)wave * 64; hw < h1; hw += (int64_t)nwave * 64) {
+            const int64_t hl = hw + lane;
+            if (hl < h1) stage[wave][lane] = rec[hl];
+            __builtin_amdgcn_wave_barrier();
+            const int cnt = (int)min((int64_t)64, h1 - hw);
+            for (int k = 0; k < cnt; ++k) {
+                const GradRec& r = stage[wave][k];
+                const int cell = r.cell;
+                if (cell < 0) continue;
+                const int ir = cell & 255, ip = (cell >> 8) & 255, iz = cell >> 16;
+                const int zz = iz + le - z0;
+                if (zz < 0 || zz >= nz) continue;
+                const int pj = full_phi ? (ip - 1 + lj + kMapNphi) % kMapNphi : wrap_dphi(ip, rf) - 1 + lj - lp;
+                const double w = (double)r.wr[li] * (double)r.wphi[lj] * (double)r.wz[le];
+                const int base = ((ir + li - lr) * np + pj) * nz + zz;
+                const int cstride = nr * np * nz;
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) atomicAdd(&acc[comp * cstride + base], r.gc[comp] * w);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < size; i += blockDim.x) {
+            const double v = acc[i];
+            if (v == 0.0) continue;
+            const int zz = i % nz, rest = i / nz;
+            const int pj = rest % np, rest2 = rest / np;
+            const int rr = rest2 % nr, comp = rest2 / nr;
+            const int iphi = full_phi ? pj : rf + lp + pj;  // map_index wraps it
+            unsafeAtomicAdd(a.grad_map + map_index(comp, lr + rr, iphi, z0 + zz), v);
+        }
+        __syncthreads();
     }
 }
 
@@ -687,7 +778,8 @@ __global__ void k_map_grad(AdjBufs a) {
 __global__ void k_sum_chi2(AdjBufs a) {
     __shared__ double sh[1024];
     double acc = 0.0;
-    for (int64_t t = threadIdx.x; t < a.n_tracks; t += blockDim.x) acc += (double)a.chi2_track[t];
+    if (!a.status->err)
+        for (int64_t t = threadIdx.x; t < a.n_tracks; t += blockDim.x) acc += (double)a.chi2_track[t];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
@@ -702,8 +794,11 @@ __global__ void k_fill_f64(double* p, int64_t n) {
         p[i] = 0.0;
 }
 
-__global__ void k_clear_err(uint32_t* err) {
-    if (threadIdx.x == 0) err[0] = 0u;
+__global__ void k_clear_status(AdjStatus* st) {
+    if (threadIdx.x == 0) {
+        st->err = 0u;
+        st->max_ops = 0;
+    }
 }
 
 inline int blocks_for(int64_t n, int block, int cap) {
@@ -715,39 +810,53 @@ inline int blocks_for(int64_t n, int block, int cap) {
 
 }  // namespace
 
-int64_t adj_max_ops(int n_rows) {
-    // strictly increasing cluster rows: at most n_rows - 1 row steps to reach
-    // the outermost cluster and per pass, n_rows updates per pass, 3 resets
-    return 4 * (int64_t)(n_rows - 1) + 3 * (int64_t)n_rows + 3;
+void enqueue_refit_prepare(const AdjBufs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, a.status);
+    if (a.n_tracks == 0) return;
+    hipLaunchKernelGGL(k_adj_prep, dim3(blocks_for(a.n_tracks, 256, 16384)), dim3(256), 0, st, a);
+    if (a.n_hits > 0)
+        hipLaunchKernelGGL(k_map_correct, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_count, dim3(blocks_for(a.n_tracks, 256, 4096)), dim3(256), 0, st, a);
 }
 
-void enqueue_adj_clear(const AdjBufs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, st, a.err);
+void enqueue_refit_forward(const AdjBufs& a, int64_t t0, int64_t t1, bool outputs, hipStream_t st) {
+    if (t1 <= t0) return;
+    const dim3 g(blocks_for(t1 - t0, 128, 16384)), b(128);
+    if (a.tape)
+        hipLaunchKernelGGL(k_refit_fwd<true>, g, b, 0, st, a, t0, t1, outputs ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_refit_fwd<false>, g, b, 0, st, a, t0, t1, outputs ? 1 : 0);
 }
 
-void enqueue_refit_fwd(const AdjBufs& a, hipStream_t st) {
-    if (a.n_tracks > 0) {
-        hipLaunchKernelGGL(k_adj_prep, dim3(blocks_for(a.n_tracks, 256, 16384)), dim3(256), 0, st, a);
-        if (a.n_hits > 0)
-            hipLaunchKernelGGL(k_map_correct, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a);
-        hipLaunchKernelGGL(k_refit_fwd, dim3(blocks_for(a.n_tracks, 128, 16384)), dim3(128), 0, st, a);
-    }
+void enqueue_refit_total(const AdjBufs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_sum_chi2, dim3(1), dim3(1024), 0, st, a);
 }
 
-void enqueue_refit_bwd(const AdjBufs& a, hipStream_t st) {
-    if (a.n_tracks > 0) {
-        if (a.adj_f64)
-            hipLaunchKernelGGL(k_refit_bwd<double>, dim3(blocks_for(a.n_tracks, 128, 16384)), dim3(128), 0, st, a);
-        else
-            hipLaunchKernelGGL(k_refit_bwd<float>, dim3(blocks_for(a.n_tracks, 128, 16384)), dim3(128), 0, st, a);
-    }
-    if (a.grad_map) {
-        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(kMapSize, 256, 1024)), dim3(256), 0, st, a.grad_map,
-                           (int64_t)kMapSize);
-        if (a.n_hits > 0)
-            hipLaunchKernelGGL(k_map_grad, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a);
-    }
+void enqueue_refit_reverse(const AdjBufs& a, int64_t t0, int64_t t1, hipStream_t st) {
+    if (t1 <= t0) return;
+    const dim3 g(blocks_for(t1 - t0, 128, 16384)), b(128);
+    if (a.adj_f64)
+        hipLaunchKernelGGL(k_refit_bwd<double>, g, b, 0, st, a, t0, t1);
+    else
+        hipLaunchKernelGGL(k_refit_bwd<float>, g, b, 0, st, a, t0, t1);
+}
+
+size_t map_grad_scratch_bytes(int64_t n_hits) { return sizeof(GradRec) * (size_t)n_hits; }
+
+void enqueue_refit_map_grad(const AdjBufs& a, void* scratch, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(kMapSize, 256, 1024)), dim3(256), 0, st, a.grad_map,
+                       (int64_t)kMapSize);
+    if (a.n_hits <= 0) return;
+    GradRec* rec = (GradRec*)scratch;
+    hipLaunchKernelGGL(k_grad_cells, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a, rec);
+    hipLaunchKernelGGL(k_map_scatter, dim3((unsigned)((a.n_hits + kMapScatterHits - 1) / kMapScatterHits)),
+                       dim3(kMapScatterThreads), 0, st, a, (const GradRec*)rec);
+}
+
+void enqueue_refit_hit_grad(const AdjBufs& a, double* out, hipStream_t st) {
+    if (a.n_hits > 0)
+        hipLaunchKernelGGL(k_hit_grad_out, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a,
+                           (double2*)out);
 }
 
 }  // namespace tpcca

@@ -68,13 +68,17 @@ struct tpcca_ctx {
     hipStream_t own_stream = nullptr;
     bool events = false;
     float stage_ms[8] = {};
-    // differentiable refit: scratch, error word, last forward
+    // differentiable refit: per-track / per-cluster scratch, tape, status, last forward
     void* adj_base = nullptr;
     size_t adj_bytes = 0;
     int64_t adj_cap_t = -1, adj_cap_h = -1;
-    uint32_t* h_adj_err = nullptr;  // pinned
+    void* tape_base = nullptr;
+    size_t tape_bytes = 0;
+    AdjStatus* h_adj_status = nullptr;  // pinned
     AdjBufs adj{};
-    bool adj_valid = false;
+    bool adj_valid = false;   // a recorded forward is available to tpcca_refit_bwd
+    bool adj_taped = false;   // ... and its tape covers the whole set
+    int64_t adj_batch = 0;    // tracks per batch when the backward recomputes
 };
 
 namespace {
@@ -148,6 +152,8 @@ tpcca_status check_tuning(tpcca_ctx* ctx, const tpcca_tuning& t) {
         return fail(ctx, TPCCA_E_ARG, "block sizes must be multiples of 64 in [64, 1024]");
     if (t.block_tracklet > 256 || t.block_refit > 256)
         return fail(ctx, TPCCA_E_ARG, "tracklet and refit blocks hold at most 256 threads");
+    if (t.tape_mb < 1) return fail(ctx, TPCCA_E_ARG, "tape_mb must be >= 1");
+    if (t.xcd_remap != 0 && t.xcd_remap != 1) return fail(ctx, TPCCA_E_ARG, "xcd_remap must be 0 or 1");
     return TPCCA_OK;
 }
 
@@ -324,7 +330,7 @@ Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out
 }
 
 Launch make_launch(const tpcca_tuning& t) {
-    return Launch{t.block_links, t.block_tracklet, t.block_refit, t.block_scan, t.sort_seeds};
+    return Launch{t.block_links, t.block_tracklet, t.block_refit, t.block_scan, t.sort_seeds, t.xcd_remap};
 }
 
 // The whole pipeline for instances [i0, i1) with clusters [c0, c1).
@@ -427,7 +433,8 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
     const void* ps[12] = {in->inst_sector, in->row_start, in->y, in->z, out->inst, out->param,
                           out->cov, out->hit_start, out->hit_id, out->chi2_total, ctx->arena.base, (void*)st};
     std::memcpy(key.p, ps, sizeof(ps));
-    const int64_t vs[8] = {in->n_inst, N, out->cap_tracks, out->cap_hits, ctx->tuning.hits_per_bin,
+    const int64_t vs[8] = {in->n_inst, N, out->cap_tracks, out->cap_hits,
+                           ctx->tuning.hits_per_bin * 4 + ctx->tuning.xcd_remap * 2 + ctx->tuning.sort_seeds,
                            ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
                            ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
                            (int64_t)(intptr_t)out->x_ref ^ (int64_t)(intptr_t)out->chi2};
@@ -464,21 +471,19 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
 namespace {
 
 struct AdjLayout {
-    size_t o_inst, o_row, o_yz, o_grad, o_nops, o_ckpt, o_tape, o_err, total;
+    size_t o_inst, o_row, o_yz, o_grad, o_rec, o_nops, o_status, total;
 };
 
-AdjLayout adj_layout(int64_t cap_t, int64_t cap_h, int n_rows) {
-    const int64_t max_ck = (adj_max_ops(n_rows) + kCk - 1) / kCk;
+AdjLayout adj_layout(int64_t cap_t, int64_t cap_h) {
     Layout L;
     AdjLayout a;
     a.o_inst = L.add(4 * cap_h);
     a.o_row = L.add(cap_h);
     a.o_yz = L.add(8 * cap_h);
-    a.o_grad = L.add(16 * cap_h);
+    a.o_grad = L.add(3 * 16 * cap_h);
+    a.o_rec = L.add(map_grad_scratch_bytes(cap_h));
     a.o_nops = L.add(4 * cap_t);
-    a.o_ckpt = L.add((size_t)4 * kCkWords * max_ck * cap_t);
-    a.o_tape = L.add((size_t)4 * kTapeWords * kCk * cap_t);
-    a.o_err = L.add(256);
+    a.o_status = L.add(256);
     a.total = L.total;
     return a;
 }
@@ -486,7 +491,8 @@ AdjLayout adj_layout(int64_t cap_t, int64_t cap_h, int n_rows) {
 tpcca_status ensure_adj_arena(tpcca_ctx* ctx, int64_t nt, int64_t nh) {
     if (ctx->adj_base && nt <= ctx->adj_cap_t && nh <= ctx->adj_cap_h) return TPCCA_OK;
     const int64_t ct = std::max(nt, ctx->adj_cap_t), ch = std::max(nh, ctx->adj_cap_h);
-    const AdjLayout L = adj_layout(ct, ch, ctx->params.n_rows);
+    const AdjLayout L = adj_layout(ct, ch);
+    ctx->adj_valid = false;
     if (ctx->adj_base) {
         HIP_TRY(hipDeviceSynchronize());
         HIP_TRY(hipFree(ctx->adj_base));
@@ -501,6 +507,38 @@ tpcca_status ensure_adj_arena(tpcca_ctx* ctx, int64_t nt, int64_t nh) {
     ctx->adj_bytes = L.total;
     ctx->adj_cap_t = ct;
     ctx->adj_cap_h = ch;
+    return TPCCA_OK;
+}
+
+tpcca_status ensure_tape(tpcca_ctx* ctx, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (ctx->tape_base && bytes <= ctx->tape_bytes) return TPCCA_OK;
+    ctx->adj_valid = false;
+    if (ctx->tape_base) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(ctx->tape_base));
+        ctx->tape_base = nullptr;
+        ctx->tape_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->tape_base, bytes);
+    if (e != hipSuccess) {
+        ctx->tape_base = nullptr;
+        return hip_fail(ctx, e, "refit tape allocation");
+    }
+    ctx->tape_bytes = bytes;
+    return TPCCA_OK;
+}
+
+tpcca_status read_adj_status(tpcca_ctx* ctx, const AdjBufs& a, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(ctx->h_adj_status, a.status, sizeof(AdjStatus), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    const uint32_t err = ctx->h_adj_status->err;
+    if (err & AERR_RANGE)
+        return fail(ctx, TPCCA_E_ARG, "refit set: hit_start, instance, start row or row_start out of range");
+    if (err & AERR_HIT) return fail(ctx, TPCCA_E_ARG, "refit set: a cluster id lies outside its track's instance");
+    if (err & AERR_ROWS) return fail(ctx, TPCCA_E_ARG, "refit set: cluster rows of a track not strictly increasing");
+    if (err) return fail(ctx, TPCCA_E_INTERNAL, "refit tape bound exceeded");
     return TPCCA_OK;
 }
 
@@ -545,6 +583,8 @@ tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
     t->block_refit = 128;
     t->block_scan = 256;
     t->sort_seeds = 0;
+    t->tape_mb = 32768;
+    t->xcd_remap = 1;
     return TPCCA_OK;
 }
 
@@ -602,7 +642,8 @@ void tpcca_destroy(tpcca_ctx* ctx) {
     if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
     if (ctx->arena.base) hipFree(ctx->arena.base);
     if (ctx->adj_base) hipFree(ctx->adj_base);
-    if (ctx->h_adj_err) hipHostFree(ctx->h_adj_err);
+    if (ctx->tape_base) hipFree(ctx->tape_base);
+    if (ctx->h_adj_status) hipHostFree(ctx->h_adj_status);
     if (ctx->dK) hipFree(ctx->dK);
     if (ctx->dctr) hipFree(ctx->dctr);
     if (ctx->hctr) hipHostFree(ctx->hctr);
@@ -828,7 +869,7 @@ tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div
 
 tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_refit_set* set,
                              const float* map_coef, float* chi2_track, int32_t* track_ok, double* chi2_total,
-                             void* hip_stream) {
+                             int32_t record, void* hip_stream) {
     if (!ctx) return TPCCA_E_ARG;
     ctx->adj_valid = false;
     if (!in || !set || !chi2_total) return fail(ctx, TPCCA_E_ARG, "null clusters, refit set or chi2_total");
@@ -845,10 +886,11 @@ tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* in, const tpc
     if (nt == 0 && nh != 0) return fail(ctx, TPCCA_E_ARG, "clusters given without tracks");
     hipStream_t st = (hipStream_t)hip_stream;
     HIP_TRY(hipSetDevice(ctx->device));
-    if (!ctx->h_adj_err) HIP_TRY(hipHostMalloc((void**)&ctx->h_adj_err, 256, hipHostMallocDefault));
+    if (!ctx->h_adj_status)
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_adj_status, sizeof(AdjStatus), hipHostMallocDefault));
     tpcca_status s = ensure_adj_arena(ctx, std::max<int64_t>(nt, 1), std::max<int64_t>(nh, 1));
     if (s != TPCCA_OK) return s;
-    const AdjLayout L = adj_layout(ctx->adj_cap_t, ctx->adj_cap_h, ctx->params.n_rows);
+    const AdjLayout L = adj_layout(ctx->adj_cap_t, ctx->adj_cap_h);
     char* base = (char*)ctx->adj_base;
     AdjBufs a{};
     a.K = ctx->dK;
@@ -874,27 +916,33 @@ tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* in, const tpc
     a.hit_yz = (float2*)(base + L.o_yz);
     a.hit_grad = (double2*)(base + L.o_grad);
     a.nops = (int32_t*)(base + L.o_nops);
-    a.ckpt = (uint32_t*)(base + L.o_ckpt);
-    a.tape = (uint32_t*)(base + L.o_tape);
-    a.max_ck = (int32_t)((adj_max_ops(ctx->params.n_rows) + kCk - 1) / kCk);
-    a.err = (uint32_t*)(base + L.o_err);
+    a.status = (AdjStatus*)(base + L.o_status);
     a.chi2_track = chi2_track;
     a.track_ok = track_ok;
     a.chi2_total = chi2_total;
     a.adj_f64 = (ctx->params.flags & TPCCA_FLAG_ADJOINT_F64) ? 1 : 0;
-    enqueue_adj_clear(a, st);
-    enqueue_refit_fwd(a, st);
-    HIP_TRY(hipMemcpyAsync(ctx->h_adj_err, a.err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));
-    const uint32_t err = ctx->h_adj_err[0];
-    if (err & AERR_RANGE)
-        return fail(ctx, TPCCA_E_ARG, "refit set: hit_start, instance, start row or row_start out of range");
-    if (err & AERR_HIT) return fail(ctx, TPCCA_E_ARG, "refit set: a cluster id lies outside its track's instance");
-    if (err & AERR_ROWS) return fail(ctx, TPCCA_E_ARG, "refit set: cluster rows of a track not strictly increasing");
-    if (err) return fail(ctx, TPCCA_E_INTERNAL, "refit checkpoint bound exceeded");
+    // validation, corrected clusters, operation counts; the host sizes the tape
+    enqueue_refit_prepare(a, st);
+    s = read_adj_status(ctx, a, st);
+    if (s != TPCCA_OK) return s;
+    a.tape_ops = ctx->h_adj_status->max_ops;
+    const int64_t per_track = std::max<int64_t>(1, (int64_t)a.tape_ops * kTapeBytesPerOp);
+    const int64_t budget = (int64_t)ctx->tuning.tape_mb << 20;
+    const int64_t batch = std::min<int64_t>(std::max<int64_t>(1, budget / per_track), std::max<int64_t>(nt, 1));
+    const bool taped = record && batch >= nt;
+    if (taped) {
+        s = ensure_tape(ctx, (size_t)(per_track * std::max<int64_t>(nt, 1)));
+        if (s != TPCCA_OK) return s;
+        a.tape = (uint32_t*)ctx->tape_base;
+    }
+    enqueue_refit_forward(a, 0, nt, true, st);
+    enqueue_refit_total(a, st);
+    s = read_adj_status(ctx, a, st);
+    if (s != TPCCA_OK) return s;
     ctx->adj = a;
-    ctx->adj_valid = true;
+    ctx->adj_valid = record != 0;
+    ctx->adj_taped = taped;
+    ctx->adj_batch = batch;
     ctx->err.clear();
     return TPCCA_OK;
 }
@@ -902,7 +950,7 @@ tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* in, const tpc
 tpcca_status tpcca_refit_bwd(tpcca_ctx* ctx, const float* grad_chi2, double* grad_params0, double* grad_map,
                              double* grad_hit_yz, void* hip_stream) {
     if (!ctx) return TPCCA_E_ARG;
-    if (!ctx->adj_valid) return fail(ctx, TPCCA_E_ARG, "no successful tpcca_refit_fwd to differentiate");
+    if (!ctx->adj_valid) return fail(ctx, TPCCA_E_ARG, "no recorded tpcca_refit_fwd to differentiate");
     AdjBufs a = ctx->adj;
     if (a.n_tracks > 0 && (!grad_chi2 || !grad_params0))
         return fail(ctx, TPCCA_E_ARG, "null grad_chi2 or grad_params0");
@@ -911,9 +959,25 @@ tpcca_status tpcca_refit_bwd(tpcca_ctx* ctx, const float* grad_chi2, double* gra
     a.grad_chi2 = grad_chi2;
     a.grad_params = grad_params0;
     a.grad_map = grad_map;
-    enqueue_refit_bwd(a, st);
-    if (grad_hit_yz && a.n_hits > 0)
-        HIP_TRY(hipMemcpyAsync(grad_hit_yz, a.hit_grad, 16 * (size_t)a.n_hits, hipMemcpyDeviceToDevice, st));
+    if (ctx->adj_taped) {
+        enqueue_refit_reverse(a, 0, a.n_tracks, st);
+    } else {
+        // the set's tape exceeds the budget: record and reverse batch by batch
+        const int64_t per_track = std::max<int64_t>(1, (int64_t)a.tape_ops * kTapeBytesPerOp);
+        tpcca_status s = ensure_tape(ctx, (size_t)(per_track * ctx->adj_batch));
+        if (s != TPCCA_OK) return s;
+        a.tape = (uint32_t*)ctx->tape_base;
+        for (int64_t t0 = 0; t0 < a.n_tracks; t0 += ctx->adj_batch) {
+            const int64_t t1 = std::min(a.n_tracks, t0 + ctx->adj_batch);
+            enqueue_refit_forward(a, t0, t1, false, st);
+            enqueue_refit_reverse(a, t0, t1, st);
+        }
+    }
+    if (grad_map) {
+        const AdjLayout L = adj_layout(ctx->adj_cap_t, ctx->adj_cap_h);
+        enqueue_refit_map_grad(a, (char*)ctx->adj_base + L.o_rec, st);
+    }
+    if (grad_hit_yz) enqueue_refit_hit_grad(a, grad_hit_yz, st);
     HIP_TRY(hipGetLastError());
     return TPCCA_OK;
 }

@@ -112,7 +112,7 @@ struct Bufs {
 };
 
 struct Launch {
-    int block_links, block_tracklet, block_refit, block_scan, sort_seeds;
+    int block_links, block_tracklet, block_refit, block_scan, sort_seeds, xcd_remap;
 };
 
 constexpr int kScanBlocks = 1024;

@@ -215,17 +215,28 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
     (void)nr;
 }
 
+// The GPU hands consecutive workgroups to its 8 XCDs in turn (workgroup g
+// runs on XCD g mod 8), and every XCD has its own L2. Renumbering physical
+// workgroup g of a period P (a multiple of 8) to logical workgroup
+// (g mod 8) * P/8 + g/8 gives XCD x the contiguous logical range
+// [x P/8, (x+1) P/8): work that is adjacent in the logical order (the rows of
+// one sector instance, the seeds of one instance) then shares one L2 instead
+// of being spread over all eight.
+__device__ __forceinline__ int64_t xcd_logical(int64_t g, int64_t P) { return (g & 7) * (P >> 3) + (g >> 3); }
+
 // ------------------------------------------------------------------ links
 // One workgroup per (instance, row); one lane per hit of the row. Candidate
 // pairs (u on row+1, d on row-1) inside the windows; the minimum straight-line
 // deviation score wins, ties to the smaller (id_u, id_d). When both adjacent
 // rows fit in `cap` clusters, their coordinates and bin starts are staged in
 // LDS once per workgroup and every candidate read is an LDS read.
-__global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int cap) {
+__global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t nseg, int cap, int remap) {
     extern __shared__ unsigned char smem[];
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
-    const int64_t seg = seg0 + blockIdx.x;
+    const int64_t l = remap ? xcd_logical(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    if (l >= nseg) return;
+    const int64_t seg = seg0 + l;
     const int r = (int)(seg % nr);
     const int64_t a = b.row_start[seg], e = b.row_start[seg + 1];
     if (r == 0 || r == nr - 1) {
@@ -671,14 +682,23 @@ __device__ __forceinline__ int lower_bound_inst(const int32_t* a, int64_t lo, in
 
 // One lane per start hit: seed, stage 1 (chain), stage 2 (outward), turn,
 // stage 3 (inward re-pick), weights.
-__global__ __launch_bounds__(256) void k_tracklet(Bufs b) {
+__global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
     const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
     if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;  // never hit: N/3 bound
     unsigned long long st_chain = 0, st_rows = 0, st_cand = 0, st_picks = 0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cnt; k += (int64_t)gridDim.x * blockDim.x) {
+    // logical workgroup (seeds are ordered by instance): with the XCD
+    // renumbering over the workgroups that have seeds, each XCD follows the
+    // seeds of about one eighth of the instances
+    int64_t lg = blockIdx.x, period = gridDim.x;
+    if (remap && gridDim.x >= 8) {
+        const int64_t active = (cnt + blockDim.x - 1) / blockDim.x;
+        period = min((active + 7) / 8 * 8, (int64_t)(gridDim.x & ~7u));
+        lg = blockIdx.x < period ? xcd_logical(blockIdx.x, period) : cnt;  // past the period: no seeds
+    }
+    for (int64_t k = lg * blockDim.x + threadIdx.x; k < cnt; k += period * blockDim.x) {
         const int64_t j = base + k;
         const int32_t pos0 = b.starts[j];
         const int32_t inst = b.start_inst[j];
@@ -1069,7 +1089,9 @@ void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, int max_row, 
         cap = 0;
         bytes = 0;
     }
-    hipLaunchKernelGGL(k_links, dim3((unsigned)nseg), dim3(L.block_links), bytes, st, b, seg0, cap);
+    const int64_t grid = L.xcd_remap ? (nseg + 7) / 8 * 8 : nseg;
+    hipLaunchKernelGGL(k_links, dim3((unsigned)grid), dim3(L.block_links), bytes, st, b, seg0, nseg, cap,
+                       L.xcd_remap);
 }
 
 void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, hipStream_t st) {
@@ -1079,7 +1101,8 @@ void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_
 }
 
 void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
-    hipLaunchKernelGGL(k_tracklet, dim3(grid_for(bound, L.block_tracklet, 16384)), dim3(L.block_tracklet), 0, st, b);
+    hipLaunchKernelGGL(k_tracklet, dim3(grid_for(bound, L.block_tracklet, 16384)), dim3(L.block_tracklet), 0, st, b,
+                       L.xcd_remap);
 }
 
 void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {

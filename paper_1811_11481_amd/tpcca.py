@@ -75,6 +75,8 @@ class Tuning(ctypes.Structure):
         ("block_refit", ctypes.c_int32),
         ("block_scan", ctypes.c_int32),
         ("sort_seeds", ctypes.c_int32),
+        ("tape_mb", ctypes.c_int32),
+        ("xcd_remap", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -189,7 +191,8 @@ def load():
         L.tpcca_fp32_selfcheck.restype = st
         L.tpcca_fp32_selfcheck.argtypes = [vp, vp, vp, vp, i64, vp]
         L.tpcca_refit_fwd.restype = st
-        L.tpcca_refit_fwd.argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(RefitSetC), vp, vp, vp, vp, vp]
+        L.tpcca_refit_fwd.argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(RefitSetC), vp, vp, vp, vp,
+                                      i32, vp]
         L.tpcca_refit_bwd.restype = st
         L.tpcca_refit_bwd.argtypes = [vp] * 6
         _lib = L
@@ -443,10 +446,12 @@ class Tracker:
                         a.tolist()))
 
     # ---- differentiable refit ---------------------------------------------
-    def refit_forward(self, clusters: DeviceClusters, rset: "RefitSet", params0=None, coef=None, stream=None):
+    def refit_forward(self, clusters: DeviceClusters, rset: "RefitSet", params0=None, coef=None, record=True,
+                      stream=None):
         """chi2 per track (float32), track ok flags, FP64 total of the refit with
         frozen masks; params0 (n, 5) float32 overrides rset.params0, coef is
-        the (3, 16, 16, 32) float32 correction map or None."""
+        the (3, 16, 16, 32) float32 correction map or None; record keeps what
+        refit_backward needs."""
         torch = _torch()
         n = rset.n_tracks
         dev = clusters.y.device
@@ -461,7 +466,7 @@ class Tracker:
         total = torch.empty(1, dtype=torch.float64, device=dev)
         cin, cset = clusters.c_struct(), rset.c_struct(p0)
         self._check(self.lib.tpcca_refit_fwd(self.h, ctypes.byref(cin), ctypes.byref(cset), _ptr(coef), _ptr(chi2),
-                                             _ptr(ok), _ptr(total), _stream(stream)))
+                                             _ptr(ok), _ptr(total), 1 if record else 0, _stream(stream)))
         self._adj_gen = getattr(self, "_adj_gen", 0) + 1
         self._adj_hits = rset.n_hits
         return chi2[:n], ok[:n], total
@@ -550,13 +555,15 @@ def refit_chi2(tracker: Tracker, clusters: DeviceClusters, rset: RefitSet, param
     """chi2 per track of the frozen-mask refit as a differentiable torch function
     of params0 (n, 5) and of the correction map coef (3, 16, 16, 32) or None."""
     torch = _torch()
+    # (inside Function.forward gradients are always disabled: decide here)
+    record = torch.is_grad_enabled() and (params0.requires_grad or (coef is not None and coef.requires_grad))
 
     class _RefitChi2(torch.autograd.Function):
         @staticmethod
         def forward(fctx, p, c):
             p32 = p.detach().to(torch.float32).contiguous()
             c32 = None if c is None else c.detach().to(torch.float32).contiguous()
-            chi2, ok, _ = tracker.refit_forward(clusters, rset, p32, c32)
+            chi2, ok, _ = tracker.refit_forward(clusters, rset, p32, c32, record=record)
             fctx.p32, fctx.c32, fctx.gen = p32, c32, tracker._adj_gen
             fctx.p_shape, fctx.c_shape = p.shape, None if c is None else c.shape
             fctx.mark_non_differentiable(ok)

@@ -219,3 +219,75 @@ def test_refit_set_validation(c1_setup):
     assert chi2.numel() == 0 and total.item() == 0.0
     gp, gm, _ = trk.refit_backward(torch.zeros(0, dtype=torch.float32, device="cuda"))
     assert gp.numel() == 0 and float(gm.abs().max()) == 0.0
+
+
+def _permute(rset, order):
+    import torch
+
+    from paper_1811_11481_amd import RefitSet
+    hs = rset.hit_start.cpu().numpy()
+    order = np.asarray(order)
+    pos = np.concatenate([np.arange(hs[t], hs[t + 1]) for t in order])
+    lens = hs[order + 1] - hs[order]
+    o = torch.as_tensor(order, device="cuda")
+    p = torch.as_tensor(pos, device="cuda")
+    return RefitSet(rset.params0[o].contiguous(), rset.cov0[o].contiguous(), rset.row0[o].contiguous(),
+                    rset.inst[o].contiguous(), torch.as_tensor(np.concatenate([[0], np.cumsum(lens)]), device="cuda"),
+                    rset.hit_id[p].contiguous(), rset.hit_mask[p].contiguous())
+
+
+def test_map_gradient_independent_of_track_order():
+    """C2, all tracks: in instance order a workgroup's clusters touch a small
+    coefficient box; in random order every workgroup spans all sectors and both
+    sides (full phi range, z cut into slabs). Same gradients up to the order of
+    the FP64 accumulation."""
+    import torch
+
+    from paper_1811_11481_amd import DeviceClusters, RefitSet, Tracker
+    cs = synth.generate("C2")
+    trk = Tracker()
+    dc = DeviceClusters.from_host(cs)
+    trk.track(dc)
+    rs = RefitSet.from_tracker(trk)
+    log("C2 refit set: %d tracks, %d clusters" % (rs.n_tracks, rs.n_hits))
+    coef = torch.as_tensor(_smooth_map(21), device="cuda")
+    perm = np.random.default_rng(2).permutation(rs.n_tracks)
+    out = []
+    for r in (rs, _permute(rs, perm)):
+        chi2, ok, _ = trk.refit_forward(dc, r, coef=coef)
+        w = torch.ones(r.n_tracks, dtype=torch.float32, device="cuda")
+        gp, gm, _ = trk.refit_backward(w)
+        out.append((chi2.cpu().numpy(), gp.cpu().numpy(), gm.cpu().numpy().reshape(-1)))
+    (c0, p0, m0), (c1, p1, m1) = out
+    assert np.array_equal(c0[perm], c1) and np.array_equal(p0[perm], p1)
+    assert np.abs(m0 - m1).max() <= 1e-12 * np.abs(m0).max()
+    assert np.count_nonzero(m0) > 1000
+
+
+def test_batched_recompute_equals_full_tape(c1_setup):
+    """A tape budget below the set's tape makes the backward re-record the
+    forward batch by batch: same gradients as the whole-set tape."""
+    import torch
+
+    from paper_1811_11481_amd import DeviceClusters, RefitSet, Tracker, TpccaError, default_tuning
+    cs = synth.generate("C2")
+    dc = DeviceClusters.from_host(cs)
+    full = Tracker()
+    full.track(dc)
+    rs = RefitSet.from_tracker(full)
+    small = Tracker(tuning=default_tuning(tape_mb=1))  # ~13 tracks per batch
+    coef = torch.as_tensor(_smooth_map(31), device="cuda")
+    w = torch.as_tensor(np.random.default_rng(1).uniform(0.5, 2, rs.n_tracks), dtype=torch.float32, device="cuda")
+    res = []
+    for trk in (full, small):
+        chi2, _, tot = trk.refit_forward(dc, rs, coef=coef)
+        gp, gm, gh = trk.refit_backward(w, want_map=True, want_hits=True)
+        res.append((chi2.cpu().numpy(), tot.item(), gp.cpu().numpy(), gm.cpu().numpy(), gh.cpu().numpy()))
+    (c0, t0, p0, m0, h0), (c1, t1, p1, m1, h1) = res
+    assert np.array_equal(c0, c1) and t0 == t1
+    assert np.array_equal(p0, p1) and np.array_equal(h0, h1)
+    assert np.abs(m0 - m1).max() <= 1e-12 * np.abs(m0).max()
+    # forward only: nothing recorded to differentiate
+    full.refit_forward(dc, rs, coef=coef, record=False)
+    with pytest.raises(TpccaError):
+        full.refit_backward(w)
