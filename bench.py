@@ -64,12 +64,13 @@ def byte_model(stage: str, st: dict, n_clusters: int, n_seg: int, hits_per_bin: 
 
 
 def kernel_source_sha256() -> str:
-    import glob
+    """Hash of the tracking kernels' sources (the differentiable refit's files
+    do not enter: they build no kernel of the tracking path)."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1811_11481_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(src, "*.hip")) + glob.glob(os.path.join(src, "*.h"))):
-        h.update(open(f, "rb").read())
+    for f in ("internal.h", "kernels.hip", "kf_device.h"):
+        h.update(open(os.path.join(src, f), "rb").read())
     return h.hexdigest()
 
 

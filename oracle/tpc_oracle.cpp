@@ -174,7 +174,7 @@ T asin_over_deriv(T u) {
 // Returns false (state untouched) if |sin phi| leaves the guard or u is too big.
 template <class T>
 bool propagate(State<T>& s, T x1, T x2, const Consts<T>& k) {
-    const T one = (T)1, half = (T)0.5, two = (T)2;
+    const T one = (T)1, half = (T)0.5;
     const T dx = x2 - x1;
     const T s1 = s.p[2];
     const T kq = k.kB * s.p[4];
@@ -193,11 +193,12 @@ bool propagate(State<T>& s, T x1, T x2, const Consts<T>& k) {
     // Jacobian F (identity plus these entries), the derivative of this step:
     // d tan(mean dir) = (1 + tt^2) (dphi1 + dphi2) / 2 with dphi = d(sin phi) / cos,
     // d arc / d sin(phi1) = dx tt / (c1 c2), and for q/pT the chord and u terms.
-    const T f02 = ((dx * w) * ((one / c1) + (one / c2))) * half;
-    const T f04 = ((dx * w) * ((k.kB * dx) / c2)) * half;
-    const T f12 = t * ((dx * tt) / (c1 * c2));
+    const T ic1 = one / c1, ic2 = one / c2;
+    const T f02 = ((dx * w) * (ic1 + ic2)) * half;
+    const T f04 = ((dx * w) * ((k.kB * dx) * ic2)) * half;
+    const T f12 = t * ((dx * tt) * (ic1 * ic2));
     const T f13 = arc;
-    const T dlc = (((k.kB * dx) * lc) * tt) / (two * c2);  // d chord / d(q/pT)
+    const T dlc = (((k.kB * dx) * lc) * tt) * (half * ic2);  // d chord / d(q/pT)
     const T du = (k.kB * lc + kq * dlc) * half;             // d u / d(q/pT)
     const T f14 = t * (dlc * g + (lc * asin_over_deriv(u)) * du);
     const T f24 = k.kB * dx;

@@ -71,11 +71,12 @@ __device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, cons
     const float g = asin_over_u(u);
     const float arc = lc * g;
     const float t = s.p[3];
-    const float f02 = ((dx * w) * ((1.0f / c1) + (1.0f / c2))) * 0.5f;
-    const float f04 = ((dx * w) * ((K.kB * dx) / c2)) * 0.5f;
-    const float f12 = t * ((dx * tt) / (c1 * c2));
+    const float ic1 = 1.0f / c1, ic2 = 1.0f / c2;  // two reciprocals serve four Jacobian terms
+    const float f02 = ((dx * w) * (ic1 + ic2)) * 0.5f;
+    const float f04 = ((dx * w) * ((K.kB * dx) * ic2)) * 0.5f;
+    const float f12 = t * ((dx * tt) * (ic1 * ic2));
     const float f13 = arc;
-    const float dlc = (((K.kB * dx) * lc) * tt) / (2.0f * c2);
+    const float dlc = (((K.kB * dx) * lc) * tt) * (0.5f * ic2);
     const float du = (K.kB * lc + kq * dlc) * 0.5f;
     const float f14 = t * (dlc * g + (lc * asin_over_u_deriv(u)) * du);
     const float f24 = K.kB * dx;
