@@ -81,7 +81,7 @@ typedef struct {
 
 /* Launch/tiling choices. They never change results (tested bit-exact). */
 typedef struct {
-    int32_t hits_per_bin;     /* grid occupancy target per bin (>= 1), default 2 */
+    int32_t hits_per_bin;     /* grid occupancy target per bin (>= 1), default 1 */
     int32_t block_links;      /* threads per block of the neighbour kernel (64..1024), default 256 */
     int32_t block_tracklet;   /* threads per block of the tracklet kernel (64..256), default 256 */
     int32_t block_refit;      /* threads per block of the refit kernel (64..256), default 128 */

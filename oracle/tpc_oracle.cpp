@@ -77,7 +77,7 @@ void orc_default_params(orc_params* p) {
     p->c0[0] = 1.0; p->c0[1] = 1.0; p->c0[2] = 0.25; p->c0[3] = 0.25; p->c0[4] = 400.0;
     p->n_min = 10;
     p->max_miss = 8;
-    p->hits_per_bin = 2;
+    p->hits_per_bin = 1;
     p->n_threads = 1;
 }
 }
@@ -155,7 +155,12 @@ inline float asin_over(float u) {
     const float w = u * u;
     const float c1 = (float)(1.0 / 6.0), c2 = (float)(3.0 / 40.0), c3 = (float)(5.0 / 112.0),
                 c4 = (float)(35.0 / 1152.0), c5 = (float)(63.0 / 2816.0), c6 = (float)(231.0 / 13312.0);
-    return 1.0f + w * (c1 + w * (c2 + w * (c3 + w * (c4 + w * (c5 + w * c6)))));
+    float h = std::fma(w, c6, c5);
+    h = std::fma(w, h, c4);
+    h = std::fma(w, h, c3);
+    h = std::fma(w, h, c2);
+    h = std::fma(w, h, c1);
+    return std::fma(w, h, 1.0f);
 }
 // d/du of asin(u)/u from the same series (both precisions; it only enters the
 // Jacobian): u * sum_n 2n c_n u^(2n-2).
@@ -164,7 +169,12 @@ T asin_over_deriv(T u) {
     const T w = u * u;
     const T d1 = (T)(2.0 / 6.0), d2 = (T)(12.0 / 40.0), d3 = (T)(30.0 / 112.0), d4 = (T)(280.0 / 1152.0),
             d5 = (T)(630.0 / 2816.0), d6 = (T)(2772.0 / 13312.0);
-    return u * (d1 + w * (d2 + w * (d3 + w * (d4 + w * (d5 + w * d6)))));
+    T h = std::fma(w, d6, d5);
+    h = std::fma(w, h, d4);
+    h = std::fma(w, h, d3);
+    h = std::fma(w, h, d2);
+    h = std::fma(w, h, d1);
+    return u * h;
 }
 
 // Helix step x1 -> x2 in a uniform field along z (Section 3 uses the full field;
@@ -178,12 +188,12 @@ bool propagate(State<T>& s, T x1, T x2, const Consts<T>& k) {
     const T dx = x2 - x1;
     const T s1 = s.p[2];
     const T kq = k.kB * s.p[4];
-    const T s2 = s1 + kq * dx;
+    const T s2 = std::fma(kq, dx, s1);
     if (!(std::fabs(s2) < k.sinphi_max)) return false;
-    const T c1 = std::sqrt(one - s1 * s1);
-    const T c2 = std::sqrt(one - s2 * s2);
+    const T c1 = std::sqrt(std::fma(-s1, s1, one));
+    const T c2 = std::sqrt(std::fma(-s2, s2, one));
     const T tt = (s1 + s2) / (c1 + c2);      // tan of the mean direction
-    const T w = one + tt * tt;
+    const T w = std::fma(tt, tt, one);
     const T lc = dx * std::sqrt(w);           // signed chord
     const T u = (kq * lc) * half;
     if (!(u * u <= k.u_max2)) return false;
@@ -199,11 +209,11 @@ bool propagate(State<T>& s, T x1, T x2, const Consts<T>& k) {
     const T f12 = t * ((dx * tt) * (ic1 * ic2));
     const T f13 = arc;
     const T dlc = (((k.kB * dx) * lc) * tt) * (half * ic2);  // d chord / d(q/pT)
-    const T du = (k.kB * lc + kq * dlc) * half;             // d u / d(q/pT)
-    const T f14 = t * (dlc * g + (lc * asin_over_deriv(u)) * du);
+    const T du = std::fma(k.kB, lc, kq * dlc) * half;      // d u / d(q/pT)
+    const T f14 = t * std::fma(dlc, g, (lc * asin_over_deriv(u)) * du);
     const T f24 = k.kB * dx;
-    s.p[0] = s.p[0] + dx * tt;
-    s.p[1] = s.p[1] + t * arc;
+    s.p[0] = std::fma(dx, tt, s.p[0]);
+    s.p[1] = std::fma(t, arc, s.p[1]);
     s.p[2] = s2;
     // C <- F C F^T: first B = F C (full 5x5), then the lower triangle of B F^T.
     T Cf[5][5];
@@ -211,18 +221,18 @@ bool propagate(State<T>& s, T x1, T x2, const Consts<T>& k) {
         for (int j = 0; j < 5; ++j) Cf[i][j] = s.C[pk(i, j)];
     T B[5][5];
     for (int j = 0; j < 5; ++j) {
-        B[0][j] = (Cf[0][j] + f02 * Cf[2][j]) + f04 * Cf[4][j];
-        B[1][j] = ((Cf[1][j] + f12 * Cf[2][j]) + f13 * Cf[3][j]) + f14 * Cf[4][j];
-        B[2][j] = Cf[2][j] + f24 * Cf[4][j];
+        B[0][j] = std::fma(f04, Cf[4][j], std::fma(f02, Cf[2][j], Cf[0][j]));
+        B[1][j] = std::fma(f14, Cf[4][j], std::fma(f13, Cf[3][j], std::fma(f12, Cf[2][j], Cf[1][j])));
+        B[2][j] = std::fma(f24, Cf[4][j], Cf[2][j]);
         B[3][j] = Cf[3][j];
         B[4][j] = Cf[4][j];
     }
     for (int i = 0; i < 5; ++i) {
         for (int j = 0; j <= i; ++j) {
             T v;
-            if (j == 0) v = (B[i][0] + f02 * B[i][2]) + f04 * B[i][4];
-            else if (j == 1) v = ((B[i][1] + f12 * B[i][2]) + f13 * B[i][3]) + f14 * B[i][4];
-            else if (j == 2) v = B[i][2] + f24 * B[i][4];
+            if (j == 0) v = std::fma(f04, B[i][4], std::fma(f02, B[i][2], B[i][0]));
+            else if (j == 1) v = std::fma(f14, B[i][4], std::fma(f13, B[i][3], std::fma(f12, B[i][2], B[i][1])));
+            else if (j == 2) v = std::fma(f24, B[i][4], B[i][2]);
             else v = B[i][j];
             s.C[pk(i, j)] = v;
         }
@@ -242,16 +252,16 @@ Innov<T> innovation(const State<T>& s, T my, T mz, const Consts<T>& k) {
     const T one = (T)1;
     Innov<T> n;
     const T s00 = s.C[0] + k.vy, s01 = s.C[1], s11 = s.C[2] + k.vz;
-    const T det = s00 * s11 - s01 * s01;
+    const T det = std::fma(s00, s11, -(s01 * s01));
     const T idet = one / det;
     n.a00 = s11 * idet;
     n.a01 = (-s01) * idet;
     n.a11 = s00 * idet;
     n.r0 = my - s.p[0];
     n.r1 = mz - s.p[1];
-    const T w0 = n.a00 * n.r0 + n.a01 * n.r1;
-    const T w1 = n.a01 * n.r0 + n.a11 * n.r1;
-    n.chi2 = n.r0 * w0 + n.r1 * w1;
+    const T w0 = std::fma(n.a00, n.r0, n.a01 * n.r1);
+    const T w1 = std::fma(n.a01, n.r0, n.a11 * n.r1);
+    n.chi2 = std::fma(n.r0, w0, n.r1 * w1);
     return n;
 }
 
@@ -264,12 +274,12 @@ void update(State<T>& s, const Innov<T>& n) {
         c1j[j] = s.C[pk(1, j)];
     }
     for (int i = 0; i < 5; ++i) {
-        K0[i] = c0j[i] * n.a00 + c1j[i] * n.a01;
-        K1[i] = c0j[i] * n.a01 + c1j[i] * n.a11;
+        K0[i] = std::fma(c0j[i], n.a00, c1j[i] * n.a01);
+        K1[i] = std::fma(c0j[i], n.a01, c1j[i] * n.a11);
     }
-    for (int i = 0; i < 5; ++i) s.p[i] = s.p[i] + (K0[i] * n.r0 + K1[i] * n.r1);
+    for (int i = 0; i < 5; ++i) s.p[i] = s.p[i] + std::fma(K0[i], n.r0, K1[i] * n.r1);
     for (int i = 0; i < 5; ++i)
-        for (int j = 0; j <= i; ++j) s.C[pk(i, j)] = s.C[pk(i, j)] - (K0[i] * c0j[j] + K1[i] * c1j[j]);
+        for (int j = 0; j <= i; ++j) s.C[pk(i, j)] = s.C[pk(i, j)] - std::fma(K0[i], c0j[j], K1[i] * c1j[j]);
 }
 
 // Covariance reset at a change of direction or a pass start: keep the

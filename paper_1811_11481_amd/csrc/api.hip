@@ -577,7 +577,7 @@ tpcca_status tpcca_default_params(tpcca_params* p) {
 
 tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
     if (!t) return TPCCA_E_ARG;
-    t->hits_per_bin = 2;
+    t->hits_per_bin = 1;
     t->block_links = 256;
     t->block_tracklet = 256;
     t->block_refit = 128;

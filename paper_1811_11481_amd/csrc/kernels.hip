@@ -570,7 +570,7 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, c
     if (g.n == 0) return false;
     const float s00 = s.C[0] + K.vy, s01 = s.C[1], s11 = s.C[2] + K.vz;
     const float wy = K.nsig * __builtin_sqrtf(s00), wz = K.nsig * __builtin_sqrtf(s11);
-    const float det = s00 * s11 - s01 * s01;
+    const float det = __builtin_fmaf(s00, s11, -(s01 * s01));
     const float idet = 1.0f / det;
     const float a00 = s11 * idet, a01 = (-s01) * idet, a11 = s00 * idet;
     const float py = s.p[0], pz = s.p[1];
@@ -583,9 +583,9 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, c
         const float r0 = c.x - py, r1 = c.y - pz;
         ++ncand;
         if (!(__builtin_fabsf(r0) <= wy && __builtin_fabsf(r1) <= wz)) return;
-        const float w0 = a00 * r0 + a01 * r1;
-        const float w1 = a01 * r0 + a11 * r1;
-        const float chi2 = r0 * w0 + r1 * w1;
+        const float w0 = __builtin_fmaf(a00, r0, a01 * r1);
+        const float w1 = __builtin_fmaf(a01, r0, a11 * r1);
+        const float chi2 = __builtin_fmaf(r0, w0, r1 * w1);
         if (!(chi2 <= K.chi2_pick)) return;
         // cluster ids decide only exact chi2 ties: load them only then
         if (!found || chi2 < out.inn.chi2 || (chi2 == out.inn.chi2 && b.sid[pos] < b.sid[out.pos])) {

@@ -4,7 +4,8 @@
 // packed lower-triangular order 00,10,11,20,21,22,30,31,32,33,40,41,42,43,44.
 // Every expression is evaluated in the written order in IEEE binary32: the
 // library is built with -ffp-contract=off and this header forbids contraction
-// as well, so no multiply-add is fused; / and sqrt are correctly rounded.
+// as well, so a multiply-add is fused exactly where __builtin_fmaf is written
+// (one rounding, as IEEE fma) and nowhere else; / and sqrt are correctly rounded.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -39,7 +40,12 @@ __device__ __forceinline__ float asin_over_u(float u) {
     const float w = u * u;
     const float c1 = (float)(1.0 / 6.0), c2 = (float)(3.0 / 40.0), c3 = (float)(5.0 / 112.0),
                 c4 = (float)(35.0 / 1152.0), c5 = (float)(63.0 / 2816.0), c6 = (float)(231.0 / 13312.0);
-    return 1.0f + w * (c1 + w * (c2 + w * (c3 + w * (c4 + w * (c5 + w * c6)))));
+    float h = __builtin_fmaf(w, c6, c5);
+    h = __builtin_fmaf(w, h, c4);
+    h = __builtin_fmaf(w, h, c3);
+    h = __builtin_fmaf(w, h, c2);
+    h = __builtin_fmaf(w, h, c1);
+    return __builtin_fmaf(w, h, 1.0f);
 }
 
 // Its derivative from the same series.
@@ -47,7 +53,12 @@ __device__ __forceinline__ float asin_over_u_deriv(float u) {
     const float w = u * u;
     const float d1 = (float)(2.0 / 6.0), d2 = (float)(12.0 / 40.0), d3 = (float)(30.0 / 112.0),
                 d4 = (float)(280.0 / 1152.0), d5 = (float)(630.0 / 2816.0), d6 = (float)(2772.0 / 13312.0);
-    return u * (d1 + w * (d2 + w * (d3 + w * (d4 + w * (d5 + w * d6)))));
+    float h = __builtin_fmaf(w, d6, d5);
+    h = __builtin_fmaf(w, h, d4);
+    h = __builtin_fmaf(w, h, d3);
+    h = __builtin_fmaf(w, h, d2);
+    h = __builtin_fmaf(w, h, d1);
+    return u * h;
 }
 
 // One helix step x1 -> x2 in a uniform field along z: sin phi advances by
@@ -59,12 +70,12 @@ __device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, cons
     const float dx = x2 - x1;
     const float s1 = s.p[2];
     const float kq = K.kB * s.p[4];
-    const float s2 = s1 + kq * dx;
+    const float s2 = __builtin_fmaf(kq, dx, s1);
     if (!(__builtin_fabsf(s2) < K.sinphi_max)) return false;
-    const float c1 = __builtin_sqrtf(1.0f - s1 * s1);
-    const float c2 = __builtin_sqrtf(1.0f - s2 * s2);
+    const float c1 = __builtin_sqrtf(__builtin_fmaf(-s1, s1, 1.0f));
+    const float c2 = __builtin_sqrtf(__builtin_fmaf(-s2, s2, 1.0f));
     const float tt = (s1 + s2) / (c1 + c2);
-    const float w = 1.0f + tt * tt;
+    const float w = __builtin_fmaf(tt, tt, 1.0f);
     const float lc = dx * __builtin_sqrtf(w);
     const float u = (kq * lc) * 0.5f;
     if (!(u * u <= K.u_max2)) return false;
@@ -77,11 +88,11 @@ __device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, cons
     const float f12 = t * ((dx * tt) * (ic1 * ic2));
     const float f13 = arc;
     const float dlc = (((K.kB * dx) * lc) * tt) * (0.5f * ic2);
-    const float du = (K.kB * lc + kq * dlc) * 0.5f;
-    const float f14 = t * (dlc * g + (lc * asin_over_u_deriv(u)) * du);
+    const float du = __builtin_fmaf(K.kB, lc, kq * dlc) * 0.5f;
+    const float f14 = t * __builtin_fmaf(dlc, g, (lc * asin_over_u_deriv(u)) * du);
     const float f24 = K.kB * dx;
-    s.p[0] = s.p[0] + dx * tt;
-    s.p[1] = s.p[1] + t * arc;
+    s.p[0] = __builtin_fmaf(dx, tt, s.p[0]);
+    s.p[1] = __builtin_fmaf(t, arc, s.p[1]);
     s.p[2] = s2;
     // B = F C; only rows 0, 1, 2 differ from C.
     float B0[5], B1[5], B2[5];
@@ -89,9 +100,9 @@ __device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, cons
     for (int j = 0; j < 5; ++j) {
         const float c0j = s.C[pk(0, j)], c1j = s.C[pk(1, j)], c2j = s.C[pk(2, j)], c3j = s.C[pk(3, j)],
                     c4j = s.C[pk(4, j)];
-        B0[j] = (c0j + f02 * c2j) + f04 * c4j;
-        B1[j] = ((c1j + f12 * c2j) + f13 * c3j) + f14 * c4j;
-        B2[j] = c2j + f24 * c4j;
+        B0[j] = __builtin_fmaf(f04, c4j, __builtin_fmaf(f02, c2j, c0j));
+        B1[j] = __builtin_fmaf(f14, c4j, __builtin_fmaf(f13, c3j, __builtin_fmaf(f12, c2j, c1j)));
+        B2[j] = __builtin_fmaf(f24, c4j, c2j);
     }
     // C' = B F^T (lower triangle). Rows 3, 4 of B are rows 3, 4 of C.
     float B3[5], B4[5];
@@ -105,9 +116,9 @@ __device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, cons
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         const float* b = Bi[i];
-        Cn[pk(i, 0)] = (b[0] + f02 * b[2]) + f04 * b[4];
-        if (i >= 1) Cn[pk(i, 1)] = ((b[1] + f12 * b[2]) + f13 * b[3]) + f14 * b[4];
-        if (i >= 2) Cn[pk(i, 2)] = b[2] + f24 * b[4];
+        Cn[pk(i, 0)] = __builtin_fmaf(f04, b[4], __builtin_fmaf(f02, b[2], b[0]));
+        if (i >= 1) Cn[pk(i, 1)] = __builtin_fmaf(f14, b[4], __builtin_fmaf(f13, b[3], __builtin_fmaf(f12, b[2], b[1])));
+        if (i >= 2) Cn[pk(i, 2)] = __builtin_fmaf(f24, b[4], b[2]);
         if (i >= 3) Cn[pk(i, 3)] = b[3];
         if (i >= 4) Cn[pk(i, 4)] = b[4];
     }
@@ -125,16 +136,16 @@ struct Innov {
 __device__ __forceinline__ Innov kf_innovation(const KState& s, float my, float mz, const DevConsts& K) {
     Innov n;
     const float s00 = s.C[0] + K.vy, s01 = s.C[1], s11 = s.C[2] + K.vz;
-    const float det = s00 * s11 - s01 * s01;
+    const float det = __builtin_fmaf(s00, s11, -(s01 * s01));
     const float idet = 1.0f / det;
     n.a00 = s11 * idet;
     n.a01 = (-s01) * idet;
     n.a11 = s00 * idet;
     n.r0 = my - s.p[0];
     n.r1 = mz - s.p[1];
-    const float w0 = n.a00 * n.r0 + n.a01 * n.r1;
-    const float w1 = n.a01 * n.r0 + n.a11 * n.r1;
-    n.chi2 = n.r0 * w0 + n.r1 * w1;
+    const float w0 = __builtin_fmaf(n.a00, n.r0, n.a01 * n.r1);
+    const float w1 = __builtin_fmaf(n.a01, n.r0, n.a11 * n.r1);
+    n.chi2 = __builtin_fmaf(n.r0, w0, n.r1 * w1);
     return n;
 }
 
@@ -148,15 +159,16 @@ __device__ __forceinline__ void kf_update(KState& s, const Innov& n) {
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        K0[i] = c0j[i] * n.a00 + c1j[i] * n.a01;
-        K1[i] = c0j[i] * n.a01 + c1j[i] * n.a11;
+        K0[i] = __builtin_fmaf(c0j[i], n.a00, c1j[i] * n.a01);
+        K1[i] = __builtin_fmaf(c0j[i], n.a01, c1j[i] * n.a11);
     }
 #pragma unroll
-    for (int i = 0; i < 5; ++i) s.p[i] = s.p[i] + (K0[i] * n.r0 + K1[i] * n.r1);
+    for (int i = 0; i < 5; ++i) s.p[i] = s.p[i] + __builtin_fmaf(K0[i], n.r0, K1[i] * n.r1);
 #pragma unroll
     for (int i = 0; i < 5; ++i)
 #pragma unroll
-        for (int j = 0; j <= i; ++j) s.C[pk(i, j)] = s.C[pk(i, j)] - (K0[i] * c0j[j] + K1[i] * c1j[j]);
+        for (int j = 0; j <= i; ++j)
+            s.C[pk(i, j)] = s.C[pk(i, j)] - __builtin_fmaf(K0[i], c0j[j], K1[i] * c1j[j]);
 }
 
 // Covariance reset at a turn or pass start: variances scaled, correlations dropped.

@@ -100,7 +100,7 @@ def test_plain_equals_batched_and_is_deterministic(c1):
     assert tracks_equal(a, b) and tracks_equal(a, c)
 
 
-@pytest.mark.parametrize("tune", [dict(hits_per_bin=1), dict(hits_per_bin=3, block_tracklet=64, xcd_remap=0),
+@pytest.mark.parametrize("tune", [dict(hits_per_bin=2), dict(hits_per_bin=3, block_tracklet=64, xcd_remap=0),
                                   dict(hits_per_bin=8, block_links=64, block_refit=256, block_scan=512)])
 def test_results_independent_of_tuning(c1, c1_oracle, tune):
     from paper_1811_11481_amd import default_tuning
