@@ -184,7 +184,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     size_t o_sel = L.add(4 * cap_sel), o_soff = L.add(4 * cap_sel), o_sn = L.add(4 * cap_sel);
     size_t o_spos = L.add(4 * N), o_syz = L.add(8 * N), o_srow = L.add(N), o_smask = L.add(N);
     size_t o_rs = L.add(80 * cap_sel), o_rc = L.add(4 * cap_sel), o_rn = L.add(4 * cap_sel),
-           o_rr = L.add(4 * cap_sel), o_rok = L.add(4 * cap_sel);
+           o_rr = L.add(4 * cap_sel), o_rok = L.add(4 * cap_sel), o_kt = L.add(4 * cap_sel), o_kho = L.add(4 * cap_sel);
     size_t o_part = L.add(8 * kScanBlocks);
     *total = L.total;
     if (!really) return;
@@ -225,6 +225,8 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     b.rf_nacc = (int32_t*)(base + o_rn);
     b.rf_row = (int32_t*)(base + o_rr);
     b.rf_ok = (int32_t*)(base + o_rok);
+    b.trk_t = (int32_t*)(base + o_kt);
+    b.trk_ho = (int32_t*)(base + o_kho);
     b.scan_part = (unsigned long long*)(base + o_part);
 }
 
@@ -241,8 +243,8 @@ tpcca_status ensure_arena(tpcca_ctx* ctx, int64_t N, int64_t nseg, int64_t ninst
         A.base = nullptr;
     }
     if (ctx->has_graph) {
-        hipGraphExecDestroy(ctx->gexec);
-        hipGraphDestroy(ctx->graph);
+        (void)hipGraphExecDestroy(ctx->gexec);
+        (void)hipGraphDestroy(ctx->graph);
         ctx->has_graph = false;
     }
     ctx->has_last = false;
@@ -354,7 +356,7 @@ void enqueue_range(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, i
     mark(5);
     enqueue_refit(b, L, (c1 - c0) / std::max(1, n_min) + ninst, st);
     mark(6);
-    enqueue_write(b, L, 0, st);
+    enqueue_write(b, L, (c1 - c0) / std::max(1, n_min) + ninst, st);
     mark(7);
 }
 
@@ -418,7 +420,7 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
         enqueue_reset(b, st);
         enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, max_row(0, in->n_inst), st, ctx);
         enqueue_finish(b, st);
-        hipEventRecord(ctx->ev[8], st);
+        (void)hipEventRecord(ctx->ev[8], st);
         HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(st));
@@ -441,20 +443,20 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
     std::memcpy(key.v, vs, sizeof(vs));
     if (!ctx->has_graph || !(ctx->gkey == key)) {
         if (ctx->has_graph) {
-            hipGraphExecDestroy(ctx->gexec);
-            hipGraphDestroy(ctx->graph);
+            (void)hipGraphExecDestroy(ctx->gexec);
+            (void)hipGraphDestroy(ctx->graph);
             ctx->has_graph = false;
         }
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
         enqueue_reset(b, st);
         enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, max_row(0, in->n_inst), st, nullptr);
         enqueue_finish(b, st);
-        hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
+        (void)hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
         hipError_t e = hipStreamEndCapture(st, &ctx->graph);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            hipGraphDestroy(ctx->graph);
+            (void)hipGraphDestroy(ctx->graph);
             return hip_fail(ctx, e, "hipGraphInstantiate");
         }
         ctx->has_graph = true;
@@ -631,11 +633,11 @@ tpcca_status tpcca_create(const tpcca_params* params, const tpcca_tuning* tuning
 
 void tpcca_destroy(tpcca_ctx* ctx) {
     if (!ctx) return;
-    hipSetDevice(ctx->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
     if (ctx->has_graph) {
-        hipGraphExecDestroy(ctx->gexec);
-        hipGraphDestroy(ctx->graph);
+        (void)hipGraphExecDestroy(ctx->gexec);
+        (void)hipGraphDestroy(ctx->graph);
     }
     if (ctx->events)
         for (auto& e : ctx->ev) hipEventDestroy(e);
@@ -709,8 +711,8 @@ tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_
     const uint32_t saved_flags = ctx->params.flags;
     ctx->params.flags &= ~TPCCA_FLAG_TIMING;  // time the captured form
     hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
     tpcca_tuning best = ctx->tuning;
     auto time_it = [&](const tpcca_tuning& t, float* ms_out) -> tpcca_status {
         tpcca_status s = tpcca_set_tuning(ctx, &t);
@@ -719,13 +721,13 @@ tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_
         if (s != TPCCA_OK) return s;
         std::vector<float> ms;
         for (int r = 0; r < repeats; ++r) {
-            hipEventRecord(e0, st);
+            (void)hipEventRecord(e0, st);
             s = run(ctx, sample, &tr, hip_stream, true);
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
             if (s != TPCCA_OK) return s;
             float m = 0;
-            hipEventElapsedTime(&m, e0, e1);
+            (void)hipEventElapsedTime(&m, e0, e1);
             ms.push_back(m);
         }
         std::sort(ms.begin(), ms.end());
@@ -753,17 +755,17 @@ tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     ctx->params.flags = saved_flags;
     tpcca_set_tuning(ctx, &best);
     *out = best;
     ctx->has_last = false;  // internal buffers are about to go away
-    hipStreamSynchronize(st);
-    hipFree(mem);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(mem);
     if (ctx->has_graph) {  // graph refers to the freed buffers
-        hipGraphExecDestroy(ctx->gexec);
-        hipGraphDestroy(ctx->graph);
+        (void)hipGraphExecDestroy(ctx->gexec);
+        (void)hipGraphDestroy(ctx->graph);
         ctx->has_graph = false;
     }
     return s;

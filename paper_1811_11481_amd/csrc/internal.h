@@ -95,6 +95,8 @@ struct Bufs {
     int32_t* rf_nacc;
     int32_t* rf_row;
     int32_t* rf_ok;
+    int32_t* trk_t;      // [cap_sel] output track index of a selected tracklet (-1: none)
+    int32_t* trk_ho;     // [cap_sel] its first output hit
     // scan scratch
     unsigned long long* scan_part;  // [kScanBlocks]
     // outputs

@@ -473,49 +473,80 @@ struct SelectOp {
             raise_err(b.ctr, ERR_SCRATCH);
             return;
         }
-        const int nr = b.K->n_rows;
-        const int nh = b.tl_nhits[j];
         b.sel_tl[si] = (int32_t)j;
         b.sel_off[si] = (int32_t)ho;
         b.sel_n[si] = own;
-        const uint32_t* mask = b.tl_ownmask + j * 8;
-        int m = 0;
-        for (int k = nh - 1; k >= 0; --k) {  // picks are stored rows-descending
-            if ((mask[k >> 5] >> (k & 31)) & 1u) {
-                const int32_t pos = b.tl_pick_pos[j * nr + k];
-                b.sel_pos[ho + m] = pos;
-                b.sel_yz[ho + m] = b.yz[pos];
-                b.sel_row[ho + m] = b.tl_pick_row[j * nr + k];
-                ++m;
-            }
-        }
     }
 };
 
-// Owned picks of every tracklet of the current range: count and bitmask.
+// Owned picks of every tracklet of the current range: count and bitmask. One
+// wave per tracklet, one lane per pick (the picks' weight reads are
+// independent, so they overlap instead of queueing behind one lane).
 __global__ void k_own(Bufs b) {
     const int nr = b.K->n_rows, n_min = b.K->n_min;
     const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
     if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;
-    for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k0 < cnt; k0 += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t k0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; k0 < cnt; k0 += nwave) {
         const int64_t j = base + k0;
         const int nh = b.tl_nhits[j];
         uint32_t mk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         int own = 0;
         if (nh >= n_min) {
             const uint32_t w = packed_weight(nh, b.tl_tid[j]);
-            for (int k = 0; k < nh; ++k) {
-                if (b.weight[b.tl_pick_pos[j * nr + k]] == w) {
-                    mk[k >> 5] |= 1u << (k & 31);
-                    ++own;
-                }
+#pragma unroll
+            for (int c = 0; c < 256; c += 64) {
+                if (c >= nh) break;
+                const int k = c + lane;
+                const bool o = k < nh && b.weight[b.tl_pick_pos[j * nr + k]] == w;
+                const unsigned long long bal = __ballot(o);
+                mk[c >> 5] = (uint32_t)bal;
+                mk[(c >> 5) + 1] = (uint32_t)(bal >> 32);
+                own += __popcll(bal);
             }
         }
-        b.tl_own[j] = own;
-        uint32_t* dst = b.tl_ownmask + j * 8;
+        if (lane == 0) {
+            b.tl_own[j] = own;
+            uint32_t* dst = b.tl_ownmask + j * 8;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) dst[q] = mk[q];
+            for (int q = 0; q < 8; ++q) dst[q] = mk[q];
+        }
+    }
+}
+
+// Cluster lists of the selected tracklets (offsets from the selection scan):
+// one wave per tracklet, one lane per pick. Owned pick k goes to position
+// (owned picks after k) of the list, i.e. rows ascending, as the picks are
+// stored rows descending.
+__global__ void k_sel_fill(Bufs b) {
+    const int nr = b.K->n_rows;
+    const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
+    if (base + cnt > b.cap_sel) cnt = b.cap_sel > base ? b.cap_sel - base : 0;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t k0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; k0 < cnt; k0 += nwave) {
+        const int64_t si = base + k0;
+        const int32_t j = b.sel_tl[si];
+        const int64_t ho = b.sel_off[si];
+        const int own = b.sel_n[si];
+        if (ho + own > b.n_clusters) continue;  // flagged by the scan
+        const int nh = b.tl_nhits[j];
+        const uint32_t* mask = b.tl_ownmask + (int64_t)j * 8;
+        for (int c = 0; c < nh; c += 64) {
+            const int k = c + lane;
+            if (k >= nh || !((mask[k >> 5] >> (k & 31)) & 1u)) continue;
+            int le = 0;  // owned picks with index <= k
+            for (int q = 0; q < (k >> 5); ++q) le += __popc(mask[q]);
+            le += __popc(mask[k >> 5] & (uint32_t)((2ull << (k & 31)) - 1ull));
+            const int64_t m = ho + (own - le);
+            const int32_t pos = b.tl_pick_pos[(int64_t)j * nr + k];
+            b.sel_pos[m] = pos;
+            b.sel_yz[m] = b.yz[pos];
+            b.sel_row[m] = b.tl_pick_row[(int64_t)j * nr + k];
+        }
     }
 }
 
@@ -536,8 +567,11 @@ struct TrackOp {
         const int nacc = (int)(v & 0xFFFFFFFFull);
         if (t >= b.cap_tracks || ho + nacc > b.cap_hits) {
             raise_err(b.ctr, ERR_OUT_CAP);
+            b.trk_t[si] = -1;
             return;
         }
+        b.trk_t[si] = (int32_t)t;
+        b.trk_ho[si] = (int32_t)ho;
         const DevConsts& K = *b.K;
         const int32_t tl = b.sel_tl[si];
         const int32_t inst = b.start_inst[tl];
@@ -550,12 +584,36 @@ struct TrackOp {
         b.o_chi2[t] = b.rf_chi2[si];
         b.o_ndf[t] = 2 * nacc - 5;
         b.o_hit_start[t] = ho;
-        const int off = b.sel_off[si], n = b.sel_n[si];
-        int m = 0;
-        for (int i = 0; i < n; ++i)
-            if (b.sel_mask[off + i] & 4) b.o_hit_id[ho + m++] = b.sid[b.sel_pos[off + i]];
     }
 };
+
+// Cluster ids of the output tracks: one wave per selected tracklet, one lane
+// per cluster; the clusters used in the last pass keep their order (ballot
+// prefix counts).
+__global__ void k_trk_fill(Bufs b) {
+    const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
+    if (base + cnt > b.cap_sel) cnt = b.cap_sel > base ? b.cap_sel - base : 0;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t k0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; k0 < cnt; k0 += nwave) {
+        const int64_t si = base + k0;
+        if (!b.rf_ok[si]) continue;
+        const int32_t t = b.trk_t[si];
+        if (t < 0) continue;  // capacity exceeded: flagged by the scan
+        const int64_t ho = b.trk_ho[si];
+        const int off = b.sel_off[si], n = b.sel_n[si];
+        int run = 0;
+        for (int c = 0; c < n; c += 64) {
+            const int i = c + lane;
+            const bool use = i < n && (b.sel_mask[off + i] & 4);
+            const unsigned long long bal = __ballot(use);
+            if (use) b.o_hit_id[ho + run + __popcll(bal & below)] = b.sid[b.sel_pos[off + i]];
+            run += __popcll(bal);
+        }
+    }
+}
 
 // ------------------------------------------------------------------ tracklets
 struct Pick {
@@ -1106,9 +1164,10 @@ void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_
 }
 
 void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
-    hipLaunchKernelGGL(k_own, dim3(grid_for(bound, 256, 16384)), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_own, dim3(grid_for(bound * 64, 256, 16384)), dim3(256), 0, st, b);
     SelectOp op{b};
     launch_scan(op, b, SL_SEL, L.block_scan, st);
+    hipLaunchKernelGGL(k_sel_fill, dim3(grid_for(bound * 64, 256, 16384)), dim3(256), 0, st, b);
 }
 
 void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
@@ -1116,9 +1175,9 @@ void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st
 }
 
 void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
-    (void)bound;
     TrackOp op{b};
     launch_scan(op, b, SL_TRK, L.block_scan, st);
+    hipLaunchKernelGGL(k_trk_fill, dim3(grid_for(bound * 64, 256, 16384)), dim3(256), 0, st, b);
 }
 
 void enqueue_finish(const Bufs& b, hipStream_t st) {
