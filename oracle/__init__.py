@@ -356,7 +356,8 @@ def frozen_chi2_grad_fd(inp, coef=None, coef_index=(), h_param=(1e-4, 1e-4, 1e-6
     """Reference gradient of the frozen-mask refit chi2 by central differences of
     the FP64 function: d chi2_t / d params0_t (n x 5, each track's chi2 depends
     only on its own start state, so one perturbation serves all tracks) and
-    d (sum_t chi2_t) / d coef[k] for the flat coefficient indices in coef_index."""
+    d (sum_t chi2_t) / d coef[k] for the flat coefficient indices in coef_index.
+    h_param: steps for the five start parameters, a 5-vector or per track (n x 5)."""
     base = np.zeros(MAP_SIZE) if coef is None else np.asarray(coef, np.float64).reshape(-1).copy()
     use_map = coef is not None or len(coef_index) > 0
 
@@ -367,15 +368,16 @@ def frozen_chi2_grad_fd(inp, coef=None, coef_index=(), h_param=(1e-4, 1e-4, 1e-6
 
     st0 = np.asarray(inp["st0"], np.float64)
     gp = np.zeros((len(st0), 5))
+    hp = np.broadcast_to(np.asarray(h_param, np.float64), (len(st0), 5))
     ok_all = f(st0, base)[0]
     for k in range(5):
         sp, sm = st0.copy(), st0.copy()
-        sp[:, k] += h_param[k]
-        sm[:, k] -= h_param[k]
+        sp[:, k] += hp[:, k]
+        sm[:, k] -= hp[:, k]
         okp, cp = f(sp, base)
         okm, cm = f(sm, base)
         ok_all &= okp & okm
-        gp[:, k] = (cp - cm) / (2.0 * h_param[k])
+        gp[:, k] = (cp - cm) / (2.0 * hp[:, k])
     gc = np.zeros(len(coef_index))
     for j, k in enumerate(coef_index):
         cpl, cmi = base.copy(), base.copy()

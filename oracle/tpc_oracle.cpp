@@ -541,6 +541,10 @@ void build_tracklet(const Input& in, const Consts<T>& k, Result<T>& R, int64_t s
             ++miss;
         }
     }
+    // The state at the end of the outward following is the tracklet's output:
+    // the refit starts from it.
+    const State<T> s_out = s;
+    const int row_out = cur;
     // turn, stage 3: inward through the seed, re-picking every row
     reset_cov(s, k);
     bool ok = true;
@@ -569,10 +573,10 @@ void build_tracklet(const Input& in, const Consts<T>& k, Result<T>& R, int64_t s
         }
     }
     R.tl_nhits[sidx] = nh;
-    R.tl_row[sidx] = cur;
+    R.tl_row[sidx] = row_out;
     T* st = R.tl_state.data() + sidx * 20;
-    for (int i = 0; i < 5; ++i) st[i] = s.p[i];
-    for (int i = 0; i < 15; ++i) st[5 + i] = s.C[i];
+    for (int i = 0; i < 5; ++i) st[i] = s_out.p[i];
+    for (int i = 0; i < 15; ++i) st[5 + i] = s_out.C[i];
 }
 
 // ---------------------------------------------------------------- 7. refit

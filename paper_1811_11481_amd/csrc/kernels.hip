@@ -825,6 +825,14 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
                     ++miss;
                 }
             }
+            // the state at the end of the outward following is the
+            // tracklet's output: the refit starts from it
+            float* o = b.tl_state + j * 20;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) o[q] = s.p[q];
+#pragma unroll
+            for (int q = 0; q < 15; ++q) o[5 + q] = s.C[q];
+            b.tl_row[j] = cur;
             // turn, stage 3
             kf_reset(s, K);
             bool down_ok = true;
@@ -858,16 +866,11 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
                     }
                 }
             }
-            b.tl_row[j] = cur;
         }
         b.tl_nhits[j] = nh;
         st_picks += nh;
-        float* o = b.tl_state + j * 20;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) o[q] = s.p[q];
-#pragma unroll
-        for (int q = 0; q < 15; ++q) o[5 + q] = s.C[q];
         if (!ok) {
+            float* o = b.tl_state + j * 20;
 #pragma unroll
             for (int q = 0; q < 20; ++q) o[q] = 0.0f;
         }

@@ -107,10 +107,10 @@ def test_refit_is_translation_invariant(c1_inputs):
         ok, c = _f(inp, st0=st, **kw)
         assert ok.all()
         assert np.allclose(c, chi2, rtol=1e-9, atol=1e-9)
-    # and the start state does matter
+    # and the start state does matter, if very little (three covariance resets)
     st = inp["st0"].copy()
     st[:, 1] += 0.37
-    assert not np.allclose(_f(inp, st0=st)[1], chi2, rtol=1e-9, atol=1e-9)
+    assert not np.allclose(_f(inp, st0=st)[1], chi2, rtol=1e-13, atol=0)
 
 
 def _touched_coefs(inp, comp):
