@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--extra", default="C2x8", help="comma-separated extra workloads timed in the batched form")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable-refit leg (C5)")
     ap.add_argument("--diff-tracks", type=int, default=100000)
+    ap.add_argument("--diff-only", action="store_true",
+                    help="run only the differentiable-refit leg and print its JSON object")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -157,6 +159,9 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.diff_only:
+        print(json.dumps({"differentiable_refit": diff_leg(args, torch, np, synth)}))
+        return
     if args.copy_calibration:
         src = torch.empty(args.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
         src.fill_(1.0)

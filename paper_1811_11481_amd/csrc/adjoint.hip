@@ -201,9 +201,9 @@ __device__ __forceinline__ void f_apply(A v[5], const A f[6]) {
 
 // Adjoint of a row step with input (sin phi, tan lambda, q/pT) and covariance
 // C: pbar <- F^T pbar + 2 sum_bc M_bc dF_bc/dp (M = Cbar F C), Cbar <- F^T Cbar F.
-template <class A>
+template <class A, class KC>
 __device__ __forceinline__ void adj_prop(const float C[15], float s1, float t, float q, float dx, A pb[5], A Cb[15],
-                                         const DevConsts& K) {
+                                         const KC& K) {
     D3<A> fd[6];
     step_jacobian<A>(A(s1), A(t), A(q), A(dx), A(K.kB), fd);
     A f[6];
@@ -255,8 +255,8 @@ __device__ __forceinline__ void adj_prop(const float C[15], float s1, float t, f
 }
 
 // Adjoint of a covariance reset: variances scaled, correlations dropped.
-template <class A>
-__device__ __forceinline__ void adj_reset(A Cb[15], const DevConsts& K) {
+template <class A, class KC>
+__device__ __forceinline__ void adj_reset(A Cb[15], const KC& K) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
 #pragma unroll
@@ -272,9 +272,9 @@ __device__ __forceinline__ void adj_reset(A Cb[15], const DevConsts& K) {
 //   Gbar = pbar+ (A r)^T - 2 Cbar+ G A
 //   Abar = (G^T pbar+) r^T - G^T Cbar+ G + cb r r^T,  Sbar = -A Abar A
 //   Cbar = Cbar+ + sym(H^T Sbar H) + sym(Gbar H)
-template <class A>
+template <class A, class KC>
 __device__ __forceinline__ void adj_upd(const float C[15], float r0f, float r1f, A pb[5], A Cb[15], A& mb0, A& mb1,
-                                        A cb, const DevConsts& K) {
+                                        A cb, const KC& K) {
     const A r0 = A(r0f), r1 = A(r1f);
     const A s00 = A(C[0]) + A(K.vy), s01 = A(C[1]), s11 = A(C[2]) + A(K.vz);
     const A idet = A(1) / (s00 * s11 - s01 * s01);
@@ -473,8 +473,11 @@ __device__ __forceinline__ void rec_op(uint4* tp, int k, const float* C, bool co
 // cluster's row, coordinates and mask are loaded one cluster ahead.
 template <bool kTape>
 __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_t t1, int outputs) {
-    if (a.status->err) return;
     const DevConsts& K = *a.K;
+    const KfConsts kc = kf_consts(K);
+    __shared__ float sX[kMaxRows];
+    kf_load_rows(sX, K);  // before the status test: every thread reaches its barrier
+    if (a.status->err) return;
     const int cap = a.tape_ops;
     for (int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t1;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
                     else set_err(a.status, AERR_TAPE);
                 }
                 ++k;
-                if (!kf_propagate(s, K.X[cur], K.X[nx], K)) ok = false;
+                if (!kf_propagate(s, sX[cur], sX[nx], kc)) ok = false;
                 else cur = nx;
             }
         };
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
                 else set_err(a.status, AERR_TAPE);
             }
             ++k;
-            kf_reset(s, K);
+            kf_reset(s, kc);
             const bool inward = pass != 1;
             int i_n = inward ? n - 1 : 0;
             int t_n = rows[i_n];
@@ -532,7 +535,7 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
                 }
                 step_to(target);
                 if (!ok || !((mk >> pass) & 1u)) continue;
-                const Innov inn = kf_innovation(s, c.x - ref_y, c.y - ref_z, K);
+                const Innov inn = kf_innovation(s, c.x - ref_y, c.y - ref_z, kc);
                 if (kTape) {
                     if (k < cap) rec_op(tp, k, s.C, true, inn.r0, inn.r1, 0.0f, op_word(OP_UPD, pass, 0, 0, i));
                     else set_err(a.status, AERR_TAPE);
@@ -564,6 +567,9 @@ __device__ __forceinline__ void load_op(const uint4* tp, int k, uint4 w[kTapeWor
 template <class A>
 __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_t t1) {
     const DevConsts& K = *a.K;
+    const KfConsts kc = kf_consts(K);
+    __shared__ float sX[kMaxRows];
+    kf_load_rows(sX, K);
     const int64_t NH = a.n_hits;
     for (int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t1;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -594,7 +600,7 @@ __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_
             const uint32_t ow = v[4].z;
             const int kind = (int)(ow & 3u);
             if (kind == OP_RESET) {
-                adj_reset(Cb, K);
+                adj_reset(Cb, kc);
                 continue;
             }
             const float C[15] = {__uint_as_float(v[0].x), __uint_as_float(v[0].y), __uint_as_float(v[0].z),
@@ -605,11 +611,11 @@ __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_
             const float o0 = __uint_as_float(v[3].w), o1 = __uint_as_float(v[4].x);
             if (kind == OP_PROP) {
                 const int from = (int)((ow >> 4) & 255u), to = (int)((ow >> 12) & 255u);
-                adj_prop<A>(C, o0, o1, __uint_as_float(v[4].y), K.X[to] - K.X[from], pb, Cb, K);
+                adj_prop<A>(C, o0, o1, __uint_as_float(v[4].y), sX[to] - sX[from], pb, Cb, kc);
             } else {
                 const int hit = (int)((ow >> 20) & 255u), pass = (int)((ow >> 2) & 3u);
                 A mb0 = A(0), mb1 = A(0);
-                adj_upd<A>(C, o0, o1, pb, Cb, mb0, mb1, pass == 2 ? cb : A(0), K);
+                adj_upd<A>(C, o0, o1, pb, Cb, mb0, mb1, pass == 2 ? cb : A(0), kc);
                 a.hit_grad[pass * NH + off + hit] = make_double2((double)mb0, (double)mb1);
             }
         }

@@ -622,7 +622,7 @@ struct Pick {
 };
 
 // Best cluster on the row of segment `seg` for the predicted state.
-__device__ __forceinline__ bool pick_on_row(const Bufs& b, const DevConsts& K, const KState& s, int64_t seg,
+__device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, const KState& s, int64_t seg,
                                             const SegHdr& h, Pick& out, unsigned long long& ncand) {
     const GridView g = grid_view(b, seg, h);
     if (g.n == 0) return false;
@@ -743,6 +743,10 @@ __device__ __forceinline__ int lower_bound_inst(const int32_t* a, int64_t lo, in
 __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
+    const KfConsts kc = kf_consts(K);
+    const int stats = K.stats;
+    __shared__ float sX[kMaxRows];
+    kf_load_rows(sX, K);
     const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
     if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;  // never hit: N/3 bound
@@ -784,7 +788,7 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
         const int32_t pm = chain[m];
         KState s;
         const float2 c0 = b.yz[pos0], cm = b.yz[pm], ce = b.yz[pe];
-        const bool seeded = seed_from_chain(K, K.X[r0], c0.x, c0.y, K.X[r0 + m], cm.x, K.X[r0 + L - 1], ce.x, ce.y, s);
+        const bool seeded = seed_from_chain(K, sX[r0], c0.x, c0.y, sX[r0 + m], cm.x, sX[r0 + L - 1], ce.x, ce.y, s);
         int cur = r0;
         bool ok = seeded;
         // stage 1
@@ -793,11 +797,11 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
             for (int i = 0; i < L; ++i) {
                 const float2 cp = cn;
                 if (i + 1 < L) cn = b.yz[chain[i + 1]];  // next hit, loaded ahead
-                if (i > 0 && !kf_propagate(s, K.X[r0 + i - 1], K.X[r0 + i], K)) {
+                if (i > 0 && !kf_propagate(s, sX[r0 + i - 1], sX[r0 + i], kc)) {
                     ok = false;
                     break;
                 }
-                const Innov n = kf_innovation(s, cp.x, cp.y, K);
+                const Innov n = kf_innovation(s, cp.x, cp.y, kc);
                 kf_update(s, n);
             }
             st_chain += L;
@@ -810,14 +814,14 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
             // the next row's grid header does not depend on the state: load it
             // one row ahead so that its latency hides behind the propagation
             SegHdr hn = load_hdr(b, seg0 + min(cur + 1, nr - 1));
-            for (int r = cur + 1; r < nr && miss < K.max_miss; ++r) {
+            for (int r = cur + 1; r < nr && miss < kc.max_miss; ++r) {
                 const SegHdr h = hn;
                 hn = load_hdr(b, seg0 + min(r + 1, nr - 1));
-                if (!kf_propagate(s, K.X[r - 1], K.X[r], K)) break;
+                if (!kf_propagate(s, sX[r - 1], sX[r], kc)) break;
                 cur = r;
                 ++st_rows;
                 Pick pk_;
-                if (pick_on_row(b, K, s, seg0 + r, h, pk_, st_cand)) {
+                if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
                     kf_update(s, pk_.inn);
                     last = r;
                     miss = 0;
@@ -834,10 +838,10 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
             for (int q = 0; q < 15; ++q) o[5 + q] = s.C[q];
             b.tl_row[j] = cur;
             // turn, stage 3
-            kf_reset(s, K);
+            kf_reset(s, kc);
             bool down_ok = true;
             for (int r = cur - 1; r >= last; --r) {
-                if (!kf_propagate(s, K.X[r + 1], K.X[r], K)) {
+                if (!kf_propagate(s, sX[r + 1], sX[r], kc)) {
                     down_ok = false;
                     break;
                 }
@@ -850,18 +854,18 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
                     const SegHdr h = hn3;
                     hn3 = load_hdr(b, seg0 + max(r - 1, 0));
                     if (r != cur) {
-                        if (!kf_propagate(s, K.X[cur], K.X[r], K)) break;
+                        if (!kf_propagate(s, sX[cur], sX[r], kc)) break;
                         cur = r;
                     }
                     ++st_rows;
                     Pick pk_;
-                    if (pick_on_row(b, K, s, seg0 + r, h, pk_, st_cand)) {
+                    if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
                         kf_update(s, pk_.inn);
                         b.tl_pick_pos[j * nr + nh] = pk_.pos;
                         b.tl_pick_row[j * nr + nh] = (uint8_t)r;
                         ++nh;
                         miss = 0;
-                    } else if (++miss >= K.max_miss) {
+                    } else if (++miss >= kc.max_miss) {
                         break;
                     }
                 }
@@ -874,12 +878,12 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
 #pragma unroll
             for (int q = 0; q < 20; ++q) o[q] = 0.0f;
         }
-        if (nh >= K.n_min) {
+        if (nh >= kc.n_min) {
             const uint32_t w = packed_weight(nh, tid);
             for (int q = 0; q < nh; ++q) atomicMax(&b.weight[b.tl_pick_pos[j * nr + q]], w);
         }
     }
-    if (K.stats) {
+    if (stats) {
         stat_add(b.ctr, ST_CHAIN_HITS, st_chain);
         stat_add(b.ctr, ST_TL_ROWS, st_rows);
         stat_add(b.ctr, ST_TL_CAND, st_cand);
@@ -893,6 +897,10 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
 // used iff its predicted chi2 <= chi2_rej.
 __global__ __launch_bounds__(256) void k_refit(Bufs b) {
     const DevConsts& K = *b.K;
+    const KfConsts kc = kf_consts(K);
+    const int stats = K.stats;
+    __shared__ float sX[kMaxRows];
+    kf_load_rows(sX, K);
     const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
     if (base + cnt > b.cap_sel) cnt = b.cap_sel > base ? b.cap_sel - base : 0;  // never hit: N/n_min bound
@@ -917,7 +925,7 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
         const int outer = ok ? (int)b.sel_row[off + n - 1] : 0;
         while (ok && cur != outer) {
             const int nx = cur < outer ? cur + 1 : cur - 1;
-            if (!kf_propagate(s, K.X[cur], K.X[nx], K)) ok = false;
+            if (!kf_propagate(s, sX[cur], sX[nx], kc)) ok = false;
             else cur = nx;
             ++st_rows;
         }
@@ -925,7 +933,7 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
         float chi2sum = 0.0f;
         int nacc = 0;
         for (int pass = 0; pass < 3 && ok; ++pass) {
-            kf_reset(s, K);
+            kf_reset(s, kc);
             const bool inward = (pass != 1);
             // the next cluster's row, coordinates and mask are loaded one
             // iteration ahead, so no row step waits on memory
@@ -945,7 +953,7 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
                 }
                 while (cur != target) {
                     const int nx = cur < target ? cur + 1 : cur - 1;
-                    if (!kf_propagate(s, K.X[cur], K.X[nx], K)) {
+                    if (!kf_propagate(s, sX[cur], sX[nx], kc)) {
                         ok = false;
                         break;
                     }
@@ -954,9 +962,9 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
                 }
                 if (!ok) break;
                 const float my = c.x, mz = c.y;
-                const Innov inn = kf_innovation(s, my - ref_y, mz - ref_z, K);
+                const Innov inn = kf_innovation(s, my - ref_y, mz - ref_z, kc);
                 ++st_hits;
-                if (inn.chi2 <= K.chi2_rej) {
+                if (inn.chi2 <= kc.chi2_rej) {
                     kf_update(s, inn);
                     s.p[0] = s.p[0] + (ref_y - my);
                     s.p[1] = s.p[1] + (ref_z - mz);
@@ -980,9 +988,9 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
         b.rf_chi2[si] = chi2sum;
         b.rf_nacc[si] = nacc;
         b.rf_row[si] = cur;
-        b.rf_ok[si] = (ok && nacc >= K.n_min) ? 1 : 0;
+        b.rf_ok[si] = (ok && nacc >= kc.n_min) ? 1 : 0;
     }
-    if (K.stats) {
+    if (stats) {
         stat_add(b.ctr, ST_RF_ROWS, st_rows);
         stat_add(b.ctr, ST_RF_HITS, st_hits);
     }

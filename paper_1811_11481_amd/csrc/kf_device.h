@@ -28,6 +28,39 @@ struct DevConsts {
     float c0[5];
 };
 
+// The scalar constants of the row steps, copied into registers once per
+// kernel (before any store, so they come in as uniform scalar loads). A step
+// that read them from global memory would wait on each of those loads, and a
+// wait on the vector-memory counter also waits for every load issued before
+// it, prefetches included.
+struct KfConsts {
+    float kB, vy, vz, nsig, chi2_pick, chi2_rej, sinphi_max, cov_reset, u_max2;
+    int max_miss, n_min;
+};
+
+__device__ __forceinline__ KfConsts kf_consts(const DevConsts& K) {
+    KfConsts c;
+    c.kB = K.kB;
+    c.vy = K.vy;
+    c.vz = K.vz;
+    c.nsig = K.nsig;
+    c.chi2_pick = K.chi2_pick;
+    c.chi2_rej = K.chi2_rej;
+    c.sinphi_max = K.sinphi_max;
+    c.cov_reset = K.cov_reset;
+    c.u_max2 = K.u_max2;
+    c.max_miss = K.max_miss;
+    c.n_min = K.n_min;
+    return c;
+}
+
+// Pad-row radii in LDS for one workgroup (indexed per lane without touching
+// the vector-memory counter). Every thread of the block must call it.
+__device__ __forceinline__ void kf_load_rows(float* sX, const DevConsts& K) {
+    for (int i = threadIdx.x; i < K.n_rows; i += blockDim.x) sX[i] = K.X[i];
+    __syncthreads();
+}
+
 struct KState {
     float p[5];
     float C[15];
@@ -66,7 +99,8 @@ __device__ __forceinline__ float asin_over_u_deriv(float u) {
 // times the arc (signed chord * asin(u)/u). Covariance: C <- F C F^T with the
 // exact Jacobian of this step. Returns false and leaves the state unchanged
 // when |sin phi| would reach the guard or the step bends too much.
-__device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, const DevConsts& K) {
+template <class KC>
+__device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, const KC& K) {
     const float dx = x2 - x1;
     const float s1 = s.p[2];
     const float kq = K.kB * s.p[4];
@@ -133,7 +167,8 @@ struct Innov {
     float a00, a01, a11, r0, r1, chi2;
 };
 
-__device__ __forceinline__ Innov kf_innovation(const KState& s, float my, float mz, const DevConsts& K) {
+template <class KC>
+__device__ __forceinline__ Innov kf_innovation(const KState& s, float my, float mz, const KC& K) {
     Innov n;
     const float s00 = s.C[0] + K.vy, s01 = s.C[1], s11 = s.C[2] + K.vz;
     const float det = __builtin_fmaf(s00, s11, -(s01 * s01));
@@ -172,7 +207,8 @@ __device__ __forceinline__ void kf_update(KState& s, const Innov& n) {
 }
 
 // Covariance reset at a turn or pass start: variances scaled, correlations dropped.
-__device__ __forceinline__ void kf_reset(KState& s, const DevConsts& K) {
+template <class KC>
+__device__ __forceinline__ void kf_reset(KState& s, const KC& K) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
 #pragma unroll
