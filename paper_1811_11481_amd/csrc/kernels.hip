@@ -623,7 +623,7 @@ struct Pick {
 
 // Best cluster on the row of segment `seg` for the predicted state.
 __device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, const KState& s, int64_t seg,
-                                            const SegHdr& h, Pick& out, unsigned long long& ncand) {
+                                            const SegHdr& h, Pick& out, unsigned int& ncand) {
     const GridView g = grid_view(b, seg, h);
     if (g.n == 0) return false;
     const float s00 = s.C[0] + K.vy, s01 = s.C[1], s11 = s.C[2] + K.vz;
@@ -664,35 +664,37 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, co
         q10 = g.bs[(z0 + 1) * g.ny + y0];
         q11 = g.bs[(z0 + 1) * g.ny + y1 + 1];
     }
-    for (int bz = z0; bz <= z1; ++bz) {
-        int q0, q1;
-        if (bz == z0) {
-            q0 = q00;
-            q1 = q01;
-        } else if (bz == z0 + 1) {
-            q0 = q10;
-            q1 = q11;
-        } else {
-            q0 = g.bs[bz * g.ny + y0];
-            q1 = g.bs[bz * g.ny + y1 + 1];
+    // the candidates of those two rows as one list, four per memory round
+    // trip: a wave then runs as many candidate tests as its longest list
+    // needs, not the sum of per-row chunks and remainders
+    const int na = max(q01 - q00, 0), n2 = na + max(q11 - q10, 0);
+    for (int k = 0; k < n2; k += 4) {
+        int64_t pos[4];
+        float2 c[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = min(k + i, n2 - 1);  // past the end: a repeat of the last, not tested
+            pos[i] = g.rs + (kk < na ? q00 + kk : q10 + (kk - na));
+            c[i] = b.yz[pos[i]];
         }
-        int q = q0;
-        for (; q + 4 <= q1; q += 4) {  // four candidates per memory round trip
-            const float2 ca = b.yz[g.rs + q], cb = b.yz[g.rs + q + 1], cc = b.yz[g.rs + q + 2],
-                         cd = b.yz[g.rs + q + 3];
-            consider(g.rs + q, ca);
-            consider(g.rs + q + 1, cb);
-            consider(g.rs + q + 2, cc);
-            consider(g.rs + q + 3, cd);
-        }
-        if (q < q1) {
-            const int rem = q1 - q;
-            const float2 ca = b.yz[g.rs + q];
-            const float2 cb = rem > 1 ? b.yz[g.rs + q + 1] : ca;
-            const float2 cc = rem > 2 ? b.yz[g.rs + q + 2] : ca;
-            consider(g.rs + q, ca);
-            if (rem > 1) consider(g.rs + q + 1, cb);
-            if (rem > 2) consider(g.rs + q + 2, cc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (k + i < n2) consider(pos[i], c[i]);
+    }
+    // further rows of a tall window, one row at a time
+    for (int bz = z0 + 2; bz <= z1; ++bz) {
+        const int q0 = g.bs[bz * g.ny + y0], q1 = g.bs[bz * g.ny + y1 + 1];
+        for (int q = q0; q < q1; q += 4) {
+            int64_t pos[4];
+            float2 c[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                pos[i] = g.rs + min(q + i, q1 - 1);
+                c[i] = b.yz[pos[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (q + i < q1) consider(pos[i], c[i]);
         }
     }
     return found;
@@ -750,7 +752,7 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
     if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;  // never hit: N/3 bound
-    unsigned long long st_chain = 0, st_rows = 0, st_cand = 0, st_picks = 0;
+    unsigned int st_chain = 0, st_rows = 0, st_cand = 0, st_picks = 0;  // per lane: 32 bits suffice
     // logical workgroup (seeds are ordered by instance): with the XCD
     // renumbering over the workgroups that have seeds, each XCD follows the
     // seeds of about one eighth of the instances
@@ -904,7 +906,7 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
     const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
     if (base + cnt > b.cap_sel) cnt = b.cap_sel > base ? b.cap_sel - base : 0;  // never hit: N/n_min bound
-    unsigned long long st_rows = 0, st_hits = 0;
+    unsigned int st_rows = 0, st_hits = 0;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cnt; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t si = base + k;
         const int32_t tl = b.sel_tl[si];
