@@ -25,6 +25,7 @@ namespace tpcca {
 namespace {
 
 constexpr float kBinMargin = 0.01f;  // cm: bin ranges of window queries are widened by this
+constexpr int kCandChunk = 8;         // window candidates loaded per memory round trip
 constexpr int kSmallRow = 4096;
 constexpr int kLargeRow = 16384;      // TPCCA_MAX_ROW_CLUSTERS
 constexpr int kKeyShift = 14;         // key = bin << 14 | local index (both < 16384)
@@ -664,36 +665,36 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, co
         q10 = g.bs[(z0 + 1) * g.ny + y0];
         q11 = g.bs[(z0 + 1) * g.ny + y1 + 1];
     }
-    // the candidates of those two rows as one list, four per memory round
-    // trip: a wave then runs as many candidate tests as its longest list
+    // the candidates of those two rows as one list, kCandChunk per memory
+    // round trip: a wave then runs as many candidate tests as its longest list
     // needs, not the sum of per-row chunks and remainders
     const int na = max(q01 - q00, 0), n2 = na + max(q11 - q10, 0);
-    for (int k = 0; k < n2; k += 4) {
-        int64_t pos[4];
-        float2 c[4];
+    for (int k = 0; k < n2; k += kCandChunk) {
+        int64_t pos[kCandChunk];
+        float2 c[kCandChunk];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kCandChunk; ++i) {
             const int kk = min(k + i, n2 - 1);  // past the end: a repeat of the last, not tested
             pos[i] = g.rs + (kk < na ? q00 + kk : q10 + (kk - na));
             c[i] = b.yz[pos[i]];
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kCandChunk; ++i)
             if (k + i < n2) consider(pos[i], c[i]);
     }
     // further rows of a tall window, one row at a time
     for (int bz = z0 + 2; bz <= z1; ++bz) {
         const int q0 = g.bs[bz * g.ny + y0], q1 = g.bs[bz * g.ny + y1 + 1];
-        for (int q = q0; q < q1; q += 4) {
-            int64_t pos[4];
-            float2 c[4];
+        for (int q = q0; q < q1; q += kCandChunk) {
+            int64_t pos[kCandChunk];
+            float2 c[kCandChunk];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < kCandChunk; ++i) {
                 pos[i] = g.rs + min(q + i, q1 - 1);
                 c[i] = b.yz[pos[i]];
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < kCandChunk; ++i)
                 if (q + i < q1) consider(pos[i], c[i]);
         }
     }
