@@ -89,6 +89,43 @@ def measured_traffic(kernel: str, workload: str):
     return int(d["traffic_bytes_per_launch"])
 
 
+def stage_roofline(trk, dc, cs, workload, warmup, steps):
+    """Per-stage kernel time (HIP events between the stages, on the launch
+    stream), algorithmic bytes from the work counters, and the roofline of the
+    dominant kernel."""
+    from paper_1811_11481_amd import Tracker, default_params
+    from paper_1811_11481_amd.tpcca import FLAG_STATS, FLAG_TIMING
+
+    trk_t = Tracker(params=default_params(flags=FLAG_TIMING), tuning=trk.tuning)
+    outt = trk_t.alloc_tracks(dc)
+    stage_ms = {}
+    for k in range(warmup + steps):
+        trk_t.track(dc, outt, batched=True)
+        if k >= warmup:
+            for name, v in trk_t.stage_times().items():
+                stage_ms.setdefault(name, []).append(v)
+    stage_avg = {k: statistics.mean(v) for k, v in stage_ms.items()}
+    # work counters for the byte model (separate pass: the counters use atomics)
+    trk_s = Tracker(params=default_params(flags=FLAG_STATS), tuning=trk.tuning)
+    trk_s.track(dc, trk_s.alloc_tracks(dc), batched=True)
+    st = trk_s.stats()
+    nseg = cs.n_inst * 152
+    hpb = trk.tuning.hits_per_bin
+    stages = {}
+    for name, t in stage_avg.items():
+        b = byte_model(name, st, cs.n_clusters, nseg, hpb)
+        stages[name] = {"ms": round(t, 4), "alg_bytes": b,
+                        "GBps": round(b / (t * 1e-3) / 1e9, 2) if t > 0 and b else None}
+    dom = max((k for k in stages if k != "finish"), key=lambda k: stages[k]["ms"])
+    dom_bytes = stages[dom]["alg_bytes"]
+    achieved = dom_bytes / (stages[dom]["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic("k_" + dom.rstrip("s") if dom == "tracklets" else "k_" + dom, workload),
+                "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": stages[dom]["ms"]}
+    return stages, roofline
+
+
 def diff_leg(args, torch, np, synth):
     """Differentiable refit: chi2 of the frozen-mask three-pass refit of the
     first tracks found in C5, as a function of the start states and a
@@ -153,8 +190,7 @@ def main():
     import torch
 
     import synth
-    from paper_1811_11481_amd import DeviceClusters, Tracker, default_params
-    from paper_1811_11481_amd.tpcca import FLAG_STATS, FLAG_TIMING
+    from paper_1811_11481_amd import DeviceClusters, Tracker
 
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
@@ -205,35 +241,7 @@ def main():
         assert out.n_tracks == n_tracks
         print("[bench] plain: %.3f ms/step" % plain_ms, file=sys.stderr, flush=True)
 
-    # per-stage kernel time: HIP events between the stages on the launch stream
-    trk_t = Tracker(params=default_params(flags=FLAG_TIMING), tuning=trk.tuning)
-    outt = trk_t.alloc_tracks(dc)
-    stage_ms = {}
-    for k in range(args.warmup + args.steps):
-        trk_t.track(dc, outt, batched=True)
-        if k >= args.warmup:
-            for name, v in trk_t.stage_times().items():
-                stage_ms.setdefault(name, []).append(v)
-    stage_avg = {k: statistics.mean(v) for k, v in stage_ms.items()}
-    # work counters for the byte model (separate pass: the counters use atomics)
-    trk_s = Tracker(params=default_params(flags=FLAG_STATS), tuning=trk.tuning)
-    trk_s.track(dc, trk_s.alloc_tracks(dc), batched=True)
-    st = trk_s.stats()
-    nseg = cs.n_inst * 152
-    hpb = trk.tuning.hits_per_bin
-    stages = {}
-    for name, t in stage_avg.items():
-        b = byte_model(name, st, cs.n_clusters, nseg, hpb)
-        stages[name] = {"ms": round(t, 4), "alg_bytes": b,
-                        "GBps": round(b / (t * 1e-3) / 1e9, 2) if t > 0 and b else None}
-    dom = max((k for k in stages if k != "finish"), key=lambda k: stages[k]["ms"])
-    dom_bytes = stages[dom]["alg_bytes"]
-    achieved = dom_bytes / (stages[dom]["ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic("k_" + dom.rstrip("s") if dom == "tracklets" else "k_" + dom,
-                                            args.workload),
-                "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": stages[dom]["ms"]}
+    stages, roofline = stage_roofline(trk, dc, cs, args.workload, args.warmup, args.steps)
     print("[bench] stages (ms): %s" % {k: v["ms"] for k, v in stages.items()}, file=sys.stderr, flush=True)
 
     extra = {}
@@ -250,10 +258,11 @@ def main():
             trk.track(edc, eout, batched=True)
         torch.cuda.synchronize()
         ems = (time.perf_counter() - e0) / ek * 1e3
+        est, eroof = stage_roofline(trk, edc, ecs, wl, max(1, args.warmup), ek)
         extra[wl] = {"workload": WORKLOADS[wl], "n_clusters": ecs.n_clusters, "n_instances": ecs.n_inst,
                      "ms_per_step": round(ems, 4), "clusters_per_s": round(ecs.n_clusters / (ems * 1e-3), 1),
                      "tracks_per_s": round(eout.n_tracks / (ems * 1e-3), 1), "n_tracks": eout.n_tracks,
-                     "steps": ek}
+                     "steps": ek, "stages": est, "roofline": eroof}
         print("[bench] %s batched: %.3f ms/step" % (wl, ems), file=sys.stderr, flush=True)
         del edc, eout
 

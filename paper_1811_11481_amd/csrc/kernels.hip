@@ -26,6 +26,7 @@ namespace {
 
 constexpr float kBinMargin = 0.01f;  // cm: bin ranges of window queries are widened by this
 constexpr int kCandChunk = 8;         // window candidates loaded per memory round trip
+constexpr int kNbKeep = 4;            // neighbour candidates in row r-1 kept in registers per hit
 constexpr int kSmallRow = 4096;
 constexpr int kLargeRow = 16384;      // TPCCA_MAX_ROW_CLUSTERS
 constexpr int kKeyShift = 14;         // key = bin << 14 | local index (both < 16384)
@@ -283,6 +284,52 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
             const int dy1 = bin_of((yh + wyd) + kBinMargin, gd.ymin, gd.iy, gd.ny);
             const int dz0 = bin_of((zh - wzd) - kBinMargin, gd.zmin, gd.iz, gd.nz);
             const int dz1 = bin_of((zh + wzd) + kBinMargin, gd.zmin, gd.iz, gd.nz);
+            // a candidate pair (u, d) that passed both boxes
+            auto pair = [&](int q, float yu, float zu, int t, float yd, float zd) {
+                ++n_pairs;
+                const float ey = (yd + (yu - yd) * tr) - yh;
+                const float ez = (zd + (zu - zd) * tr) - zh;
+                const float sc = ey * ey + ez * ez;
+                if (!(sc <= smax)) return;
+                bool take = !found || sc < best;
+                if (!take && sc == best) {  // ids decide only exact ties
+                    const int32_t uid = b.sid[gu.rs + q], did = b.sid[gd.rs + t];
+                    const int32_t buid = b.sid[gu.rs + bu], bdid = b.sid[gd.rs + bd];
+                    take = uid < buid || (uid == buid && did < bdid);
+                }
+                if (take) {
+                    found = true;
+                    best = sc;
+                    bu = q;
+                    bd = t;
+                }
+            };
+            // the d candidates inside their box, scanned once: up to kNbKeep kept
+            // in registers (a shift register, no indexed register access)
+            int nd = 0;
+            int dt0 = 0, dt1 = 0, dt2 = 0, dt3 = 0;
+            float2 dc0 = make_float2(0.0f, 0.0f), dc1 = dc0, dc2 = dc0, dc3 = dc0;
+            const bool short_d = dz1 - dz0 <= 1;
+            if (short_d) {
+                const int d00 = bsd[dz0 * gd.ny + dy0], d01 = bsd[dz0 * gd.ny + dy1 + 1];
+                int d10 = 0, d11 = 0;
+                if (dz1 > dz0) {
+                    d10 = bsd[(dz0 + 1) * gd.ny + dy0];
+                    d11 = bsd[(dz0 + 1) * gd.ny + dy1 + 1];
+                }
+                const int na = max(d01 - d00, 0), n2 = na + max(d11 - d10, 0);
+                for (int k = 0; k < n2; ++k) {
+                    const int t = k < na ? d00 + k : d10 + (k - na);
+                    const float2 pd = cd[t];
+                    if (!(__builtin_fabsf(pd.x - yh) <= wyd && __builtin_fabsf(pd.y - zh) <= wzd)) continue;
+                    dt3 = dt2; dc3 = dc2;
+                    dt2 = dt1; dc2 = dc1;
+                    dt1 = dt0; dc1 = dc0;
+                    dt0 = t; dc0 = pd;
+                    ++nd;
+                }
+            }
+            const bool kept = short_d && nd <= kNbKeep;
             for (int uz = uz0; uz <= uz1; ++uz) {
                 const int q0 = bsu[uz * gu.ny + uy0], q1 = bsu[uz * gu.ny + uy1 + 1];
                 for (int q = q0; q < q1; ++q) {
@@ -290,29 +337,19 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     const float yu = pu.x, zu = pu.y;
                     if (!(__builtin_fabsf(yu - yh) <= wyu && __builtin_fabsf(zu - zh) <= wzu)) continue;
                     ++n_cu;
+                    if (kept) {
+                        if (nd > 0) pair(q, yu, zu, dt0, dc0.x, dc0.y);
+                        if (nd > 1) pair(q, yu, zu, dt1, dc1.x, dc1.y);
+                        if (nd > 2) pair(q, yu, zu, dt2, dc2.x, dc2.y);
+                        if (nd > 3) pair(q, yu, zu, dt3, dc3.x, dc3.y);
+                        continue;
+                    }
                     for (int dz = dz0; dz <= dz1; ++dz) {
                         const int t0 = bsd[dz * gd.ny + dy0], t1 = bsd[dz * gd.ny + dy1 + 1];
                         for (int t = t0; t < t1; ++t) {
                             const float2 pd = cd[t];
-                            const float yd = pd.x, zd = pd.y;
-                            if (!(__builtin_fabsf(yd - yh) <= wyd && __builtin_fabsf(zd - zh) <= wzd)) continue;
-                            ++n_pairs;
-                            const float ey = (yd + (yu - yd) * tr) - yh;
-                            const float ez = (zd + (zu - zd) * tr) - zh;
-                            const float sc = ey * ey + ez * ez;
-                            if (!(sc <= smax)) continue;
-                            bool take = !found || sc < best;
-                            if (!take && sc == best) {  // ids decide only exact ties
-                                const int32_t uid = b.sid[gu.rs + q], did = b.sid[gd.rs + t];
-                                const int32_t buid = b.sid[gu.rs + bu], bdid = b.sid[gd.rs + bd];
-                                take = uid < buid || (uid == buid && did < bdid);
-                            }
-                            if (take) {
-                                found = true;
-                                best = sc;
-                                bu = q;
-                                bd = t;
-                            }
+                            if (!(__builtin_fabsf(pd.x - yh) <= wyd && __builtin_fabsf(pd.y - zh) <= wzd)) continue;
+                            pair(q, yu, zu, t, pd.x, pd.y);
                         }
                     }
                 }
@@ -796,10 +833,16 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
         bool ok = seeded;
         // stage 1
         if (ok) {
-            float2 cn = b.yz[chain[0]];
+            // two-deep prefetch: the coordinates of hit i+1 and the position of
+            // hit i+2 are in flight while hit i is fitted
+            float2 cn = c0;
+            int32_t pn = L > 1 ? chain[1] : pos0;
             for (int i = 0; i < L; ++i) {
                 const float2 cp = cn;
-                if (i + 1 < L) cn = b.yz[chain[i + 1]];  // next hit, loaded ahead
+                if (i + 1 < L) {
+                    cn = b.yz[pn];
+                    if (i + 2 < L) pn = chain[i + 2];
+                }
                 if (i > 0 && !kf_propagate(s, sX[r0 + i - 1], sX[r0 + i], kc)) {
                     ok = false;
                     break;
@@ -852,6 +895,11 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
             }
             if (down_ok) {
                 miss = 0;
+                // picks leave four at a time (one 16-byte and one 4-byte store)
+                // from a shift register, newest in p0; rows pack oldest-lowest
+                const bool vec = (nr & 3) == 0;  // 16-byte aligned per-tracklet rows
+                int32_t p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+                uint32_t rows4 = 0;
                 SegHdr hn3 = load_hdr(b, seg0 + last);
                 for (int r = last; r >= 0; --r) {
                     const SegHdr h = hn3;
@@ -864,13 +912,41 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
                     Pick pk_;
                     if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
                         kf_update(s, pk_.inn);
-                        b.tl_pick_pos[j * nr + nh] = pk_.pos;
-                        b.tl_pick_row[j * nr + nh] = (uint8_t)r;
+                        if (vec) {
+                            p3 = p2;
+                            p2 = p1;
+                            p1 = p0;
+                            p0 = pk_.pos;
+                            rows4 = (rows4 >> 8) | ((uint32_t)r << 24);
+                            if (((nh + 1) & 3) == 0) {
+                                *reinterpret_cast<int4*>(b.tl_pick_pos + j * nr + nh - 3) = make_int4(p3, p2, p1, p0);
+                                *reinterpret_cast<uint32_t*>(b.tl_pick_row + j * nr + nh - 3) = rows4;
+                            }
+                        } else {
+                            b.tl_pick_pos[j * nr + nh] = pk_.pos;
+                            b.tl_pick_row[j * nr + nh] = (uint8_t)r;
+                        }
                         ++nh;
                         miss = 0;
                     } else if (++miss >= kc.max_miss) {
                         break;
                     }
+                }
+                if (vec) {  // the last picks, fewer than four
+                    const int k = nh & 3;
+                    int32_t* pp = b.tl_pick_pos + j * nr + (nh - k);
+                    uint8_t* pr = b.tl_pick_row + j * nr + (nh - k);
+                    if (k == 3) {
+                        pp[0] = p2;
+                        pp[1] = p1;
+                        pp[2] = p0;
+                    } else if (k == 2) {
+                        pp[0] = p1;
+                        pp[1] = p0;
+                    } else if (k == 1) {
+                        pp[0] = p0;
+                    }
+                    for (int i = 0; i < k; ++i) pr[i] = (uint8_t)(rows4 >> (8 * (4 - k + i)));
                 }
             }
         }
@@ -882,8 +958,23 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
             for (int q = 0; q < 20; ++q) o[q] = 0.0f;
         }
         if (nh >= kc.n_min) {
+            // weights: the picks are read back eight per memory round trip
+            // (atomic max: the order of the tracklets does not matter)
             const uint32_t w = packed_weight(nh, tid);
-            for (int q = 0; q < nh; ++q) atomicMax(&b.weight[b.tl_pick_pos[j * nr + q]], w);
+            const int32_t* pp = b.tl_pick_pos + j * nr;
+            if ((nr & 3) == 0) {
+                for (int q = 0; q < nh; q += 8) {
+                    const int4 a = *reinterpret_cast<const int4*>(pp + q);
+                    int4 c = make_int4(0, 0, 0, 0);
+                    if (q + 4 < nh) c = *reinterpret_cast<const int4*>(pp + q + 4);  // q + 8 <= nr
+                    const int32_t v[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (q + i < nh) atomicMax(&b.weight[v[i]], w);
+                }
+            } else {
+                for (int q = 0; q < nh; ++q) atomicMax(&b.weight[pp[q]], w);
+            }
         }
     }
     if (stats) {
