@@ -645,8 +645,9 @@ __global__ void k_hit_grad_out(AdjBufs a, double2* out) {
 //   in LDS, cut into z slabs when it exceeds kMapGradLds doubles; each wave
 //   stages 64 records in LDS with one coalesced load, then takes one slot at
 //   a time and its 64 lanes add the slot's 4 x 4 x 4 cube (lane = (i, j, e)),
-//   so a wave's LDS atomics never share an address; the box's non-zero
-//   entries then go to the global gradient with FP64 atomics.
+//   so a wave's LDS atomics never share an address (a z stride of 4 mod 16
+//   doubles spreads them evenly over the banks); the box's non-zero entries
+//   then go to the global gradient with FP64 atomics.
 // Tracks of one sector touch ~5 of 16 phi and half of the z coefficients: the
 // global atomics drop from 192 per cluster to about one box per workgroup.
 constexpr int kMapScatterHits = 4096;
@@ -695,7 +696,7 @@ __device__ __forceinline__ int wrap_dphi(int ip, int ref) {
 }
 
 __global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, const GradRec* rec) {
-    __shared__ double acc[kMapGradLds];
+    __shared__ double acc[kMapGradLds + 192];  // the box, then one discard slot per lane and component
     __shared__ GradRec stage[kMapScatterThreads / 64][64];
     __shared__ int lo[3], hi[3], ref;
     const int64_t h0 = (int64_t)blockIdx.x * kMapScatterHits;
@@ -734,35 +735,55 @@ __global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, c
     const bool full_phi = hi[1] - lo[1] + 1 >= kMapNphi;
     const int lp = full_phi ? 0 : lo[1], np = full_phi ? kMapNphi : hi[1] - lo[1] + 1;
     const int lz = lo[2], hz = hi[2];
-    const int slab = 3 * nr * np;        // <= 3 * 16 * 16 = 768
-    const int nzt = kMapGradLds / slab;  // >= 9
+    const int slab = 3 * nr * np;  // <= 3 * 16 * 16 = 768
+    // z stride of the box: 4 mod 16 doubles (a wave's 4 z lanes x 4 phi lanes
+    // then cover every LDS bank once), as small as the z extent allows
+    int nzs = 4;
+    while (nzs < hz - lz + 1 && (nzs + 16) * slab <= kMapGradLds) nzs += 16;
+    const int cstride = nr * np * nzs;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const int li = lane >> 4, lj = (lane >> 2) & 3, le = lane & 3;
-    for (int z0 = lz; z0 <= hz; z0 += nzt) {
-        const int nz = min(nzt, hz - z0 + 1);
-        const int size = slab * nz;
+    for (int z0 = lz; z0 <= hz; z0 += nzs) {
+        const int nz = min(nzs, hz - z0 + 1);
+        const int size = 3 * cstride;
         for (int i = threadIdx.x; i < size; i += blockDim.x) acc[i] = 0.0;
         __syncthreads();
         // each wave stages 64 records with one coalesced load, then adds
-        // them one at a time from LDS
+        // them one at a time from LDS; the next record's fields are read
+        // before this one's adds are issued, so no read waits for the adds
         for (int64_t hw = h0 + (int64_t)wave * 64; hw < h1; hw += (int64_t)nwave * 64) {
             const int64_t hl = hw + lane;
             if (hl < h1) stage[wave][lane] = rec[hl];
             __builtin_amdgcn_wave_barrier();
             const int cnt = (int)min((int64_t)64, h1 - hw);
+            int cell = stage[wave][0].cell;
+            float wr = stage[wave][0].wr[li], wp = stage[wave][0].wphi[lj], wz = stage[wave][0].wz[le];
+            double g0 = stage[wave][0].gc[0], g1 = stage[wave][0].gc[1], g2 = stage[wave][0].gc[2];
             for (int k = 0; k < cnt; ++k) {
-                const GradRec& r = stage[wave][k];
-                const int cell = r.cell;
-                if (cell < 0) continue;
+                const int kn = min(k + 1, cnt - 1);
+                const int cell_n = stage[wave][kn].cell;
+                const float wr_n = stage[wave][kn].wr[li], wp_n = stage[wave][kn].wphi[lj], wz_n = stage[wave][kn].wz[le];
+                const double g0_n = stage[wave][kn].gc[0], g1_n = stage[wave][kn].gc[1], g2_n = stage[wave][kn].gc[2];
+                // every lane always issues its three adds (a lane with nothing
+                // to add adds zero to a slot of its own past the box), so the
+                // compiler can count them and the next record's reads do not
+                // wait for them
                 const int ir = cell & 255, ip = (cell >> 8) & 255, iz = cell >> 16;
                 const int zz = iz + le - z0;
-                if (zz < 0 || zz >= nz) continue;
+                const bool ok = (cell >= 0) & (zz >= 0) & (zz < nz);
                 const int pj = full_phi ? (ip - 1 + lj + kMapNphi) % kMapNphi : wrap_dphi(ip, rf) - 1 + lj - lp;
-                const double w = (double)r.wr[li] * (double)r.wphi[lj] * (double)r.wz[le];
-                const int base = ((ir + li - lr) * np + pj) * nz + zz;
-                const int cstride = nr * np * nz;
-#pragma unroll
-                for (int comp = 0; comp < 3; ++comp) atomicAdd(&acc[comp * cstride + base], r.gc[comp] * w);
+                const double w = ok ? (double)wr * (double)wp * (double)wz : 0.0;
+                const int base = ((ir + li - lr) * np + pj) * nzs + zz;
+                atomicAdd(&acc[ok ? base : kMapGradLds + lane], g0 * w);
+                atomicAdd(&acc[ok ? cstride + base : kMapGradLds + 64 + lane], g1 * w);
+                atomicAdd(&acc[ok ? 2 * cstride + base : kMapGradLds + 128 + lane], g2 * w);
+                cell = cell_n;
+                wr = wr_n;
+                wp = wp_n;
+                wz = wz_n;
+                g0 = g0_n;
+                g1 = g1_n;
+                g2 = g2_n;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -770,7 +791,7 @@ __global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, c
         for (int i = threadIdx.x; i < size; i += blockDim.x) {
             const double v = acc[i];
             if (v == 0.0) continue;
-            const int zz = i % nz, rest = i / nz;
+            const int zz = i % nzs, rest = i / nzs;
             const int pj = rest % np, rest2 = rest / np;
             const int rr = rest2 % nr, comp = rest2 / nr;
             const int iphi = full_phi ? pj : rf + lp + pj;  // map_index wraps it

@@ -182,20 +182,46 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
         }
     }
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < P; i += nt) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const uint32_t x = key[i], w = key[ixj];
-                    const bool asc = (i & k) == 0;
-                    if ((x > w) == asc) {
-                        key[i] = w;
-                        key[ixj] = x;
+    if (P <= nt && nt == 256) {
+        // one key per thread, padded to 256: partners within a wave are
+        // exchanged by lane shuffles, only the three distances of 64 and more
+        // go through LDS
+        uint32_t x = tid < P ? key[tid] : 0xFFFFFFFFu;
+        for (int k = 2; k <= 256; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                uint32_t y;
+                if (j < 64) {
+                    y = __shfl_xor(x, j, 64);
+                } else {
+                    __syncthreads();
+                    key[tid] = x;
+                    __syncthreads();
+                    y = key[tid ^ j];
+                }
+                const bool asc = (tid & k) == 0, low = (tid & j) == 0;
+                const uint32_t mn = x < y ? x : y, mx = x < y ? y : x;
+                x = (low == asc) ? mn : mx;
+            }
+        }
+        __syncthreads();
+        key[tid] = x;
+        __syncthreads();
+    } else {
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < P; i += nt) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint32_t x = key[i], w = key[ixj];
+                        const bool asc = (i & k) == 0;
+                        if ((x > w) == asc) {
+                            key[i] = w;
+                            key[ixj] = x;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     int32_t* bs = b.bin_start + a + seg;
