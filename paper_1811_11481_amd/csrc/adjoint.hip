@@ -123,14 +123,22 @@ template <class A>
 __device__ __forceinline__ D3<A> operator*(D3<A> a, A k) {
     return D3<A>{a.v * k, a.d0 * k, a.d1 * k, a.d2 * k};
 }
+// The reverse sweep needs derivatives, not the forward's rounding: in binary32
+// it divides and takes square roots with the hardware reciprocal and square
+// root (about 1 ulp) instead of the correctly rounded sequences.
+__device__ __forceinline__ float rcp_a(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_a(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_a(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_a(double x) { return sqrt(x); }
+
 template <class A>
 __device__ __forceinline__ D3<A> operator/(D3<A> a, D3<A> b) {
-    const A q = a.v / b.v, ib = A(1) / b.v;
+    const A ib = rcp_a(b.v), q = a.v * ib;
     return D3<A>{q, (a.d0 - q * b.d0) * ib, (a.d1 - q * b.d1) * ib, (a.d2 - q * b.d2) * ib};
 }
 template <class A>
 __device__ __forceinline__ D3<A> dsqrt(D3<A> a) {
-    const A s = sqrt(a.v), h = A(0.5) / s;
+    const A s = sqrt_a(a.v), h = A(0.5) * rcp_a(s);
     return D3<A>{s, a.d0 * h, a.d1 * h, a.d2 * h};
 }
 
@@ -277,7 +285,7 @@ __device__ __forceinline__ void adj_upd(const float C[15], float r0f, float r1f,
                                         A cb, const KC& K) {
     const A r0 = A(r0f), r1 = A(r1f);
     const A s00 = A(C[0]) + A(K.vy), s01 = A(C[1]), s11 = A(C[2]) + A(K.vz);
-    const A idet = A(1) / (s00 * s11 - s01 * s01);
+    const A idet = rcp_a(s00 * s11 - s01 * s01);
     const A a00 = s11 * idet, a01 = -s01 * idet, a11 = s00 * idet;
     A G0[5], G1[5];
 #pragma unroll

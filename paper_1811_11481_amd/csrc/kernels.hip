@@ -703,7 +703,6 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, co
     bool found = false;
     auto consider = [&](int64_t pos, float2 c) {
         const float r0 = c.x - py, r1 = c.y - pz;
-        ++ncand;
         if (!(__builtin_fabsf(r0) <= wy && __builtin_fabsf(r1) <= wz)) return;
         const float w0 = __builtin_fmaf(a00, r0, a01 * r1);
         const float w1 = __builtin_fmaf(a01, r0, a11 * r1);
@@ -741,9 +740,15 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, co
             pos[i] = g.rs + (kk < na ? q00 + kk : q10 + (kk - na));
             c[i] = b.yz[pos[i]];
         }
+        // slots past the end get an infinite y: the window test rejects them
+        // without a branch of their own
 #pragma unroll
-        for (int i = 0; i < kCandChunk; ++i)
-            if (k + i < n2) consider(pos[i], c[i]);
+        for (int i = 0; i < kCandChunk; ++i) {
+            float2 ci = c[i];
+            if (k + i >= n2) ci.x = __builtin_inff();
+            consider(pos[i], ci);
+        }
+        ncand += (unsigned)min(kCandChunk, n2 - k);
     }
     // further rows of a tall window, one row at a time
     for (int bz = z0 + 2; bz <= z1; ++bz) {
@@ -757,8 +762,12 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, co
                 c[i] = b.yz[pos[i]];
             }
 #pragma unroll
-            for (int i = 0; i < kCandChunk; ++i)
-                if (q + i < q1) consider(pos[i], c[i]);
+            for (int i = 0; i < kCandChunk; ++i) {
+                float2 ci = c[i];
+                if (q + i >= q1) ci.x = __builtin_inff();
+                consider(pos[i], ci);
+            }
+            ncand += (unsigned)min(kCandChunk, q1 - q);
         }
     }
     return found;
