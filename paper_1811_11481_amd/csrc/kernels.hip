@@ -741,7 +741,8 @@ __device__ __forceinline__ bool pick_on_row(const Bufs& b, const KfConsts& K, co
             c[i] = b.yz[pos[i]];
         }
         // slots past the end get an infinite y: the window test rejects them
-        // without a branch of their own
+        // without a branch of their own (an infinite y passes only an infinite
+        // window, whose s00 = inf makes a00 zero and the chi2 NaN)
 #pragma unroll
         for (int i = 0; i < kCandChunk; ++i) {
             float2 ci = c[i];
