@@ -865,52 +865,66 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
         KState s;
         const float2 c0 = b.yz[pos0], cm = b.yz[pm], ce = b.yz[pe];
         const bool seeded = seed_from_chain(K, sX[r0], c0.x, c0.y, sX[r0 + m], cm.x, sX[r0 + L - 1], ce.x, ce.y, s);
-        int cur = r0;
+        int cur = r0, last = r0, miss = 0;
         bool ok = seeded;
-        // stage 1
-        if (ok) {
-            // two-deep prefetch: the coordinates of hit i+1 and the position of
-            // hit i+2 are in flight while hit i is fitted
-            float2 cn = c0;
-            int32_t pn = L > 1 ? chain[1] : pos0;
-            for (int i = 0; i < L; ++i) {
-                const float2 cp = cn;
-                if (i + 1 < L) {
-                    cn = b.yz[pn];
-                    if (i + 2 < L) pn = chain[i + 2];
-                }
-                if (i > 0 && !kf_propagate(s, sX[r0 + i - 1], sX[r0 + i], kc)) {
-                    ok = false;
-                    break;
-                }
-                const Innov n = kf_innovation(s, cp.x, cp.y, kc);
-                kf_update(s, n);
-            }
-            st_chain += L;
-        }
         int nh = 0;
         if (ok) {
-            // stage 2
-            cur = r0 + L - 1;
-            int last = cur, miss = 0;
-            // the next row's grid header does not depend on the state: load it
-            // one row ahead so that its latency hides behind the propagation
-            SegHdr hn = load_hdr(b, seg0 + min(cur + 1, nr - 1));
-            for (int r = cur + 1; r < nr && miss < kc.max_miss; ++r) {
-                const SegHdr h = hn;
-                hn = load_hdr(b, seg0 + min(r + 1, nr - 1));
-                if (!kf_propagate(s, sX[r - 1], sX[r], kc)) break;
-                cur = r;
-                ++st_rows;
-                Pick pk_;
-                if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
-                    kf_update(s, pk_.inn);
-                    last = r;
-                    miss = 0;
-                } else {
-                    ++miss;
-                }
+            // stages 1 and 2 in one outward loop: rows of the chain take the
+            // chain's hit, rows beyond it pick a cluster. Each lane runs the
+            // same operations in the same order as two separate loops would,
+            // but a wave no longer waits for its longest chain and then again
+            // for its longest outward pick run: it waits for its longest sum.
+            st_chain += L;
+            // two-deep prefetch along the chain: the coordinates of the next
+            // hit and the position of the one after are in flight
+            float2 cn = c0;
+            int32_t pn = L > 2 ? chain[2] : pos0;
+            {
+                const Innov n = kf_innovation(s, cn.x, cn.y, kc);
+                if (L > 1) cn = b.yz[chain[1]];
+                kf_update(s, n);
             }
+            const int rc = r0 + L;  // first row after the chain
+            // a pick row's grid header does not depend on the state: it is
+            // loaded one row ahead so that its latency hides behind the propagation
+            SegHdr hn = load_hdr(b, seg0 + min(r0 + 1, nr - 1));
+            for (int r = r0 + 1; r < nr && miss < kc.max_miss; ++r) {
+                const bool in_chain = r < rc;
+                const SegHdr h = hn;
+                if (r + 1 >= rc) hn = load_hdr(b, seg0 + min(r + 1, nr - 1));
+                if (!kf_propagate(s, sX[r - 1], sX[r], kc)) {
+                    ok = ok && !in_chain;  // a failed step inside the chain voids the tracklet
+                    break;
+                }
+                cur = r;
+                Innov inn;
+                bool have;
+                if (in_chain) {
+                    const float2 cp = cn;
+                    const int i = r - r0;
+                    if (i + 1 < L) {
+                        cn = b.yz[pn];
+                        if (i + 2 < L) pn = chain[i + 2];
+                    }
+                    inn = kf_innovation(s, cp.x, cp.y, kc);
+                    have = true;
+                    last = r;
+                } else {
+                    ++st_rows;
+                    Pick pk_;
+                    have = pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand);
+                    inn = pk_.inn;
+                    if (have) {
+                        last = r;
+                        miss = 0;
+                    } else {
+                        ++miss;
+                    }
+                }
+                if (have) kf_update(s, inn);
+            }
+        }
+        if (ok) {
             // the state at the end of the outward following is the
             // tracklet's output: the refit starts from it
             float* o = b.tl_state + j * 20;
