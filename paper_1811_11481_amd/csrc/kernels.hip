@@ -1295,13 +1295,12 @@ void enqueue_grid(const Bufs& b, int i0, int i1, hipStream_t st) {
 void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, int max_row, hipStream_t st) {
     const int64_t seg0 = (int64_t)i0 * b.n_rows, nseg = (int64_t)(i1 - i0) * b.n_rows;
     if (nseg <= 0) return;
-    // LDS: two rows of (y, z) and two bin-start arrays (bins <= clusters)
-    int cap = max_row < 1 ? 1 : max_row;
-    size_t bytes = (size_t)cap * 2 * sizeof(float2) + (size_t)(cap + 1) * 2 * sizeof(int32_t);
-    if (bytes > 64 * 1024) {
-        cap = 0;
-        bytes = 0;
-    }
+    // LDS: two rows of (y, z) and two bin-start arrays (bins <= clusters), for
+    // rows of up to `cap` clusters (64 KB per workgroup); a workgroup whose
+    // neighbour rows are larger reads them from global memory
+    const int cap_lds = (int)((64 * 1024 - 2 * sizeof(int32_t)) / (2 * sizeof(float2) + 2 * sizeof(int32_t)));
+    const int cap = max_row < 1 ? 1 : min(max_row, cap_lds);
+    const size_t bytes = (size_t)cap * 2 * sizeof(float2) + (size_t)(cap + 1) * 2 * sizeof(int32_t);
     const int64_t grid = L.xcd_remap ? (nseg + 7) / 8 * 8 : nseg;
     hipLaunchKernelGGL(k_links, dim3((unsigned)grid), dim3(L.block_links), bytes, st, b, seg0, nseg, cap,
                        L.xcd_remap);
