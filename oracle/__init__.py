@@ -86,6 +86,8 @@ def lib():
         L.orc_asin_over.argtypes = [i32, dbl]
         L.orc_seed.restype = i32
         L.orc_seed.argtypes = [ctypes.POINTER(Params), i32, vp, vp]
+        L.orc_pick.restype = i64
+        L.orc_pick.argtypes = [ctypes.POINTER(Params), i32, vp, i64, vp, vp, vp]
         L.orc_refit.restype = i32
         L.orc_refit.argtypes = [ctypes.POINTER(Params), i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_replay_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 10
@@ -245,6 +247,22 @@ def seed(points8, precision=64, params=None):
     st = np.zeros(20, np.float64)
     ok = lib().orc_seed(ctypes.byref(p), precision, pts.ctypes.data, st.ctypes.data)
     return bool(ok), st
+
+
+def pick(state20, ys, zs, precision=64, params=None):
+    """The track-following pick rule on one row: index of the chosen candidate
+    (input order) or -1, and its predicted chi2 (None if nothing is picked)."""
+    p = params if params is not None else default_params()
+    st = np.ascontiguousarray(np.array(state20, dtype=np.float64))
+    if st.shape != (20,):
+        raise ValueError("state must hold 5 parameters and 15 covariance terms")
+    ys = np.ascontiguousarray(np.asarray(ys, dtype=np.float32))
+    zs = np.ascontiguousarray(np.asarray(zs, dtype=np.float32))
+    if ys.shape != zs.shape:
+        raise ValueError("ys and zs must have equal length")
+    chi2 = ctypes.c_double(0.0)
+    c = lib().orc_pick(ctypes.byref(p), precision, st.ctypes.data, len(ys), _ptr(ys), _ptr(zs), ctypes.byref(chi2))
+    return int(c), (chi2.value if c >= 0 else None)
 
 
 def refit(state20, row, rows, ys, zs, precision=64, params=None, replay=None):

@@ -938,6 +938,27 @@ int32_t orc_seed(const orc_params* p, int32_t precision, const double* pts /* x0
     return precision == 32 ? f(0.0f) : f(0.0);
 }
 
+// The pick rule of the track following on one row: candidates (ys, zs) of
+// the row in input order, the predicted state st (p[5], C[15]). Returns the
+// index of the chosen candidate or -1; *chi2 gets its predicted chi2.
+int64_t orc_pick(const orc_params* p, int32_t precision, const double* st, int64_t n, const float* ys,
+                 const float* zs, double* chi2) {
+    auto f = [&](auto zero) -> int64_t {
+        using T = decltype(zero);
+        Consts<T> k(*p);
+        State<T> s;
+        load_state(st, s);
+        const int64_t rs[2] = {0, n};
+        const int32_t sec = 0;
+        const Input in{1, &sec, rs, ys, zs};
+        Innov<T> out{};
+        const int64_t c = pick_on_row(in, k, s, 0, &out);
+        if (c >= 0 && chi2) *chi2 = (double)out.chi2;
+        return c;
+    };
+    return precision == 32 ? f(0.0f) : f(0.0);
+}
+
 // Refit of one hit list (rows ascending) from a start state at `row`.
 // out: state[20] at the innermost hit; out_scalars: chi2, nacc, row.
 // replay (may be NULL): accept bits per hit to reproduce instead of deciding.

@@ -31,8 +31,10 @@ struct Arena {
     int nr = 0;
 };
 
+// Everything a captured launch sequence depends on: every device pointer its
+// kernels take (each in its own slot), the stream, sizes and tuning.
 struct GraphKey {
-    const void* p[12];
+    const void* p[17];
     int64_t v[8];
     bool operator==(const GraphKey& o) const {
         return std::memcmp(p, o.p, sizeof(p)) == 0 && std::memcmp(v, o.v, sizeof(v)) == 0;
@@ -432,14 +434,16 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
         st = ctx->own_stream;
     }
     GraphKey key{};
-    const void* ps[12] = {in->inst_sector, in->row_start, in->y, in->z, out->inst, out->param,
-                          out->cov, out->hit_start, out->hit_id, out->chi2_total, ctx->arena.base, (void*)st};
+    const void* ps[17] = {in->inst_sector, in->row_start, in->y,        in->z,        out->inst,
+                          out->x_ref,       out->alpha,     out->param,   out->cov,     out->chi2,
+                          out->ndf,         out->hit_start, out->hit_id,  out->chi2_total,
+                          ctx->arena.base,  (void*)st,      (void*)ctx->dK};
     std::memcpy(key.p, ps, sizeof(ps));
-    const int64_t vs[8] = {in->n_inst, N, out->cap_tracks, out->cap_hits,
+    const int mrow = max_row(0, in->n_inst);  // sizes the neighbour kernel's LDS staging
+    const int64_t vs[8] = {in->n_inst, N, out->cap_tracks, out->cap_hits, mrow,
                            ctx->tuning.hits_per_bin * 4 + ctx->tuning.xcd_remap * 2 + ctx->tuning.sort_seeds,
                            ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
-                           ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
-                           (int64_t)(intptr_t)out->x_ref ^ (int64_t)(intptr_t)out->chi2};
+                           ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan};
     std::memcpy(key.v, vs, sizeof(vs));
     if (!ctx->has_graph || !(ctx->gkey == key)) {
         if (ctx->has_graph) {
@@ -449,7 +453,7 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
         }
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
         enqueue_reset(b, st);
-        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, max_row(0, in->n_inst), st, nullptr);
+        enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, mrow, st, nullptr);
         enqueue_finish(b, st);
         (void)hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
         hipError_t e = hipStreamEndCapture(st, &ctx->graph);

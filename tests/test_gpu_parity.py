@@ -100,6 +100,28 @@ def test_plain_equals_batched_and_is_deterministic(c1):
     assert tracks_equal(a, b) and tracks_equal(a, c)
 
 
+def test_batched_graph_follows_new_output_buffers(c1):
+    """The batched form replays its captured graph only while every buffer it
+    captured is the same: new alpha/ndf buffers, or x_ref and chi2 exchanged,
+    must give a new capture that writes into the buffers of this call."""
+    from paper_1811_11481_amd import DeviceClusters, Tracks
+    log("C1 batched with new output buffers")
+    ref = run_gpu(c1, batched=False, exports=False)
+    trk = ref["tracker"]
+    dc = DeviceClusters.from_host(c1)
+    first = trk.track(dc, batched=True)
+    assert tracks_equal({"tracks": first.to_numpy()}, ref)
+    fresh = Tracks(first.cap_tracks, first.cap_hits)
+    trk.track(dc, out=fresh, batched=True)
+    assert tracks_equal({"tracks": fresh.to_numpy()}, ref)
+    swapped = Tracks(first.cap_tracks, first.cap_hits)
+    for k in ("inst", "param", "cov", "hit_start", "hit_id", "chi2_total"):
+        setattr(swapped, k, getattr(first, k))
+    swapped.x_ref, swapped.chi2 = first.chi2, first.x_ref
+    trk.track(dc, out=swapped, batched=True)
+    assert tracks_equal({"tracks": swapped.to_numpy()}, ref)
+
+
 @pytest.mark.parametrize("tune", [dict(hits_per_bin=2), dict(hits_per_bin=3, block_tracklet=64, xcd_remap=0),
                                   dict(hits_per_bin=8, block_links=64, block_refit=256, block_scan=512)])
 def test_results_independent_of_tuning(c1, c1_oracle, tune):
