@@ -3,16 +3,18 @@
 
 One step = one pass of the whole hot path (grid, CA links, cleaning and
 starts, tracklets, selection, three-pass refit, compaction, FP64 totals) over
-one synthetic central Pb-Pb-like event (36 sectors x 152 pad rows, 8000
-primaries + 800 secondaries, 2 % noise, ~1.37 M clusters), with the clusters
-already resident in device memory. The timed form is the batched one (one
-launch per stage over all sector instances, replayed as a HIP graph); the
-plain form (every stage launched per sector) is timed beside it.
+one batch of synthetic input with the clusters already resident in device
+memory. The default workload is the batched central event: eight central
+Pb-Pb-like events (36 sectors x 152 pad rows, 8000 primaries + 800
+secondaries, 2 % noise each; 288 sector instances, ~10.9 M clusters) tracked
+in one batch. The timed form is the batched one (one launch per stage over all
+sector instances, replayed as a HIP graph); the plain form (every stage
+launched per sector instance) is timed beside it.
 
 Prints one JSON line (rank 0): clusters/s as `value`, tracks/s, the roofline
-of the dominant kernel (per-stage HIP events measured in this run, and an
-algorithmic byte model fed by the kernels' own work counters) and the oracle
-timed on the host as a CPU baseline.
+of the dominant kernel (per-stage HIP events measured in this run over an
+algorithmic byte model fed by the kernels' own work counters), the other
+workloads, and the oracle timed on the host cores as a CPU baseline.
 """
 from __future__ import annotations
 
@@ -33,7 +35,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 WORKLOADS = {
     "C2": "central Pb-Pb-like event: 36 sectors x 152 pad rows, 8000 primary + 800 secondary helices "
           "(pT exp(0.5 GeV) in [0.1,10], |eta|<0.9, 0.5 T), sigma 0.1 cm, 2% noise",
-    "C2x8": "eight central Pb-Pb-like events (288 sector instances) in one batch",
+    "C2x8": "batched central event: eight central Pb-Pb-like events (36 sectors x 152 pad rows each, 8000 "
+            "primary + 800 secondary helices, 2% noise; 288 sector instances) in one batch",
     "C3": "continuous-readout slice: 100 collisions x Exp(800) tracks, drift shift 0-250 cm, 2% noise",
     "C4": "256 sector instances, log-uniform 50-2000 helices each, 1% noise",
     "C1": "one sector, 200 helices, 1% noise",
@@ -43,7 +46,41 @@ WORKLOADS = {
 
 
 def byte_model(stage: str, st: dict, n_clusters: int, n_seg: int, hits_per_bin: int) -> int:
-    """Algorithmic bytes of one launch of a stage."""
+    """Algorithmic bytes of one launch of a stage: what the method itself must
+    move given its stage barriers, from the kernels' own work counters (caches
+    not credited). Per stage:
+      grid        16 B read + 12 B written per cluster, 4 B per bin and per row
+      links       8 B (y, z) + 8 B (up, dn) per cluster, 4 B per bin
+      clean+start 24 B per cluster (own links, partner links, written links), 4 B per start
+      tracklets   12 B per chain hit, 12 B per visited pick row (bin range, row
+                  table), 8 B per tested candidate, 8 B per picked hit (weight)
+      select      4 B x rows per selected tracklet, 4 B per pick, 4 B per owned hit, 16 B per track
+      refit       12 B per cluster visit (id, y, z) over the three passes,
+                  4 B per accepted cluster, 108 B per output track
+      write       8 B per output cluster"""
+    N = n_clusters
+    nbins = N // max(1, hits_per_bin) + n_seg
+    if stage == "grid":
+        return 16 * N + 12 * N + 4 * (nbins + n_seg)
+    if stage == "links":
+        return 8 * N + 4 * nbins + 8 * N
+    if stage == "clean_starts":
+        return 24 * N + 4 * st["n_starts"]
+    if stage == "tracklets":
+        return 12 * st["n_chain_hits"] + 12 * st["tl_rows_visited"] + 8 * st["tl_candidates"] + 8 * st["tl_picks"]
+    if stage == "select":
+        return 4 * 152 * st["n_selected"] + 4 * st["tl_picks"] + 4 * st["n_selected_hits"] + 16 * st["n_selected"]
+    if stage == "refit":
+        return 12 * st["rf_hit_visits"] + 4 * st["n_track_hits"] + 108 * st["n_tracks"]
+    if stage == "write":
+        return 8 * st["n_track_hits"]
+    return 0
+
+
+def impl_byte_model(stage: str, st: dict, n_clusters: int, n_seg: int, hits_per_bin: int) -> int:
+    """Bytes the implementation's own data layout moves per launch (its 32-byte
+    row headers, 80-byte tracklet states, pick tables, refit records): a second
+    column beside the algorithmic model, never the roofline numerator."""
     N = n_clusters
     if stage == "grid":
         return 24 * N + 32 * n_seg + 4 * (N // max(1, hits_per_bin) + n_seg)
@@ -114,16 +151,39 @@ def stage_roofline(trk, dc, cs, workload, warmup, steps):
     stages = {}
     for name, t in stage_avg.items():
         b = byte_model(name, st, cs.n_clusters, nseg, hpb)
-        stages[name] = {"ms": round(t, 4), "alg_bytes": b,
+        bi = impl_byte_model(name, st, cs.n_clusters, nseg, hpb)
+        stages[name] = {"ms": round(t, 4), "alg_bytes": b, "impl_bytes": bi,
                         "GBps": round(b / (t * 1e-3) / 1e9, 2) if t > 0 and b else None}
     dom = max((k for k in stages if k != "finish"), key=lambda k: stages[k]["ms"])
     dom_bytes = stages[dom]["alg_bytes"]
     achieved = dom_bytes / (stages[dom]["ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+    kname = {"tracklets": "k_tracklet", "refit": "k_refit", "links": "k_links", "grid": "k_grid"}.get(dom, dom)
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic("k_" + dom.rstrip("s") if dom == "tracklets" else "k_" + dom, workload),
-                "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": stages[dom]["ms"]}
+                "traffic": measured_traffic(kname, workload),
+                "alg_bytes_per_launch": dom_bytes, "impl_bytes_per_launch": stages[dom]["impl_bytes"],
+                "avg_launch_ms": stages[dom]["ms"], "work_counters": st}
     return stages, roofline
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Worker threads for the oracle baseline: the cores this process may run
+    on, at most 16 (a one-GPU share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def diff_leg(args, torch, np, synth):
@@ -168,12 +228,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="C2x8", choices=sorted(WORKLOADS))
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick tiling with tpcca_autotune before timing")
-    ap.add_argument("--extra", default="C2x8", help="comma-separated extra workloads timed in the batched form")
+    ap.add_argument("--extra", default="C2,C4,C3", help="comma-separated extra workloads timed in the batched form")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable-refit leg (C5)")
     ap.add_argument("--diff-tracks", type=int, default=100000)
     ap.add_argument("--diff-only", action="store_true",
@@ -273,19 +333,31 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only
-        sample = cs
-        note = "full %s workload (%d clusters), binary32 oracle, 1 thread" % (args.workload, cs.n_clusters)
-        if cs.n_clusters > 3_000_000:
-            k = max(1, int(cs.n_inst * 2_000_000 / cs.n_clusters))
+        nthr = host_threads()
+        # bounded sample: about 1.5 M clusters per worker thread (~10-20 s)
+        sample, note = cs, "full %s workload" % args.workload
+        budget = 1_500_000 * nthr
+        if cs.n_clusters > budget:
+            k = max(1, int(cs.n_inst * budget / cs.n_clusters))
             sample = cs.subset(list(range(k)))
-            note = "first %d of %d instances of %s (%d clusters), binary32 oracle, 1 thread" % (
-                k, cs.n_inst, args.workload, sample.n_clusters)
+            note = "first %d of %d sector instances of %s" % (k, cs.n_inst, args.workload)
         c0 = time.perf_counter()
-        r = oracle.run(sample, 32, threads=1)
+        r = oracle.run(sample, 32, threads=nthr)
         dt = time.perf_counter() - c0
-        cpu = {"value": round(sample.n_clusters / dt, 1), "unit": "clusters/s", "cores": 1, "kind": "oracle",
-               "sample": note, "seconds": round(dt, 3), "tracks_per_s": round(r.n_tracks / dt, 1)}
-        print("[bench] cpu oracle: %.2fs" % dt, file=sys.stderr, flush=True)
+        print("[bench] cpu oracle (%d threads): %.2fs" % (nthr, dt), file=sys.stderr, flush=True)
+        # one thread on one central event, for the per-core rate
+        one = sample.subset(list(range(min(36, sample.n_inst))))
+        c1 = time.perf_counter()
+        oracle.run(one, 32, threads=1)
+        dt1 = time.perf_counter() - c1
+        print("[bench] cpu oracle (1 thread, %d instances): %.2fs" % (one.n_inst, dt1), file=sys.stderr, flush=True)
+        cpu = {"value": round(sample.n_clusters / dt, 1), "unit": "clusters/s", "cores": nthr, "kind": "oracle",
+               "sample": "%s (%d clusters), binary32 oracle, %d worker threads over sector instances"
+                         % (note, sample.n_clusters, nthr),
+               "seconds": round(dt, 3), "tracks_per_s": round(r.n_tracks / dt, 1),
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+               "single_thread": {"clusters_per_s": round(one.n_clusters / dt1, 1), "seconds": round(dt1, 3),
+                                 "sample": "first %d instances (%d clusters)" % (one.n_inst, one.n_clusters)}}
 
     line = {
         "metric": METRIC,

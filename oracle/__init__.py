@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
         ("max_miss", ctypes.c_int32),
         ("hits_per_bin", ctypes.c_int32),
         ("n_threads", ctypes.c_int32),
+        ("planes_f32", ctypes.c_int32),
     ]
 
 
@@ -286,9 +287,17 @@ def refit(state20, row, rows, ys, zs, precision=64, params=None, replay=None):
     return bool(ok), out, sc[0], int(sc[1]), int(sc[2]), masks[:n]
 
 
-def replay_f64(st0, row0, hit_start, hit_rows, ys, zs, masks, params=None):
-    """FP64 replay of refits with given start states and accept masks."""
-    p = params if params is not None else default_params()
+def replay_f64(st0, row0, hit_start, hit_rows, ys, zs, masks, params=None, planes_f32=True):
+    """FP64 replay of refits with given start states and accept masks.
+
+    The comparison of the binary32 tracker with binary64 arithmetic is made on
+    the same hits, masks and detector: by default the pad-row planes are the
+    binary32 positions the tracker is given (its row_x parameters), not their
+    exact decimal values, which differ by up to 7.6e-6 cm. That difference
+    alone moves the q/pT of a short track by ~1e-4 of its scale, and it is a
+    difference of geometry, not of arithmetic precision."""
+    p = Params.from_buffer_copy(params if params is not None else default_params())
+    p.planes_f32 = 1 if planes_f32 else 0
     n = len(row0)
     st0 = np.ascontiguousarray(np.asarray(st0, dtype=np.float64).reshape(n, 20))
     row0 = np.ascontiguousarray(np.asarray(row0, dtype=np.int32))

@@ -59,6 +59,8 @@ typedef struct {
     int32_t max_miss;      // consecutive empty rows that end the following
     int32_t hits_per_bin;  // grid occupancy target
     int32_t n_threads;     // CPU worker threads over instances (0 = 1)
+    int32_t planes_f32;    // 1: pad-row planes at their binary32 positions in both
+                           // modes (the positions the tracker is given), 0: exact
 } orc_params;
 
 void orc_default_params(orc_params* p) {
@@ -79,6 +81,7 @@ void orc_default_params(orc_params* p) {
     p->max_miss = 8;
     p->hits_per_bin = 1;
     p->n_threads = 1;
+    p->planes_f32 = 0;
 }
 }
 
@@ -103,7 +106,10 @@ struct Consts {
     explicit Consts(const orc_params& p) {
         n_rows = p.n_rows;
         X.resize(n_rows);
-        for (int i = 0; i < n_rows; ++i) X[i] = (T)plane_x(i);
+        // the binary32 mode always sees the rounded planes; the FP64 mode sees
+        // them too when it replays a binary32 result, so that both evaluate
+        // the same detector and differ only in their arithmetic
+        for (int i = 0; i < n_rows; ++i) X[i] = p.planes_f32 ? (T)(float)plane_x(i) : (T)plane_x(i);
         dxu.assign(n_rows, 0); dxd.assign(n_rows, 0);
         wyu.assign(n_rows, 0); wzu.assign(n_rows, 0); wyd.assign(n_rows, 0); wzd.assign(n_rows, 0);
         tr.assign(n_rows, 0);

@@ -162,11 +162,10 @@ def test_c2_parameters_against_fp64_replay(c2, c2_oracle):
     sigma = np.sqrt(out[:, 5 + np.array([0, 2, 5, 9, 14])])
     err_p = np.abs(p32 - out[:, :5]) / np.maximum(np.abs(out[:, :5]), floors)
     log("max |p|-relative parameter error vs FP64: %s; above 1e-4: %s" % (err_p.max(axis=0), (err_p > 1e-4).sum(0)))
-    # relative to the parameter's scale: its magnitude, a floor, or its own
-    # statistical error when it is not significant (short tracks' q/pT)
-    err = np.abs(p32 - out[:, :5]) / np.maximum(np.maximum(np.abs(out[:, :5]), floors), sigma)
-    assert np.all(err <= 1e-4), err.max(axis=0)
-    assert np.mean(err_p <= 1e-4) > 0.999
+    # the stated bound on every track and parameter: |dp| <= 1e-4 max(|p|, floor)
+    assert np.all(err_p <= 1e-4), err_p.max(axis=0)
+    # report only: the error in units of each parameter's own statistical error
+    log("max error in sigma units: %s" % (np.abs(p32 - out[:, :5]) / sigma).max(axis=0))
     rel_chi2 = np.abs(T["chi2"] - chi2) / np.maximum(chi2, 1.0)
     assert np.all(rel_chi2 <= 1e-3)
 

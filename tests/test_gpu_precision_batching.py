@@ -62,7 +62,8 @@ def test_precision_report_central_event():
     rep["hit_lists_vs_fp64_tracker"] = {"identical": bool(same_tracks), "tracks_fp32": len(a), "tracks_fp64": len(b),
                                         "common_identical_lists": len(a & b)}
     log("PRECISION_REPORT " + json.dumps(rep))
-    assert rep["param_q_over_pt"]["max_rel_sigma_scale"] <= 1e-4
+    for nm in names:  # the stated bound, |dp| <= 1e-4 max(|p|, floor), on every track
+        assert rep["param_" + nm]["max_rel"] <= 1e-4, (nm, rep["param_" + nm])
     assert rep["cov"]["max_rel_to_sqrt_cii_cjj"] <= 1e-3
     assert len(a & b) >= 0.995 * len(b)
 

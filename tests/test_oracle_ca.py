@@ -352,3 +352,16 @@ def test_time_shift_invariance(c2s, c2s_run):
     q1 = qa.evaluate(shifted, r.trk_hit_start, r.trk_hit)
     assert abs(q0["efficiency"] - q1["efficiency"]) < 0.005
     assert abs(r.n_tracks - c2s_run.n_tracks) <= 0.01 * c2s_run.n_tracks
+
+
+def test_binary32_parameters_within_1e4_of_fp64_replay(c2s, c2s_run):
+    """Every selected track of the binary32 oracle against the binary64 replay of
+    its own cluster list, start state and accept masks (same detector: binary32
+    pad-row planes): |dp| <= 1e-4 max(|p|, floor) for every parameter."""
+    inp = oracle.refit_inputs(c2s_run, c2s)
+    ok, out, _ = oracle.replay_f64(inp["st0"], inp["row0"], inp["hit_start"], inp["hit_rows"], inp["ys"],
+                                   inp["zs"], inp["masks"])
+    assert ok.all() and len(ok) == c2s_run.n_tracks
+    floors = np.array([1.0, 1.0, 0.01, 0.01, 0.1])
+    d = np.abs(c2s_run.trk_param - out[:, :5])
+    assert np.all(d <= 1e-4 * np.maximum(np.abs(out[:, :5]), floors)), (d / np.maximum(np.abs(out[:, :5]), floors)).max(0)

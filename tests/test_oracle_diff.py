@@ -91,7 +91,7 @@ def test_frozen_refit_without_map_is_the_replay(c1_inputs):
     ok, chi2 = _f(inp)
     ok0, chi2_0 = _f(inp, coef=np.zeros(oracle.MAP_SIZE))
     okr, _, chi2_r = oracle.replay_f64(inp["st0"], inp["row0"], inp["hit_start"], inp["hit_rows"], inp["ys"],
-                                       inp["zs"], inp["masks"])
+                                       inp["zs"], inp["masks"], planes_f32=False)
     assert ok.all() and ok0.all() and okr.all()
     assert np.array_equal(chi2, chi2_0) and np.array_equal(chi2, chi2_r)
     assert np.array_equal(chi2, res.trk_chi2)  # same decisions as the FP64 run itself

@@ -328,3 +328,24 @@ def test_replay_reproduces_decisions():
                          zs[-1]], 64)[1]
     ok2, st2, chi22, nacc2, _, masks2 = oracle.refit(start, rows[0], rows, ys, zs, 64, replay=masks)
     assert ok2 and np.array_equal(masks, masks2) and np.array_equal(st, st2) and chi2 == chi22
+
+
+def test_replay_uses_the_binary32_pad_row_planes():
+    """The FP64 replay of a binary32 result evaluates the detector the tracker
+    was given: pad-row planes at their binary32 positions. A noiseless helix
+    sampled on those planes is recovered to FP64 accuracy by the replay, and
+    not by the exact-plane FP64 refit, whose planes differ by up to 7.6e-6 cm."""
+    h = LocalHelix(2.0, 1, tanl=0.4, phi0=0.2, alpha=0.0)
+    rows = np.arange(0, 100)
+    xs32 = np.array([float(np.float32(plane_x(r))) for r in rows])
+    assert np.abs(xs32 - np.array([plane_x(r) for r in rows])).max() > 1e-6
+    truth = np.array([h.at(x) for x in xs32])
+    st0 = np.concatenate([truth[0], np.diag([1.0, 1.0, 0.25, 0.25, 400.0])[np.tril_indices(5)]])
+    hs = np.array([0, len(rows)])
+    masks = np.full(len(rows), 7, np.uint8)
+    ok, out, chi2 = oracle.replay_f64(st0[None], [rows[0]], hs, rows, truth[:, 0], truth[:, 1], masks)
+    assert ok.all() and chi2[0] < 1e-12
+    assert np.allclose(out[0, :5], truth[0], rtol=1e-9, atol=1e-9)
+    ok, out, chi2 = oracle.replay_f64(st0[None], [rows[0]], hs, rows, truth[:, 0], truth[:, 1], masks,
+                                      planes_f32=False)
+    assert ok.all() and chi2[0] > 1e-9
