@@ -19,8 +19,10 @@
  *    cluster id used everywhere (outputs, exports) is the index into y/z.
  *    Coordinates are sector-local: x is the pad-row plane params.row_x[r], y
  *    along the row, z along the drift (any origin: only z differences are used).
- *  - All track arithmetic is IEEE binary32 in a fixed operation order (no FMA
- *    contraction); only cross-track sums are FP64.
+ *  - All track arithmetic is IEEE binary32 in a fixed operation order: a
+ *    fused multiply-add (one rounding) exactly where the written algorithm
+ *    has one and nowhere else (no compiler contraction), correctly rounded
+ *    division and square root; only cross-track sums are FP64.
  *  - Status codes are the only error channel; tpcca_last_error() gives text.
  *    Calls are asynchronous on `hip_stream` except where a host output is
  *    returned (track counts), which synchronises the stream once.
@@ -144,24 +146,54 @@ const char* tpcca_last_error(const tpcca_ctx* ctx);
 tpcca_status tpcca_set_tuning(tpcca_ctx* ctx, const tpcca_tuning* tuning);
 tpcca_status tpcca_get_tuning(const tpcca_ctx* ctx, tpcca_tuning* out);
 
-/* Plain form: every stage is launched once per instance, instances one after
- * another on `hip_stream`. */
+/* Plain form: the sector tracking of Section 2 (hit grid, cellular-automaton
+ * neighbour finding and evolution, start hits, Kalman tracklets with the
+ * inward pass of Section 3, selection) and the final three-pass fit of
+ * Section 3, every stage launched once per instance, instances one after
+ * another on `hip_stream`. Reads row_start back to the host once (CSR checks,
+ * launch sizes) and the track counts once at the end (two synchronisations).
+ * Errors: TPCCA_E_ARG (malformed CSR, non-finite coordinate, null pointers),
+ * TPCCA_E_CAPACITY (out->n_tracks / n_hits then hold the required sizes, or a
+ * per-row / per-instance limit above), TPCCA_E_DEVICE, TPCCA_E_OOM. */
 tpcca_status tpcca_track(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* hip_stream);
 
-/* Batched form: every stage is launched once over all instances; the launch
- * sequence is captured in a HIP graph and replayed while pointers, sizes and
- * tuning are unchanged. Output identical to tpcca_track (bit for bit). */
+/* Batched form of tpcca_track: the same computation with every stage launched
+ * once over all instances (the paper fills a GPU by processing several events
+ * at once, Section 2); the launch sequence is captured in a HIP graph and
+ * replayed while every captured pointer, the sizes and the tuning are
+ * unchanged. Output identical to tpcca_track (bit for bit); same errors. */
 tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out,
                                  void* hip_stream);
 
-/* Time the batched form over candidate tunings on `sample` (median of
- * `repeats` runs each) and write the fastest to *out (also set on ctx).
- * Outputs go to internal buffers. */
+/* Batched form without any host synchronisation (Section 5's design keeps the
+ * whole chain on the GPU with no host transfers between steps): the CSR is
+ * checked on the device, and the counts stay on the device.
+ *   counts: device int64[2], written with (n_tracks, n_hits) found (even when
+ *           above capacity); status: device int32[1], written with a
+ *           tpcca_status (TPCCA_OK, TPCCA_E_ARG, TPCCA_E_CAPACITY,
+ *           TPCCA_E_INTERNAL) when the stream reaches the end of the call.
+ * The host return value covers only what the host can see (null pointers,
+ * sizes, launch failures, scratch allocation); out->n_tracks / n_hits are not
+ * written. Sizes the neighbour kernel's LDS staging for the largest row
+ * allowed (TPCCA_MAX_ROW_CLUSTERS), so it may run slower than the
+ * synchronising forms. Output buffers identical to tpcca_track_batched. */
+tpcca_status tpcca_track_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
+                               int32_t* status, void* hip_stream);
+
+/* Autotuner of the batching form (a project extension: the paper gives no
+ * tuning procedure). Time the batched form over candidate tunings on `sample`
+ * (median of `repeats` runs each) and write the fastest to *out (also set on
+ * ctx). Outputs go to internal buffers; results never depend on the tuning. */
 tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_t repeats,
                             tpcca_tuning* out, void* hip_stream);
 
 /* ---- exports of intermediate results of the last track call (device
- * outputs in cluster-id space; sizes from tpcca_export_sizes). ---- */
+ * outputs in cluster-id space; sizes from tpcca_export_sizes). They expose
+ * the per-stage results of Section 2 (grid, neighbour links before and after
+ * the evolution step, tracklets, selected segments with the refit's accept
+ * bits of Section 3) for stage-by-stage comparison. Each returns TPCCA_E_ARG
+ * when no track call has completed on the context; asynchronous on
+ * hip_stream. ---- */
 /* host sizes[8]: n_clusters, n_segments, n_starts, n_selected, n_selected_hits, n_tracks, n_track_hits, n_rows */
 tpcca_status tpcca_export_sizes(tpcca_ctx* ctx, int64_t* sizes, void* hip_stream);
 /* sorted_id[n_clusters]: cluster id at each grid position; bin_start[n_clusters + n_segments + 1]

@@ -1,8 +1,9 @@
 """Build the HIP library libtpcca.so (gfx950) in-tree with hipcc.
 
-Flags that the binary32 contract depends on: -ffp-contract=off (no fused
-multiply-add), denormals kept, correctly rounded division and square root
-(the HIP default), packed-FP32 instructions disabled.
+Flags that the binary32 contract depends on: -ffp-contract=off (the compiler
+fuses no multiply-add by itself; the kernels write every fused multiply-add of
+the algorithm explicitly), denormals kept, correctly rounded division and
+square root, packed-FP32 instructions disabled.
 """
 from __future__ import annotations
 

@@ -34,8 +34,8 @@ struct Arena {
 // Everything a captured launch sequence depends on: every device pointer its
 // kernels take (each in its own slot), the stream, sizes and tuning.
 struct GraphKey {
-    const void* p[17];
-    int64_t v[8];
+    const void* p[19];
+    int64_t v[9];
     bool operator==(const GraphKey& o) const {
         return std::memcmp(p, o.p, sizeof(p)) == 0 && std::memcmp(v, o.v, sizeof(v)) == 0;
     }
@@ -383,6 +383,64 @@ tpcca_status finish_call(tpcca_ctx* ctx, const Bufs& b, tpcca_tracks* out, int64
     return TPCCA_OK;
 }
 
+// Everything a captured launch sequence depends on: every device pointer its
+// kernels take, the stream, the sizes and the tuning.
+GraphKey graph_key(const tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out, hipStream_t st,
+                   const int64_t* counts, const int32_t* status, int mrow) {
+    GraphKey key{};
+    const void* ps[19] = {in->inst_sector, in->row_start, in->y,        in->z,        out->inst,
+                          out->x_ref,       out->alpha,     out->param,   out->cov,     out->chi2,
+                          out->ndf,         out->hit_start, out->hit_id,  out->chi2_total,
+                          ctx->arena.base,  (void*)st,      (void*)ctx->dK, counts,     status};
+    std::memcpy(key.p, ps, sizeof(ps));
+    const int64_t vs[9] = {in->n_inst, in->n_clusters, out->cap_tracks, out->cap_hits, mrow,
+                           ctx->tuning.hits_per_bin * 4 + ctx->tuning.xcd_remap * 2 + ctx->tuning.sort_seeds,
+                           ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
+                           ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
+                           counts != nullptr ? 1 : 0};
+    std::memcpy(key.v, vs, sizeof(vs));
+    return key;
+}
+
+// Launch the context's graph, capturing `enqueue` first when the key differs
+// from the captured one.
+template <class F>
+tpcca_status replay_graph(tpcca_ctx* ctx, const GraphKey& key, hipStream_t st, F&& enqueue) {
+    if (!ctx->has_graph || !(ctx->gkey == key)) {
+        if (ctx->has_graph) {
+            (void)hipGraphExecDestroy(ctx->gexec);
+            (void)hipGraphDestroy(ctx->graph);
+            ctx->has_graph = false;
+        }
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        enqueue();
+        hipError_t e = hipStreamEndCapture(st, &ctx->graph);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(ctx->graph);
+            return hip_fail(ctx, e, "hipGraphInstantiate");
+        }
+        ctx->has_graph = true;
+        ctx->gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->gexec, st));
+    return TPCCA_OK;
+}
+
+// Kernels of the asynchronous forms: counters cleared, the CSR checked on the
+// device (a malformed input turns every stage into a no-op), all stages over
+// all instances with the neighbour staging sized for the largest row allowed,
+// then the counts and the status.
+void enqueue_async_body(const Bufs& b, const Launch& L, const tpcca_clusters* in, int64_t N, int n_min,
+                        int64_t* counts, int32_t* status, hipStream_t st) {
+    enqueue_reset(b, st);
+    enqueue_check_csr(b, st);
+    enqueue_range(b, L, 0, in->n_inst, 0, N, n_min, TPCCA_MAX_ROW_CLUSTERS, st, nullptr);
+    enqueue_finish(b, st);
+    enqueue_async_status(b, counts, status, st);
+}
+
 tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* stream, bool batched) {
     tpcca_status s = check_io(ctx, in, out);
     if (s != TPCCA_OK) return s;
@@ -433,42 +491,42 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
         if (!ctx->own_stream) HIP_TRY(hipStreamCreate(&ctx->own_stream));
         st = ctx->own_stream;
     }
-    GraphKey key{};
-    const void* ps[17] = {in->inst_sector, in->row_start, in->y,        in->z,        out->inst,
-                          out->x_ref,       out->alpha,     out->param,   out->cov,     out->chi2,
-                          out->ndf,         out->hit_start, out->hit_id,  out->chi2_total,
-                          ctx->arena.base,  (void*)st,      (void*)ctx->dK};
-    std::memcpy(key.p, ps, sizeof(ps));
     const int mrow = max_row(0, in->n_inst);  // sizes the neighbour kernel's LDS staging
-    const int64_t vs[8] = {in->n_inst, N, out->cap_tracks, out->cap_hits, mrow,
-                           ctx->tuning.hits_per_bin * 4 + ctx->tuning.xcd_remap * 2 + ctx->tuning.sort_seeds,
-                           ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
-                           ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan};
-    std::memcpy(key.v, vs, sizeof(vs));
-    if (!ctx->has_graph || !(ctx->gkey == key)) {
-        if (ctx->has_graph) {
-            (void)hipGraphExecDestroy(ctx->gexec);
-            (void)hipGraphDestroy(ctx->graph);
-            ctx->has_graph = false;
-        }
-        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    const GraphKey key = graph_key(ctx, in, out, st, nullptr, nullptr, mrow);
+    s = replay_graph(ctx, key, st, [&] {
         enqueue_reset(b, st);
         enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, mrow, st, nullptr);
         enqueue_finish(b, st);
         (void)hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
-        hipError_t e = hipStreamEndCapture(st, &ctx->graph);
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(ctx->graph);
-            return hip_fail(ctx, e, "hipGraphInstantiate");
-        }
-        ctx->has_graph = true;
-        ctx->gkey = key;
-    }
-    HIP_TRY(hipGraphLaunch(ctx->gexec, st));
+    });
+    if (s != TPCCA_OK) return s;
     HIP_TRY(hipStreamSynchronize(st));
     return finish_call(ctx, b, out, nseg);
+}
+
+// The batched sequence with the input checked on the device and the counts
+// and status left on the device: nothing is read back, nothing waits.
+tpcca_status run_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
+                       int32_t* status, void* stream) {
+    tpcca_status s = check_io(ctx, in, out);
+    if (s != TPCCA_OK) return s;
+    if (!counts || !status) return fail(ctx, TPCCA_E_ARG, "null counts or status");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t N = in->n_clusters;
+    if (in->n_inst > 0 && !in->row_start) return fail(ctx, TPCCA_E_ARG, "null row_start");
+    s = ensure_arena(ctx, std::max<int64_t>(N, 1), std::max<int64_t>((int64_t)in->n_inst * ctx->params.n_rows, 1),
+                     std::max<int64_t>(in->n_inst, 1));
+    if (s != TPCCA_OK) return s;
+    const Bufs b = make_bufs(ctx, in, out);
+    const Launch L = make_launch(ctx->tuning);
+    ctx->has_last = false;  // exports need the host counts of a synchronising call
+    if (st == nullptr) {
+        if (!ctx->own_stream) HIP_TRY(hipStreamCreate(&ctx->own_stream));
+        st = ctx->own_stream;
+    }
+    const GraphKey key = graph_key(ctx, in, out, st, counts, status, TPCCA_MAX_ROW_CLUSTERS);
+    return replay_graph(ctx, key, st, [&] { enqueue_async_body(b, L, in, N, ctx->params.n_min, counts, status, st); });
 }
 
 }  // namespace
@@ -681,6 +739,12 @@ tpcca_status tpcca_track(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks*
 tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* hip_stream) {
     if (!ctx) return TPCCA_E_ARG;
     return run(ctx, in, out, hip_stream, true);
+}
+
+tpcca_status tpcca_track_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
+                               int32_t* status, void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    return run_async(ctx, in, out, counts, status, hip_stream);
 }
 
 tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_t repeats, tpcca_tuning* out,

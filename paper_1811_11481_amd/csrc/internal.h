@@ -15,6 +15,8 @@ enum : uint32_t {
     ERR_TID_CAP = 4u,    // more than 2^20 tracklets in one instance
     ERR_OUT_CAP = 8u,    // output capacity exceeded
     ERR_SCRATCH = 16u,   // internal scratch bound violated (should not happen)
+    ERR_CSR = 32u,       // raised only by the device CSR check before any stage runs:
+                         // every stage kernel then returns at entry (constant during them)
 };
 
 // statistics slots
@@ -130,6 +132,10 @@ void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t s
 void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);
 void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);
 void enqueue_finish(const Bufs& b, hipStream_t st);
+// device-side input check (the forms that do not read row_start to the host)
+void enqueue_check_csr(const Bufs& b, hipStream_t st);
+// counts (n_tracks, n_hits) and a tpcca_status code left on the device
+void enqueue_async_status(const Bufs& b, int64_t* counts, int32_t* status, hipStream_t st);
 
 // exports (cluster-id space)
 void enqueue_export_grid(const Bufs& b, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz,

@@ -33,6 +33,12 @@ constexpr int kKeyShift = 14;         // key = bin << 14 | local index (both < 1
 
 __device__ __forceinline__ void raise_err(Counters* c, unsigned int bit) { atomicOr(&c->err, bit); }
 
+// The device CSR check (run before every stage when the host does not check
+// the input) found a malformed input: the stage kernels then do nothing. The
+// flag is written only by that check, so it is the same for every thread of
+// every later kernel.
+__device__ __forceinline__ bool input_rejected(const Counters* c) { return (c->err & ERR_CSR) != 0u; }
+
 __device__ __forceinline__ void stat_add(Counters* c, int slot, unsigned long long v) {
     // wave-aggregated add
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -94,6 +100,7 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
     __shared__ float red[4][4];
     __shared__ int sh_i[4];
     __shared__ float sh_f[4];
+    if (input_rejected(b.ctr)) return;
     const int64_t seg = seg0 + blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
     int64_t a = b.row_start[seg], e = b.row_start[seg + 1];
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
     const int64_t l = remap ? xcd_logical(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    if (l >= nseg) return;
+    if (l >= nseg || input_rejected(b.ctr)) return;
     const int64_t seg = seg0 + l;
     const int r = (int)(seg % nr);
     const int64_t a = b.row_start[seg], e = b.row_start[seg + 1];
@@ -394,6 +401,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
 
 // ------------------------------------------------------------------ clean
 __global__ void k_clean(Bufs b, int64_t c0, int64_t c1) {
+    if (input_rejected(b.ctr)) return;
     for (int64_t p = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < c1;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t u = b.up[p], d = b.dn[p];
@@ -436,6 +444,7 @@ __device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long
 template <class Op>
 __global__ void k_scan_part(Op op, unsigned long long* part) {
     __shared__ unsigned long long sh[17];
+    if (input_rejected(op.b.ctr)) return;
     const int64_t b0 = op.begin(), e0 = op.end();
     const int64_t n = e0 > b0 ? e0 - b0 : 0;
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -451,6 +460,7 @@ __global__ void k_scan_part(Op op, unsigned long long* part) {
 // single workgroup of kScanBlocks threads
 __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, Counters* ctr, int slot) {
     __shared__ unsigned long long sh[17];
+    if (input_rejected(ctr)) return;  // the range counts stay zero: no later stage has work
     const unsigned long long v = part[threadIdx.x];
     unsigned long long tot;
     const unsigned long long ex = block_excl_scan(v, sh, &tot);
@@ -467,6 +477,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, Cou
 template <class Op>
 __global__ void k_scan_apply(Op op, const unsigned long long* part, const Counters* ctr, int slot) {
     __shared__ unsigned long long sh[17];
+    if (input_rejected(ctr)) return;
     const int64_t b0 = op.begin(), e0 = op.end();
     const int64_t n = e0 > b0 ? e0 - b0 : 0;
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -1185,6 +1196,43 @@ __global__ void k_reset_counters(Counters* c) {
     for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0ull;
 }
 
+// ------------------------------------------------------------------ device input check
+// CSR over (instance, row): row_start[0] = 0, non-decreasing, last entry =
+// n_clusters, at most TPCCA_MAX_ROW_CLUSTERS per row (the host check of the
+// synchronising forms, done where the data already is).
+__global__ void k_check_csr(Bufs b, int64_t n_entries) {
+    const int64_t* rs = b.row_start;
+    unsigned int bits = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_entries;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = rs[i];
+        if (i == 0 && v != 0) bits |= ERR_ARG;
+        if (i == n_entries - 1 && v != b.n_clusters) bits |= ERR_ARG;
+        if (i + 1 < n_entries) {
+            const int64_t d = rs[i + 1] - v;
+            if (d < 0) bits |= ERR_ARG;
+            else if (d > kLargeRow) bits |= ERR_ROW_CAP;
+        }
+    }
+    if (bits) raise_err(b.ctr, bits | ERR_CSR);
+}
+
+// Counts and status of the whole call, left on the device (one thread).
+__global__ void k_async_status(Bufs b, int64_t* counts, int32_t* status) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long tot = b.ctr->slot[SL_TRK][0];
+    const int64_t nt = (int64_t)(tot >> 32), nh = (int64_t)(tot & 0xFFFFFFFFull);
+    counts[0] = nt;
+    counts[1] = nh;
+    const unsigned int e = b.ctr->err;
+    int32_t s = 0;                                         // TPCCA_OK
+    if (e & ERR_ARG) s = 1;                                // TPCCA_E_ARG
+    else if (e & (ERR_ROW_CAP | ERR_TID_CAP)) s = 2;       // TPCCA_E_CAPACITY
+    else if (e & ERR_SCRATCH) s = 5;                       // TPCCA_E_INTERNAL
+    else if ((e & ERR_OUT_CAP) || nt > b.cap_tracks || nh > b.cap_hits) s = 2;
+    *status = s;
+}
+
 // ------------------------------------------------------------------ exports
 __global__ void k_export_grid(Bufs b, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz, float* meta,
                               int64_t nseg) {
@@ -1336,6 +1384,15 @@ void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st
 
 void enqueue_finish(const Bufs& b, hipStream_t st) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, b);
+}
+
+void enqueue_check_csr(const Bufs& b, hipStream_t st) {
+    const int64_t n = (int64_t)b.n_inst * b.n_rows + 1;
+    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, b, n);
+}
+
+void enqueue_async_status(const Bufs& b, int64_t* counts, int32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_async_status, dim3(1), dim3(64), 0, st, b, counts, status);
 }
 
 void enqueue_export_grid(const Bufs& b, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz,

@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_CAPACITY", 3: "E_DEVICE", 4: "E_OOM",
 # every extern "C" symbol of include/tpcca.h
 EXPORTED = [
     "tpcca_default_params", "tpcca_default_tuning", "tpcca_create", "tpcca_destroy", "tpcca_last_error",
-    "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_track", "tpcca_track_batched", "tpcca_autotune",
+    "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_track", "tpcca_track_batched", "tpcca_track_async",
+    "tpcca_autotune",
     "tpcca_export_sizes", "tpcca_export_grid", "tpcca_export_links", "tpcca_export_tracklets",
     "tpcca_export_selected", "tpcca_get_stats", "tpcca_get_stage_times", "tpcca_fp32_selfcheck",
     "tpcca_refit_fwd", "tpcca_refit_bwd",
@@ -172,6 +173,8 @@ def load():
         for fn in ("tpcca_track", "tpcca_track_batched"):
             getattr(L, fn).restype = st
             getattr(L, fn).argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(TracksC), vp]
+        L.tpcca_track_async.restype = st
+        L.tpcca_track_async.argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(TracksC), vp, vp, vp]
         L.tpcca_autotune.restype = st
         L.tpcca_autotune.argtypes = [vp, ctypes.POINTER(Clusters), i32, ctypes.POINTER(Tuning), vp]
         L.tpcca_export_sizes.restype = st
@@ -357,6 +360,15 @@ class Tracker:
         if check:
             self._check(st)
         out.status = st
+        return out
+
+    def track_async(self, clusters: DeviceClusters, out: Tracks, counts, status, stream=None) -> Tracks:
+        """Batched form with nothing read back: `counts` (int64[2] device tensor)
+        receives (n_tracks, n_hits) and `status` (int32[1]) the status code when
+        the stream reaches the end of the call; out.n_tracks / n_hits are not set."""
+        cin, cout = clusters.c_struct(), out.c_struct()
+        self._check(self.lib.tpcca_track_async(self.h, ctypes.byref(cin), ctypes.byref(cout), _ptr(counts),
+                                               _ptr(status), _stream(stream)))
         return out
 
     def autotune(self, clusters: DeviceClusters, repeats: int = 3, stream=None) -> Tuning:
