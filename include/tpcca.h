@@ -180,6 +180,29 @@ tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca
 tpcca_status tpcca_track_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
                                int32_t* status, void* hip_stream);
 
+/* Allocation-free form of tpcca_track_async, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc. The same kernels and outputs as tpcca_track_async
+ * (bit for bit), with every scratch buffer carved from one fixed static device
+ * array of TPCCA_NOALLOC_SCRATCH_BYTES per device (resolved at context
+ * creation, held until the process ends). It calls no hipMalloc, hipFree,
+ * graph or stream creation and never waits: the kernels are enqueued on
+ * hip_stream directly (the null stream is used as given). The caller still
+ * passes inputs, outputs, counts and status (as for tpcca_track_async).
+ * Limits: n_clusters <= TPCCA_NOALLOC_MAX_CLUSTERS and n_inst <=
+ * TPCCA_NOALLOC_MAX_INST (these fit for n_rows <= 152; more pad rows need a
+ * larger per-tracklet table); an input above them, or whose scratch layout
+ * would exceed the array, returns TPCCA_E_CAPACITY before anything is
+ * enqueued. Every call on one GPU, from any context, shares that GPU's array:
+ * calls that overlap on one GPU race (serialise them on one stream). The
+ * kernels clear what must start at zero themselves; exports are not
+ * available after this call. */
+#define TPCCA_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define TPCCA_NOALLOC_MAX_CLUSTERS 131072
+#define TPCCA_NOALLOC_MAX_INST 64
+tpcca_status tpcca_track_async_noalloc(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out,
+                                       int64_t* counts, int32_t* status, void* hip_stream);
+
 /* Autotuner of the batching form (a project extension: the paper gives no
  * tuning procedure). Time the batched form over candidate tunings on `sample`
  * (median of `repeats` runs each) and write the fastest to *out (also set on

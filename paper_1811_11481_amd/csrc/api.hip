@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,12 @@
 #include "internal.h"
 
 using namespace tpcca;
+
+// Scratch of the allocation-free entry point: one fixed array per device,
+// held by every device the library is loaded on until the process ends. Host
+// code never uses this name as an address: the per-device address comes from
+// hipGetSymbolAddress at context creation.
+static __device__ __align__(256) unsigned char scratch[TPCCA_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -70,6 +77,7 @@ struct tpcca_ctx {
     hipStream_t own_stream = nullptr;
     bool events = false;
     float stage_ms[8] = {};
+    void* noalloc = nullptr;  // this device's address of the static scratch array
     // differentiable refit: per-track / per-cluster scratch, tape, status, last forward
     void* adj_base = nullptr;
     size_t adj_bytes = 0;
@@ -171,7 +179,8 @@ struct Layout {
     }
 };
 
-void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool really, size_t* total) {
+void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool really, size_t* total,
+           void* at = nullptr) {
     const int nr = ctx->params.n_rows;
     const int64_t cap_s = N / 3 + ninst + 1;
     const int64_t cap_sel = N / std::max(1, ctx->params.n_min) + ninst + 1;
@@ -190,7 +199,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     size_t o_part = L.add(8 * kScanBlocks);
     *total = L.total;
     if (!really) return;
-    char* base = (char*)ctx->arena.base;
+    char* base = (char*)(at ? at : ctx->arena.base);
     b.yz = (float2*)(base + o_yz);
     b.sid = (int32_t*)(base + o_sid);
     b.pos_of = (int32_t*)(base + o_pos);
@@ -304,10 +313,12 @@ tpcca_status load_rowstart(tpcca_ctx* ctx, const tpcca_clusters* in, hipStream_t
     return TPCCA_OK;
 }
 
-Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out) {
+Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out, void* at = nullptr,
+               int64_t N = -1, int64_t nseg = -1, int64_t ninst = -1) {
     Bufs b{};
     size_t total;
-    carve(ctx, b, ctx->arena.N, ctx->arena.nseg, ctx->arena.ninst, true, &total);
+    if (at) carve(ctx, b, N, nseg, ninst, true, &total, at);
+    else carve(ctx, b, ctx->arena.N, ctx->arena.nseg, ctx->arena.ninst, true, &total);
     b.K = ctx->dK;
     b.ctr = ctx->dctr;
     b.n_rows = ctx->params.n_rows;
@@ -504,6 +515,54 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
     return finish_call(ctx, b, out, nseg);
 }
 
+// Device addresses of the static scratch array, one per device, resolved once
+// per device with that device current.
+std::mutex g_scratch_mu;
+void* g_scratch_at[64] = {};
+
+tpcca_status resolve_scratch(tpcca_ctx* ctx) {
+    if (ctx->device >= 64) return TPCCA_OK;  // the allocation-free form then reports an error
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_at[ctx->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_scratch_at[ctx->device] = p;
+    }
+    ctx->noalloc = g_scratch_at[ctx->device];
+    return TPCCA_OK;
+}
+
+// The asynchronous sequence on the static scratch array: kernels enqueued
+// directly on the caller's stream (no graph, no allocation, no wait).
+tpcca_status run_noalloc(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
+                         int32_t* status, void* stream) {
+    tpcca_status s = check_io(ctx, in, out);
+    if (s != TPCCA_OK) return s;
+    if (!counts || !status) return fail(ctx, TPCCA_E_ARG, "null counts or status");
+    if (!ctx->noalloc) return fail(ctx, TPCCA_E_DEVICE, "static scratch address not resolved for this device");
+    if (in->n_inst > 0 && !in->row_start) return fail(ctx, TPCCA_E_ARG, "null row_start");
+    const int64_t N = in->n_clusters;
+    if (N > TPCCA_NOALLOC_MAX_CLUSTERS || in->n_inst > TPCCA_NOALLOC_MAX_INST)
+        return fail(ctx, TPCCA_E_CAPACITY, "input above the allocation-free form's limits "
+                                           "(TPCCA_NOALLOC_MAX_CLUSTERS, TPCCA_NOALLOC_MAX_INST)");
+    const int64_t N1 = std::max<int64_t>(N, 1), nseg1 = std::max<int64_t>((int64_t)in->n_inst * ctx->params.n_rows, 1),
+                  ninst1 = std::max<int64_t>(in->n_inst, 1);
+    Bufs probe{};
+    size_t total = 0;
+    carve(ctx, probe, N1, nseg1, ninst1, false, &total);
+    if (total > (size_t)TPCCA_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, TPCCA_E_CAPACITY, "input needs more than TPCCA_NOALLOC_SCRATCH_BYTES of scratch");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const Bufs b = make_bufs(ctx, in, out, ctx->noalloc, N1, nseg1, ninst1);
+    const Launch L = make_launch(ctx->tuning);
+    ctx->has_last = false;  // exports need the host counts of a synchronising call
+    hipStream_t st = (hipStream_t)stream;
+    enqueue_async_body(b, L, in, N, ctx->params.n_min, counts, status, st);
+    HIP_TRY(hipGetLastError());
+    return TPCCA_OK;
+}
+
 // The batched sequence with the input checked on the device and the counts
 // and status left on the device: nothing is read back, nothing waits.
 tpcca_status run_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
@@ -689,6 +748,11 @@ tpcca_status tpcca_create(const tpcca_params* params, const tpcca_tuning* tuning
         return TPCCA_E_DEVICE;
     }
     std::memset(ctx->hctr, 0, sizeof(Counters));
+    if (resolve_scratch(ctx) != TPCCA_OK) {
+        fprintf(stderr, "tpcca_create: %s\n", ctx->err.c_str());
+        tpcca_destroy(ctx);
+        return TPCCA_E_DEVICE;
+    }
     *out = ctx;
     return TPCCA_OK;
 }
@@ -745,6 +809,12 @@ tpcca_status tpcca_track_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_t
                                int32_t* status, void* hip_stream) {
     if (!ctx) return TPCCA_E_ARG;
     return run_async(ctx, in, out, counts, status, hip_stream);
+}
+
+tpcca_status tpcca_track_async_noalloc(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
+                                       int32_t* status, void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    return run_noalloc(ctx, in, out, counts, status, hip_stream);
 }
 
 tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_t repeats, tpcca_tuning* out,

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_CAPACITY", 3: "E_DEVICE", 4: "E_OOM",
 EXPORTED = [
     "tpcca_default_params", "tpcca_default_tuning", "tpcca_create", "tpcca_destroy", "tpcca_last_error",
     "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_track", "tpcca_track_batched", "tpcca_track_async",
-    "tpcca_autotune",
+    "tpcca_track_async_noalloc", "tpcca_autotune",
     "tpcca_export_sizes", "tpcca_export_grid", "tpcca_export_links", "tpcca_export_tracklets",
     "tpcca_export_selected", "tpcca_get_stats", "tpcca_get_stage_times", "tpcca_fp32_selfcheck",
     "tpcca_refit_fwd", "tpcca_refit_bwd",
@@ -173,8 +173,9 @@ def load():
         for fn in ("tpcca_track", "tpcca_track_batched"):
             getattr(L, fn).restype = st
             getattr(L, fn).argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(TracksC), vp]
-        L.tpcca_track_async.restype = st
-        L.tpcca_track_async.argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(TracksC), vp, vp, vp]
+        for fn in ("tpcca_track_async", "tpcca_track_async_noalloc"):
+            getattr(L, fn).restype = st
+            getattr(L, fn).argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(TracksC), vp, vp, vp]
         L.tpcca_autotune.restype = st
         L.tpcca_autotune.argtypes = [vp, ctypes.POINTER(Clusters), i32, ctypes.POINTER(Tuning), vp]
         L.tpcca_export_sizes.restype = st
@@ -369,6 +370,13 @@ class Tracker:
         cin, cout = clusters.c_struct(), out.c_struct()
         self._check(self.lib.tpcca_track_async(self.h, ctypes.byref(cin), ctypes.byref(cout), _ptr(counts),
                                                _ptr(status), _stream(stream)))
+        return out
+
+    def track_async_noalloc(self, clusters: DeviceClusters, out: Tracks, counts, status, stream=None) -> Tracks:
+        """track_async on the library's static scratch array (no allocation)."""
+        cin, cout = clusters.c_struct(), out.c_struct()
+        self._check(self.lib.tpcca_track_async_noalloc(self.h, ctypes.byref(cin), ctypes.byref(cout), _ptr(counts),
+                                                       _ptr(status), _stream(stream)))
         return out
 
     def autotune(self, clusters: DeviceClusters, repeats: int = 3, stream=None) -> Tuning:
