@@ -95,6 +95,8 @@ def lib():
         L.orc_map_eval.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.orc_refit_frozen_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 11
+        L.orc_vertex_z.restype = dbl
+        L.orc_vertex_z.argtypes = [ctypes.POINTER(Params), dbl, vp]
         _lib = L
     return _lib
 
@@ -415,3 +417,14 @@ def frozen_chi2_grad_fd(inp, coef=None, coef_index=(), h_param=(1e-4, 1e-4, 1e-6
         ok_all &= okp & okm
         gc[j] = (cp[okp & okm].sum() - cm[okp & okm].sum()) / (2.0 * h_coef)
     return ok_all, gp, gc
+
+
+def vertex_z(x, states, params=None):
+    """z of the point of closest approach to the beam line (FP64) of each track
+    state (y, z, sin phi, tan lambda, q/pT) at local x."""
+    p = params if params is not None else default_params()
+    x = np.broadcast_to(np.asarray(x, np.float64), (len(states),))
+    st = np.ascontiguousarray(np.asarray(states, np.float64).reshape(-1, 5))
+    L = lib()
+    return np.array([L.orc_vertex_z(ctypes.byref(p), float(x[i]), st[i].ctypes.data) for i in range(len(st))])
+

@@ -1126,3 +1126,39 @@ void orc_refit_frozen_f64(const orc_params* p, int64_t n_tracks, const double* s
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- vertex z
+// Continuous readout (Section 4): a track's collision time is unknown, and the
+// position of closest approach to the beam line, taken as the z of its primary
+// vertex, stands in for it. Sector frames share the beam line as their z axis,
+// so the local frame of the state is used directly.
+//
+// The helix through (x, y) with direction angle phi and curvature c = kB q/pT
+// passes its point closest to the beam line where its direction is
+// perpendicular to the position: with A = x cos phi + y sin phi and
+// B = -x sin phi + y cos phi, the turning angle d from the state to that point
+// solves A cos d + (B + 1/c) sin d = 0, i.e. d = atan2(-A c, 1 + B c) (the
+// solution nearest to the state). The transverse path is s = d / c, written
+// as s = -A / (1 + B c) * atan(w) / w with w = -A c / (1 + B c) where
+// 1 + B c > 0 (straight line: s = -A), and z0 = z + tan(lambda) s.
+extern "C" {
+
+double orc_vertex_z(const orc_params* p, double x, const double* state5) {
+    const double kB = -0.00299792458 * p->bz;
+    const double y = state5[0], z = state5[1], sp = state5[2], tl = state5[3], q = state5[4];
+    const double cp = std::sqrt(1.0 - sp * sp);
+    const double c = kB * q;
+    const double A = x * cp + y * sp, B = -x * sp + y * cp;
+    const double den = 1.0 + B * c;
+    double s;
+    if (den > 0.0) {
+        const double w = -A * c / den;
+        const double g = (w == 0.0) ? 1.0 : std::atan(w) / w;
+        s = -A / den * g;
+    } else {
+        s = std::atan2(-A * c, den) / c;
+    }
+    return z + tl * s;
+}
+
+}  // extern "C"
