@@ -1162,3 +1162,73 @@ double orc_vertex_z(const orc_params* p, double x, const double* state5) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- track-model compression
+// Section 5.1: the entropy of the stored clusters is reduced by keeping, for
+// clusters attached to tracks, only their residuals to the track model; the
+// model is the track fitted in the coordinates the clusters are stored in
+// (no calibration correction). Encoder and decoder must predict the same
+// positions, so the model is evaluated in binary32 in the tracker's own
+// operation order: from the track parameters at its innermost cluster, the
+// helix step of the tracker moves the state row by row outward, and each
+// cluster (rows ascending) is predicted where the state crosses its row.
+// Residual = cluster - prediction, in units of a step that is a power of two
+// (so the scaling is exact), rounded to the nearest integer (ties to even).
+// kResEscape marks a residual outside int16 or a cluster after a step that
+// fails (the cluster would then be stored uncompressed).
+extern "C" {
+
+enum { kResEscape = -32768 };
+
+int32_t orc_track_residuals(const orc_params* p, const double* params5, int32_t n, const int32_t* rows,
+                            const double* ys, const double* zs, int32_t step_log2, int16_t* q_out) {
+    Consts<float> k(*p);
+    State<float> s{};
+    for (int i = 0; i < 5; ++i) s.p[i] = (float)params5[i];
+    const float scale = std::ldexp(1.0f, -step_log2);  // 1 / step, exact
+    int cur = n > 0 ? rows[0] : 0;
+    bool ok = true;
+    int32_t n_esc = 0;
+    for (int i = 0; i < n; ++i) {
+        while (ok && cur < rows[i]) {
+            if (!propagate(s, k.X[cur], k.X[cur + 1], k)) ok = false;
+            else ++cur;
+        }
+        if (!ok || rows[i] < cur) {
+            q_out[2 * i] = q_out[2 * i + 1] = (int16_t)kResEscape;
+            n_esc += 1;
+            continue;
+        }
+        const float r[2] = {(float)ys[i] - s.p[0], (float)zs[i] - s.p[1]};
+        for (int c = 0; c < 2; ++c) {
+            const float q = std::nearbyint(r[c] * scale);
+            const bool fits = q >= -32767.0f && q <= 32767.0f;
+            q_out[2 * i + c] = fits ? (int16_t)q : (int16_t)kResEscape;
+            n_esc += fits ? 0 : 1;
+        }
+    }
+    return n_esc;
+}
+
+// Decoder: the clusters back from the parameters, the rows and the residuals
+// (the same model; an escaped residual decodes to NaN).
+void orc_track_decode(const orc_params* p, const double* params5, int32_t n, const int32_t* rows,
+                      const int16_t* q, int32_t step_log2, double* ys, double* zs) {
+    Consts<float> k(*p);
+    State<float> s{};
+    for (int i = 0; i < 5; ++i) s.p[i] = (float)params5[i];
+    const float step = std::ldexp(1.0f, step_log2);
+    int cur = n > 0 ? rows[0] : 0;
+    bool ok = true;
+    for (int i = 0; i < n; ++i) {
+        while (ok && cur < rows[i]) {
+            if (!propagate(s, k.X[cur], k.X[cur + 1], k)) ok = false;
+            else ++cur;
+        }
+        const bool esc_y = !ok || q[2 * i] == kResEscape, esc_z = !ok || q[2 * i + 1] == kResEscape;
+        ys[i] = esc_y ? std::nan("") : (double)(s.p[0] + (float)q[2 * i] * step);
+        zs[i] = esc_z ? std::nan("") : (double)(s.p[1] + (float)q[2 * i + 1] * step);
+    }
+}
+
+}  // extern "C"
