@@ -96,9 +96,9 @@ def lib():
         L.orc_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.orc_refit_frozen_f64.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 11
         L.orc_track_residuals.restype = i32
-        L.orc_track_residuals.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, vp, i32, vp]
+        L.orc_track_residuals.argtypes = [ctypes.POINTER(Params), vp, i32, i32, vp, vp, vp, i32, vp]
         L.orc_track_decode.restype = None
-        L.orc_track_decode.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, i32, vp, vp]
+        L.orc_track_decode.argtypes = [ctypes.POINTER(Params), vp, i32, i32, vp, vp, i32, vp, vp]
         L.orc_vertex_z.restype = dbl
         L.orc_vertex_z.argtypes = [ctypes.POINTER(Params), dbl, vp]
         _lib = L
@@ -436,29 +436,32 @@ def vertex_z(x, states, params=None):
 RES_ESCAPE = -32768
 
 
-def track_residuals(params5, rows, ys, zs, step_log2=-7, params=None):
+def track_residuals(params5, rows, ys, zs, step_log2=-7, params=None, row0=None):
     """Quantised residuals (int16 [n, 2]) of a track's clusters (rows
-    ascending) to the binary32 track model started from params5 at the first
-    row; returns (residuals, number of escaped values)."""
+    ascending) to the binary32 track model started from params5 at row0 (the
+    first cluster's row by default); returns (residuals, number of escaped
+    values)."""
     p = params if params is not None else default_params()
     pr = np.ascontiguousarray(np.asarray(params5, np.float64))
     rows = np.ascontiguousarray(np.asarray(rows, np.int32))
     ys = np.ascontiguousarray(np.asarray(ys, np.float64))
     zs = np.ascontiguousarray(np.asarray(zs, np.float64))
     q = np.zeros((max(len(rows), 1), 2), np.int16)
-    n_esc = lib().orc_track_residuals(ctypes.byref(p), pr.ctypes.data, len(rows), _ptr(rows), _ptr(ys), _ptr(zs),
-                                      int(step_log2), q.ctypes.data)
+    r0 = int(rows[0]) if row0 is None else int(row0)
+    n_esc = lib().orc_track_residuals(ctypes.byref(p), pr.ctypes.data, r0, len(rows), _ptr(rows), _ptr(ys),
+                                      _ptr(zs), int(step_log2), q.ctypes.data)
     return q[:len(rows)], int(n_esc)
 
 
-def track_decode(params5, rows, q, step_log2=-7, params=None):
+def track_decode(params5, rows, q, step_log2=-7, params=None, row0=None):
     """Clusters (ys, zs) decoded from the parameters, rows and residuals."""
     p = params if params is not None else default_params()
     pr = np.ascontiguousarray(np.asarray(params5, np.float64))
     rows = np.ascontiguousarray(np.asarray(rows, np.int32))
     q = np.ascontiguousarray(np.asarray(q, np.int16).reshape(-1, 2))
     ys, zs = np.zeros(max(len(rows), 1)), np.zeros(max(len(rows), 1))
-    lib().orc_track_decode(ctypes.byref(p), pr.ctypes.data, len(rows), _ptr(rows), q.ctypes.data, int(step_log2),
-                           ys.ctypes.data, zs.ctypes.data)
+    r0 = int(rows[0]) if row0 is None else int(row0)
+    lib().orc_track_decode(ctypes.byref(p), pr.ctypes.data, r0, len(rows), _ptr(rows), q.ctypes.data,
+                           int(step_log2), ys.ctypes.data, zs.ctypes.data)
     return ys[:len(rows)], zs[:len(rows)]
 

@@ -1169,9 +1169,10 @@ double orc_vertex_z(const orc_params* p, double x, const double* state5) {
 // model is the track fitted in the coordinates the clusters are stored in
 // (no calibration correction). Encoder and decoder must predict the same
 // positions, so the model is evaluated in binary32 in the tracker's own
-// operation order: from the track parameters at its innermost cluster, the
-// helix step of the tracker moves the state row by row outward, and each
-// cluster (rows ascending) is predicted where the state crosses its row.
+// operation order: from the track parameters at their reference row (the
+// final fit's innermost row, at or below the first cluster), the helix step of
+// the tracker moves the state row by row outward, and each cluster (rows
+// ascending) is predicted where the state crosses its row.
 // Residual = cluster - prediction, in units of a step that is a power of two
 // (so the scaling is exact), rounded to the nearest integer (ties to even).
 // kResEscape marks a residual outside int16 or a cluster after a step that
@@ -1180,13 +1181,13 @@ extern "C" {
 
 enum { kResEscape = -32768 };
 
-int32_t orc_track_residuals(const orc_params* p, const double* params5, int32_t n, const int32_t* rows,
+int32_t orc_track_residuals(const orc_params* p, const double* params5, int32_t row0, int32_t n, const int32_t* rows,
                             const double* ys, const double* zs, int32_t step_log2, int16_t* q_out) {
     Consts<float> k(*p);
     State<float> s{};
     for (int i = 0; i < 5; ++i) s.p[i] = (float)params5[i];
     const float scale = std::ldexp(1.0f, -step_log2);  // 1 / step, exact
-    int cur = n > 0 ? rows[0] : 0;
+    int cur = row0;
     bool ok = true;
     int32_t n_esc = 0;
     for (int i = 0; i < n; ++i) {
@@ -1212,13 +1213,13 @@ int32_t orc_track_residuals(const orc_params* p, const double* params5, int32_t 
 
 // Decoder: the clusters back from the parameters, the rows and the residuals
 // (the same model; an escaped residual decodes to NaN).
-void orc_track_decode(const orc_params* p, const double* params5, int32_t n, const int32_t* rows,
+void orc_track_decode(const orc_params* p, const double* params5, int32_t row0, int32_t n, const int32_t* rows,
                       const int16_t* q, int32_t step_log2, double* ys, double* zs) {
     Consts<float> k(*p);
     State<float> s{};
     for (int i = 0; i < 5; ++i) s.p[i] = (float)params5[i];
     const float step = std::ldexp(1.0f, step_log2);
-    int cur = n > 0 ? rows[0] : 0;
+    int cur = row0;
     bool ok = true;
     for (int i = 0; i < n; ++i) {
         while (ok && cur < rows[i]) {

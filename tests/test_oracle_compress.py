@@ -59,13 +59,16 @@ def test_round_trip_and_entropy_on_found_tracks():
     r = oracle.run(cs, 32)
     seg = np.searchsorted(cs.row_start, r.trk_hit, side="right") - 1
     rows = (seg % 152).astype(np.int32)
+    xplanes = np.array([np.float32(plane_x(i)) for i in range(152)])
     allq = []
     for t in range(r.n_tracks):
         a, b = r.trk_hit_start[t], r.trk_hit_start[t + 1]
         ids = r.trk_hit[a:b]
-        q, n_esc = oracle.track_residuals(r.trk_param[t], rows[a:b], cs.y[ids], cs.z[ids])
+        row0 = int(np.nonzero(xplanes == np.float32(r.trk_x[t]))[0][0])  # the final fit's reference row
+        assert row0 <= rows[a]
+        q, n_esc = oracle.track_residuals(r.trk_param[t], rows[a:b], cs.y[ids], cs.z[ids], row0=row0)
         assert n_esc == 0
-        yd, zd = oracle.track_decode(r.trk_param[t], rows[a:b], q)
+        yd, zd = oracle.track_decode(r.trk_param[t], rows[a:b], q, row0=row0)
         assert np.all(np.abs(yd - cs.y[ids]) <= STEP / 2 + 1e-5)
         assert np.all(np.abs(zd - cs.z[ids]) <= STEP / 2 + 1e-5)
         allq.append(q)
