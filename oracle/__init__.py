@@ -48,6 +48,8 @@ class Params(ctypes.Structure):
         ("hits_per_bin", ctypes.c_int32),
         ("n_threads", ctypes.c_int32),
         ("planes_f32", ctypes.c_int32),
+        ("chi2_merge", ctypes.c_double),
+        ("merge_max_gap", ctypes.c_int32),
     ]
 
 
@@ -79,8 +81,15 @@ def lib():
         L.orc_get_tracklets.argtypes = [vp] + [vp] * 8
         L.orc_get_selected.argtypes = [vp] + [vp] * 5
         L.orc_get_tracks.argtypes = [vp] + [vp] * 11
+        L.orc_merge.restype = i64
+        L.orc_merge.argtypes = [vp, ctypes.POINTER(Params), i32, vp, vp, vp, vp, vp]
+        L.orc_merged_hits.restype = i64
+        L.orc_merged_hits.argtypes = [vp]
+        L.orc_get_merged.argtypes = [vp] + [vp] * 13
         L.orc_propagate.restype = i32
         L.orc_propagate.argtypes = [ctypes.POINTER(Params), i32, vp, dbl, dbl]
+        L.orc_rotate.restype = i32
+        L.orc_rotate.argtypes = [ctypes.POINTER(Params), i32, vp, vp, dbl]
         L.orc_update.restype = dbl
         L.orc_update.argtypes = [ctypes.POINTER(Params), i32, vp, dbl, dbl]
         L.orc_asin_over.restype = dbl
@@ -170,8 +179,10 @@ class OracleResult:
         return int(self.trk_inst.shape[0])
 
 
-def run(cs, precision: int = 32, params: Params | None = None, threads: int = 1) -> OracleResult:
-    """Track a ClusterSet (instances x rows CSR) with the oracle."""
+def run(cs, precision: int = 32, params: Params | None = None, threads: int = 1, inst_event=None) -> OracleResult:
+    """Track a ClusterSet (instances x rows CSR) with the oracle. With
+    inst_event (the event of each instance) the sector tracks are also merged
+    across sectors; the result then carries a `merged` dict."""
     L = lib()
     p = params if params is not None else default_params()
     p.n_threads = threads
@@ -216,13 +227,32 @@ def run(cs, precision: int = 32, params: Params | None = None, threads: int = 1)
         tot = np.zeros(2, np.float64)
         L.orc_get_tracks(h, _ptr(ti), _ptr(tsel), _ptr(tx), _ptr(ta), _ptr(tpar), _ptr(tcov), _ptr(tchi2), _ptr(tndf),
                          _ptr(ths), _ptr(thit), _ptr(tot))
+        merged = None
+        if inst_event is not None:
+            ev = np.ascontiguousarray(np.asarray(inst_event, dtype=np.int32))
+            nm = int(L.orc_merge(h, ctypes.byref(p), int(cs.n_inst), inst_sector.ctypes.data, ev.ctypes.data,
+                                 row_start.ctypes.data, _ptr(y), _ptr(z)))
+            nmh = int(L.orc_merged_hits(h))
+            m = {"next": np.zeros(nt, np.int32), "src": np.zeros(nm, np.int32), "nseg": np.zeros(nm, np.int32),
+                 "inst": np.zeros(nm, np.int32), "x_ref": np.zeros(nm), "alpha": np.zeros(nm),
+                 "param": np.zeros(nm * 5), "cov": np.zeros(nm * 15), "chi2": np.zeros(nm),
+                 "ndf": np.zeros(nm, np.int32), "hit_start": np.zeros(nm + 1, np.int64),
+                 "hit_id": np.zeros(nmh, np.int32), "state2": np.zeros(nt * 20)}
+            L.orc_get_merged(h, *[_ptr(m[k]) for k in ("next", "src", "nseg", "inst", "x_ref", "alpha", "param",
+                                                            "cov", "chi2", "ndf", "hit_start", "hit_id", "state2")])
+            m["param"] = m["param"].reshape(nm, 5)
+            m["cov"] = m["cov"].reshape(nm, 15)
+            m["state2"] = m["state2"].reshape(nt, 20)
+            merged = m
     finally:
         L.orc_free(h)
-    return OracleResult(
+    res = OracleResult(
         precision, nr, sorted_id, bin_start, g_ny, g_nz, np.stack(meta, axis=1), up, dn, upc, dnc,
         start_hit, start_inst, start_tid, nhits, rowhit.reshape(ns, nr), state.reshape(ns, 20), srow, weight,
         sel_tl, sel_hs, sel_hit, sel_mask, sel_status, ti, tsel, tx, ta, tpar.reshape(nt, 5),
         tcov.reshape(nt, 15), tchi2, tndf, ths, thit, float(tot[0]), int(tot[1]))
+    res.merged = merged
+    return res
 
 
 # ---------------------------------------------------------------- primitives
@@ -233,6 +263,15 @@ def propagate(state20, x1, x2, precision=64, params=None):
         raise ValueError("state must hold 5 parameters and 15 covariance terms")
     ok = lib().orc_propagate(ctypes.byref(p), precision, st.ctypes.data, float(x1), float(x2))
     return bool(ok), st
+
+
+def rotate(state20, x, d, precision=64, params=None):
+    """Rotate a state at local x into the frame turned by d; returns (ok, state20, new x)."""
+    p = params if params is not None else default_params()
+    st = np.ascontiguousarray(np.array(state20, dtype=np.float64))
+    xx = np.array([x], np.float64)
+    ok = lib().orc_rotate(ctypes.byref(p), precision, st.ctypes.data, xx.ctypes.data, float(d))
+    return bool(ok), st, float(xx[0])
 
 
 def update(state20, my, mz, precision=64, params=None):

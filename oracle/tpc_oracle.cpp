@@ -36,6 +36,7 @@
 #include <cstdint>
 #include <cstring>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 extern "C" {
@@ -61,6 +62,8 @@ typedef struct {
     int32_t n_threads;     // CPU worker threads over instances (0 = 1)
     int32_t planes_f32;    // 1: pad-row planes at their binary32 positions in both
                            // modes (the positions the tracker is given), 0: exact
+    double chi2_merge;     // cross-sector merge: max chi2 (5 parameters) of a segment pair
+    int32_t merge_max_gap; // cross-sector merge: max rows between the continued segment's end and the next
 } orc_params;
 
 void orc_default_params(orc_params* p) {
@@ -82,6 +85,8 @@ void orc_default_params(orc_params* p) {
     p->hits_per_bin = 1;
     p->n_threads = 1;
     p->planes_f32 = 0;
+    p->chi2_merge = 25.0;
+    p->merge_max_gap = 24;
 }
 }
 
@@ -103,6 +108,8 @@ struct Consts {
     T smax, nsig, chi2_pick, chi2_rej, sinphi_max, cov_reset, q_max, u_max2;
     T c0[5];
     int n_min, max_miss, hpb;
+    T chi2_merge, rot_c, rot_s;  // merge cut; cos and sin of one sector's opening (20 degrees)
+    int merge_max_gap;
     explicit Consts(const orc_params& p) {
         n_rows = p.n_rows;
         X.resize(n_rows);
@@ -140,6 +147,10 @@ struct Consts {
         n_min = p.n_min;
         max_miss = p.max_miss;
         hpb = p.hits_per_bin < 1 ? 1 : p.hits_per_bin;
+        chi2_merge = (T)p.chi2_merge;
+        merge_max_gap = p.merge_max_gap;
+        rot_c = (T)std::cos(20.0 * 3.14159265358979323846 / 180.0);
+        rot_s = (T)std::sin(20.0 * 3.14159265358979323846 / 180.0);
     }
 };
 
@@ -246,6 +257,64 @@ bool propagate(State<T>& s, T x1, T x2, const Consts<T>& k) {
     return true;
 }
 
+// Rotation of the state into the frame of a neighbouring sector (the second
+// phase of Section 2 merges segments across sectors; Section 4: the refit
+// follows the helix through arbitrary rotations). The frame turns by d
+// (cos d = ca, sin d = sa): the point (x, y) becomes (x ca + y sa, -x sa + y ca),
+// the direction angle phi becomes phi - d; z, tan lambda and q/pT are frame
+// independent. The new state is taken at the new x of the point. Covariance:
+// with the new reference plane fixed, a shift dy of the point moves it by
+// (dy sa, dy ca) in the new frame; going back along the track (direction phi'
+// in the new frame) to the plane changes y' by dy ca - dy sa tan phi' =
+// dy cos phi / cos phi', z' by -dy sa tan(lambda) / cos phi' and, along the
+// curved path, sin phi' by -c sa dy (c = kB q/pT the curvature); a change of
+// sin phi gives d sin phi' = (cos phi' / cos phi) d sin phi. Fails (state
+// unchanged) unless the track still moves outward in the new frame with
+// |sin phi'| below the guard.
+template <class T>
+bool rotate(State<T>& s, T& x, T ca, T sa, const Consts<T>& k) {
+    const T one = (T)1;
+    const T sf = s.p[2];
+    const T cf = std::sqrt(std::fma(-sf, sf, one));
+    const T sn = std::fma(sf, ca, -(cf * sa));
+    const T cn = std::fma(cf, ca, sf * sa);
+    if (!(cn > (T)0) || !(std::fabs(sn) < k.sinphi_max)) return false;
+    const T xn = std::fma(x, ca, s.p[0] * sa);
+    const T yn = std::fma(-x, sa, s.p[0] * ca);
+    const T icn = one / cn;
+    const T j00 = cf * icn;
+    const T j10 = -((sa * s.p[3]) * icn);
+    const T j20 = -((k.kB * s.p[4]) * sa);
+    const T j22 = cn / cf;
+    // C' = J C J^T; J is the identity except rows 0, 1, 2 (y', z', sin phi'),
+    // whose entries are j00 (y), j10 and 1 (y, z), j20 and j22 (y, sin phi).
+    T Cf[5][5];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) Cf[i][j] = s.C[pk(i, j)];
+    T B[5][5];  // J C
+    for (int j = 0; j < 5; ++j) {
+        B[0][j] = j00 * Cf[0][j];
+        B[1][j] = std::fma(j10, Cf[0][j], Cf[1][j]);
+        B[2][j] = std::fma(j20, Cf[0][j], j22 * Cf[2][j]);
+        B[3][j] = Cf[3][j];
+        B[4][j] = Cf[4][j];
+    }
+    for (int i = 0; i < 5; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            T v;
+            if (j == 0) v = B[i][0] * j00;
+            else if (j == 1) v = std::fma(B[i][0], j10, B[i][1]);
+            else if (j == 2) v = std::fma(B[i][0], j20, B[i][2] * j22);
+            else v = B[i][j];
+            s.C[pk(i, j)] = v;
+        }
+    }
+    x = xn;
+    s.p[0] = yn;
+    s.p[2] = sn;
+    return true;
+}
+
 // Predicted chi2 of a measurement (my, mz) with V = diag(vy, vz): r^T S^-1 r,
 // S = C[0:2,0:2] + V, with the explicit 2x2 inverse.
 template <class T>
@@ -308,6 +377,7 @@ struct Input {
 
 template <class T>
 struct Result {
+    using value_type = T;
     int n_rows = 0;
     // grid
     std::vector<int32_t> sorted_id;   // [N] input id at each sorted position
@@ -333,7 +403,17 @@ struct Result {
     std::vector<T> trk_x, trk_alpha, trk_param, trk_cov, trk_chi2;
     std::vector<int64_t> trk_hit_start;
     std::vector<int32_t> trk_hit;
+    std::vector<T> trk_state2;                // [n_t * 20] state after the outward pass
+    std::vector<int32_t> trk_row, trk_row2;   // rows of the output state and of state2
     double chi2_total = 0;
+    // cross-sector merge (filled by merge_tracks)
+    std::vector<int32_t> mrg_next;            // [n_t] outer partner track (-1: none)
+    std::vector<int32_t> mrg_src;             // per merged track: first (head) sector track
+    std::vector<int32_t> mrg_nseg;            // per merged track: segments
+    std::vector<int32_t> mrg_inst, mrg_ndf;
+    std::vector<T> mrg_x, mrg_alpha, mrg_param, mrg_cov, mrg_chi2;
+    std::vector<int64_t> mrg_hit_start;
+    std::vector<int32_t> mrg_hit;
     int64_t ndf_total = 0;
 };
 
@@ -596,7 +676,9 @@ struct RefitOut {
     State<T> s;
     T chi2;
     int nacc;
-    int row;  // row of the output state (innermost hit)
+    int row;     // row of the output state (innermost hit)
+    State<T> s2; // state after the outward pass (at the outermost hit), absolute y and z
+    int row2;
 };
 
 // The refit carries y and z as offsets from a reference point that moves to
@@ -644,6 +726,12 @@ RefitOut<T> refit(const Consts<T>& k, State<T> s, int row, int n, const int32_t*
                     ++nacc;
                 }
             }
+        }
+        if (pass == 1) {  // the outward pass ends at the outermost hit: the state there
+            o.s2 = s;
+            o.s2.p[0] = ref_y + s.p[0];
+            o.s2.p[1] = ref_z + s.p[1];
+            o.row2 = cur;
         }
     }
     s.p[0] = ref_y + s.p[0];
@@ -778,6 +866,10 @@ Result<T>* run(const orc_params& p, const Input& in) {
         R->trk_alpha.push_back((T)(((sec % 18) + 0.5) * 20.0 * 3.14159265358979323846 / 180.0));
         for (int i = 0; i < 5; ++i) R->trk_param.push_back(o.s.p[i]);
         for (int i = 0; i < 15; ++i) R->trk_cov.push_back(o.s.C[i]);
+        for (int i = 0; i < 5; ++i) R->trk_state2.push_back(o.s2.p[i]);
+        for (int i = 0; i < 15; ++i) R->trk_state2.push_back(o.s2.C[i]);
+        R->trk_row.push_back(o.row);
+        R->trk_row2.push_back(o.row2);
         R->trk_chi2.push_back(o.chi2);
         R->trk_ndf.push_back(2 * o.nacc - 5);
         for (int64_t q = R->sel_hit_start[t]; q < R->sel_hit_start[t + 1]; ++q)
@@ -787,6 +879,321 @@ Result<T>* run(const orc_params& p, const Input& in) {
         R->ndf_total += 2 * o.nacc - 5;
     }
     return R;
+}
+
+// ---------------------------------------------------------------- 8. merge
+// The second phase of Section 2: the track segments found in the individual
+// sectors are merged, then fitted as one track (Section 4: the refit follows
+// the helix through rotations between sector frames). Reading of this
+// project (the paper gives no procedure): a segment A continues as segment B
+// of the same event in a phi-neighbouring sector of the same side when A's
+// state after the outward pass, rotated into B's frame and carried to B's
+// reference row (from the first row plane outward of the rotated point, row by
+// row, at most merge_max_gap rows), agrees with B's fitted state: chi2 of the
+// five parameter differences with the summed covariance <= chi2_merge. Pairs
+// are kept when each is the other's best (smallest chi2, ties to the smaller
+// track index); chains of pairs form merged tracks (a closed loop is opened
+// at its smallest track index). A merged track is refitted over all its
+// segments' clusters: the same three passes as the sector refit, from the last
+// segment's outward state, and between segments the state is rotated into the
+// next segment's frame (reference point restarted at the rotated position) and
+// carried to the first row plane towards the target before the row steps.
+
+// chi2 of d = b - a with covariance Ca + Cb (LDL^T, fixed order); false if
+// the summed covariance is not positive definite.
+template <class T>
+bool pair_chi2(const State<T>& a, const State<T>& b, T& chi2) {
+    T C[5][5], L[5][5], D[5], d[5], zz[5];
+    for (int i = 0; i < 5; ++i) {
+        d[i] = b.p[i] - a.p[i];
+        for (int j = 0; j <= i; ++j) C[i][j] = a.C[pk(i, j)] + b.C[pk(i, j)];
+    }
+    for (int j = 0; j < 5; ++j) {
+        T v = C[j][j];
+        for (int q = 0; q < j; ++q) v = v - (L[j][q] * L[j][q]) * D[q];
+        if (!(v > (T)0)) return false;
+        D[j] = v;
+        for (int i = j + 1; i < 5; ++i) {
+            T w = C[i][j];
+            for (int q = 0; q < j; ++q) w = w - (L[i][q] * L[j][q]) * D[q];
+            L[i][j] = w / v;
+        }
+    }
+    T c = (T)0;
+    for (int i = 0; i < 5; ++i) {
+        T v = d[i];
+        for (int q = 0; q < i; ++q) v = v - L[i][q] * zz[q];
+        zz[i] = v;
+        c = c + (v * v) / D[i];
+    }
+    chi2 = c;
+    return true;
+}
+
+// rotation direction from sector sa to sector sb (phi-neighbours of one side):
+// +1 if sb is the next sector counter-clockwise, -1 the previous, 0 otherwise
+inline int sector_step(int sa, int sb) {
+    if (sa / 18 != sb / 18) return 0;
+    const int a = sa % 18, b = sb % 18;
+    if (b == (a + 1) % 18) return 1;
+    if (a == (b + 1) % 18) return -1;
+    return 0;
+}
+
+// first row plane at or beyond x (dir > 0) or at or before x (dir < 0); -1 if none
+template <class T>
+int plane_towards(const Consts<T>& k, T x, int dir) {
+    if (dir > 0) {
+        for (int r = 0; r < k.n_rows; ++r)
+            if (k.X[r] >= x) return r;
+    } else {
+        for (int r = k.n_rows - 1; r >= 0; --r)
+            if (k.X[r] <= x) return r;
+    }
+    return -1;
+}
+
+// chi2 of segment A continuing as segment B (rotation step dir), or false
+template <class T>
+bool match_pair(const Consts<T>& k, const Result<T>& R, int64_t a, int64_t b, int dir, T& chi2) {
+    State<T> s;
+    for (int i = 0; i < 5; ++i) s.p[i] = R.trk_state2[a * 20 + i];
+    for (int i = 0; i < 15; ++i) s.C[i] = R.trk_state2[a * 20 + 5 + i];
+    T x = k.X[R.trk_row2[a]];
+    if (!rotate(s, x, k.rot_c, dir > 0 ? k.rot_s : -k.rot_s, k)) return false;
+    const int r1 = plane_towards(k, x, +1);
+    const int rb = R.trk_row[b];
+    if (r1 < 0 || rb < r1 || rb > r1 + k.merge_max_gap) return false;
+    if (!propagate(s, x, k.X[r1], k)) return false;
+    for (int r = r1; r < rb; ++r)
+        if (!propagate(s, k.X[r], k.X[r + 1], k)) return false;
+    State<T> sb;
+    for (int i = 0; i < 5; ++i) sb.p[i] = R.trk_param[b * 5 + i];
+    for (int i = 0; i < 15; ++i) sb.C[i] = R.trk_cov[b * 15 + i];
+    return pair_chi2(s, sb, chi2);
+}
+
+template <class T>
+struct MergedHit {
+    int row, frame;
+    T y, z;
+    int32_t id;
+};
+
+// Three-pass refit of a merged track (hits in order along the track, frames
+// 0..nf-1 with dirs[f] the rotation step from frame f to f+1), from state s
+// (absolute y, z) at row `row` of the last frame. Outputs the state at the
+// innermost hit (frame 0), chi2 and the pass-3 accepted hits.
+template <class T>
+bool refit_merged(const Consts<T>& k, State<T> s, int row, const std::vector<MergedHit<T>>& hits,
+                  const std::vector<int>& dirs, State<T>& out, T& chi2_out, int& nacc_out, int& row_out,
+                  std::vector<uint8_t>& acc3) {
+    const int n = (int)hits.size();
+    int frame = hits.empty() ? 0 : hits[n - 1].frame;
+    T ref_y = s.p[0], ref_z = s.p[1];
+    s.p[0] = (T)0;
+    s.p[1] = (T)0;
+    int cur = row;
+    auto move_to = [&](int target, int tframe) {
+        if (tframe != frame) {
+            // absolute position, into the neighbouring frame, reference restarted there
+            s.p[0] = ref_y + s.p[0];
+            s.p[1] = ref_z + s.p[1];
+            T x = k.X[cur];
+            const int dir = tframe > frame ? dirs[frame] : -dirs[tframe];
+            if (!rotate(s, x, k.rot_c, dir > 0 ? k.rot_s : -k.rot_s, k)) return false;
+            frame = tframe;
+            ref_y = s.p[0];
+            ref_z = s.p[1];
+            s.p[0] = (T)0;
+            s.p[1] = (T)0;
+            const int r1 = plane_towards(k, x, k.X[target] >= x ? +1 : -1);
+            if (r1 < 0 || !propagate(s, x, k.X[r1], k)) return false;
+            cur = r1;
+        }
+        while (cur != target) {
+            const int nx = cur < target ? cur + 1 : cur - 1;
+            if (!propagate(s, k.X[cur], k.X[nx], k)) return false;
+            cur = nx;
+        }
+        return true;
+    };
+    if (n <= 0 || !move_to(hits[n - 1].row, hits[n - 1].frame)) return false;
+    acc3.assign(n, 0);
+    T chi2sum = (T)0;
+    int nacc = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+        reset_cov(s, k);
+        const bool inward = (pass != 1);
+        for (int q = 0; q < n; ++q) {
+            const int i = inward ? n - 1 - q : q;
+            if (!move_to(hits[i].row, hits[i].frame)) return false;
+            const Innov<T> in = innovation(s, hits[i].y - ref_y, hits[i].z - ref_z, k);
+            if (in.chi2 <= k.chi2_rej) {
+                update(s, in);
+                s.p[0] = s.p[0] + (ref_y - hits[i].y);
+                s.p[1] = s.p[1] + (ref_z - hits[i].z);
+                ref_y = hits[i].y;
+                ref_z = hits[i].z;
+                if (pass == 2) {
+                    chi2sum = chi2sum + in.chi2;
+                    ++nacc;
+                    acc3[i] = 1;
+                }
+            }
+        }
+    }
+    s.p[0] = ref_y + s.p[0];
+    s.p[1] = ref_z + s.p[1];
+    out = s;
+    chi2_out = chi2sum;
+    nacc_out = nacc;
+    row_out = cur;
+    return frame == 0 && nacc >= k.n_min;
+}
+
+template <class T>
+void merge_tracks(const Consts<T>& k, const Input& in, const int32_t* inst_event, Result<T>& R) {
+    const int64_t nt = (int64_t)R.trk_inst.size();
+    const int nr = k.n_rows;
+    // instance of each (event, sector): the lowest instance index
+    std::vector<std::pair<int64_t, int>> key(in.n_inst);
+    for (int i = 0; i < in.n_inst; ++i) key[i] = {(int64_t)inst_event[i] * 64 + in.inst_sector[i], i};
+    auto inst_of = [&](int64_t ev, int sec) -> int {
+        int best = -1;
+        for (int i = 0; i < in.n_inst; ++i)
+            if (key[i].first == ev * 64 + sec && (best < 0 || i < best)) best = i;
+        return best;
+    };
+    // tracks of each instance: [first, last) in output order
+    std::vector<int64_t> tfirst(in.n_inst + 1, nt);
+    for (int64_t t = nt - 1; t >= 0; --t) tfirst[R.trk_inst[t]] = t;
+    std::vector<int64_t> tend(in.n_inst, 0);
+    for (int64_t t = 0; t < nt; ++t) tend[R.trk_inst[t]] = t + 1;
+    auto candidates = [&](int64_t t, int side_dir, auto fn) {
+        // side_dir +1: tracks that may continue t outward (t is A); -1: tracks t may continue (t is B)
+        const int inst = R.trk_inst[t];
+        const int sec = in.inst_sector[inst], side = sec / 18, phi = sec % 18;
+        for (int dir = -1; dir <= 1; dir += 2) {
+            const int nsec = side * 18 + (phi + dir + 18) % 18;
+            const int j = inst_of(inst_event[inst], nsec);
+            if (j < 0 || j == inst || tend[j] <= tfirst[j]) continue;
+            for (int64_t u = tfirst[j]; u < tend[j]; ++u) {
+                if (R.trk_inst[u] != j) continue;
+                fn(u, side_dir > 0 ? dir : -dir);
+            }
+        }
+    };
+    std::vector<int64_t> best_out(nt, -1), best_in(nt, -1);
+    for (int64_t a = 0; a < nt; ++a) {
+        T bc = (T)0;
+        candidates(a, +1, [&](int64_t b, int dir) {
+            T c;
+            if (!match_pair(k, R, a, b, dir, c) || !(c <= k.chi2_merge)) return;
+            if (best_out[a] < 0 || c < bc || (c == bc && b < best_out[a])) {
+                best_out[a] = b;
+                bc = c;
+            }
+        });
+    }
+    for (int64_t b = 0; b < nt; ++b) {
+        T bc = (T)0;
+        candidates(b, -1, [&](int64_t a, int dir) {
+            T c;
+            // a continues as b: a's frame turns by -dir' where dir' is b -> a
+            if (!match_pair(k, R, a, b, dir, c) || !(c <= k.chi2_merge)) return;
+            if (best_in[b] < 0 || c < bc || (c == bc && a < best_in[b])) {
+                best_in[b] = a;
+                bc = c;
+            }
+        });
+    }
+    R.mrg_next.assign(nt, -1);
+    std::vector<int64_t> prev(nt, -1);
+    for (int64_t a = 0; a < nt; ++a) {
+        const int64_t b = best_out[a];
+        if (b >= 0 && best_in[b] == a) {
+            R.mrg_next[a] = (int32_t)b;
+            prev[b] = a;
+        }
+    }
+    // a closed loop is opened at its smallest track index
+    for (int64_t t = 0; t < nt; ++t) {
+        if (prev[t] < 0) continue;
+        int64_t u = prev[t], m = t;
+        int steps = 0;
+        while (u >= 0 && u != t && steps++ < 64) {
+            m = std::min(m, u);
+            u = prev[u];
+        }
+        if (u == t) {
+            R.mrg_next[prev[m]] = -1;
+            prev[m] = -1;
+        }
+    }
+    // merged tracks in the order of their first segment
+    R.mrg_hit_start.assign(1, 0);
+    auto emit = [&](int32_t src, int nseg, int inst, T x, T alpha, const State<T>& s, T chi2, int ndf,
+                    const std::vector<int32_t>& hits) {
+        R.mrg_src.push_back(src);
+        R.mrg_nseg.push_back(nseg);
+        R.mrg_inst.push_back(inst);
+        R.mrg_x.push_back(x);
+        R.mrg_alpha.push_back(alpha);
+        for (int i = 0; i < 5; ++i) R.mrg_param.push_back(s.p[i]);
+        for (int i = 0; i < 15; ++i) R.mrg_cov.push_back(s.C[i]);
+        R.mrg_chi2.push_back(chi2);
+        R.mrg_ndf.push_back(ndf);
+        R.mrg_hit.insert(R.mrg_hit.end(), hits.begin(), hits.end());
+        R.mrg_hit_start.push_back((int64_t)R.mrg_hit.size());
+    };
+    auto emit_single = [&](int64_t t) {
+        State<T> s;
+        for (int i = 0; i < 5; ++i) s.p[i] = R.trk_param[t * 5 + i];
+        for (int i = 0; i < 15; ++i) s.C[i] = R.trk_cov[t * 15 + i];
+        std::vector<int32_t> h(R.trk_hit.begin() + R.trk_hit_start[t], R.trk_hit.begin() + R.trk_hit_start[t + 1]);
+        emit((int32_t)t, 1, R.trk_inst[t], R.trk_x[t], R.trk_alpha[t], s, R.trk_chi2[t], R.trk_ndf[t], h);
+    };
+    for (int64_t t = 0; t < nt; ++t) {
+        if (prev[t] >= 0) continue;  // not a first segment
+        if (R.mrg_next[t] < 0) {
+            emit_single(t);
+            continue;
+        }
+        std::vector<int64_t> chain;
+        for (int64_t u = t; u >= 0 && (int)chain.size() < 64; u = R.mrg_next[u]) chain.push_back(u);
+        std::vector<MergedHit<T>> hits;
+        std::vector<int> dirs;
+        for (size_t f = 0; f < chain.size(); ++f) {
+            const int64_t u = chain[f];
+            const int inst = R.trk_inst[u];
+            const int64_t seg0 = (int64_t)inst * nr;
+            for (int64_t q = R.trk_hit_start[u]; q < R.trk_hit_start[u + 1]; ++q) {
+                const int32_t h = R.trk_hit[q];
+                const int row = (int)(std::upper_bound(in.row_start + seg0, in.row_start + seg0 + nr + 1,
+                                                       (int64_t)h) - (in.row_start + seg0)) - 1;
+                hits.push_back({row, (int)f, (T)in.y[h], (T)in.z[h], h});
+            }
+            if (f + 1 < chain.size())
+                dirs.push_back(sector_step(in.inst_sector[inst], in.inst_sector[R.trk_inst[chain[f + 1]]]));
+        }
+        const int64_t tail = chain.back();
+        State<T> s;
+        for (int i = 0; i < 5; ++i) s.p[i] = R.trk_state2[tail * 20 + i];
+        for (int i = 0; i < 15; ++i) s.C[i] = R.trk_state2[tail * 20 + 5 + i];
+        State<T> out;
+        T chi2;
+        int nacc, row;
+        std::vector<uint8_t> acc3;
+        if (refit_merged(k, s, R.trk_row2[tail], hits, dirs, out, chi2, nacc, row, acc3)) {
+            std::vector<int32_t> h;
+            for (size_t i = 0; i < hits.size(); ++i)
+                if (acc3[i]) h.push_back(hits[i].id);
+            emit((int32_t)t, (int)chain.size(), R.trk_inst[t], k.X[row], R.trk_alpha[t], out, chi2, 2 * nacc - 5, h);
+        } else {
+            for (int64_t u : chain) emit_single(u);
+        }
+    }
 }
 
 struct Handle {
@@ -897,6 +1304,42 @@ void orc_get_tracks(void* h, int32_t* inst, int32_t* sel, double* x, double* alp
     if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
 }
 
+// Cross-sector merge of the tracks of a finished run (same inputs as orc_run;
+// inst_event: the event of each instance). Returns the number of merged tracks.
+int64_t orc_merge(void* h, const orc_params* p, int32_t n_inst, const int32_t* inst_sector, const int32_t* inst_event,
+                  const int64_t* row_start, const float* y, const float* z) {
+    Input in{n_inst, inst_sector, row_start, y, z};
+    auto f = [&](auto* R) -> int64_t {
+        using T = typename std::remove_pointer<decltype(R)>::type::value_type;
+        Consts<T> k(*p);
+        R->mrg_src.clear(); R->mrg_nseg.clear(); R->mrg_inst.clear(); R->mrg_ndf.clear(); R->mrg_x.clear();
+        R->mrg_alpha.clear(); R->mrg_param.clear(); R->mrg_cov.clear(); R->mrg_chi2.clear();
+        R->mrg_hit.clear(); R->mrg_hit_start.clear();
+        merge_tracks(k, in, inst_event, *R);
+        return (int64_t)R->mrg_src.size();
+    };
+    return ((Handle*)h)->prec == 32 ? f(res<float>(h)) : f(res<double>(h));
+}
+
+// n_hits of the merged tracks
+int64_t orc_merged_hits(void* h) {
+    auto f = [&](auto* R) -> int64_t { return (int64_t)R->mrg_hit.size(); };
+    return ((Handle*)h)->prec == 32 ? f(res<float>(h)) : f(res<double>(h));
+}
+
+void orc_get_merged(void* h, int32_t* next, int32_t* src, int32_t* nseg, int32_t* inst, double* x, double* alpha,
+                    double* param, double* cov, double* chi2, int32_t* ndf, int64_t* hit_start, int32_t* hit,
+                    double* state2) {
+    auto f = [&](auto* R) {
+        copy_out(R->mrg_next, next); copy_out(R->mrg_src, src); copy_out(R->mrg_nseg, nseg);
+        copy_out(R->mrg_inst, inst); copy_out(R->mrg_x, x); copy_out(R->mrg_alpha, alpha);
+        copy_out(R->mrg_param, param); copy_out(R->mrg_cov, cov); copy_out(R->mrg_chi2, chi2);
+        copy_out(R->mrg_ndf, ndf); copy_out(R->mrg_hit_start, hit_start); copy_out(R->mrg_hit, hit);
+        copy_out(R->trk_state2, state2);
+    };
+    if (((Handle*)h)->prec == 32) f(res<float>(h)); else f(res<double>(h));
+}
+
 // ---- primitives (for pinning the oracle against closed forms) -----------
 int32_t orc_propagate(const orc_params* p, int32_t precision, double* st, double x1, double x2) {
     auto f = [&](auto zero) -> int32_t {
@@ -906,6 +1349,22 @@ int32_t orc_propagate(const orc_params* p, int32_t precision, double* st, double
         load_state(st, s);
         if (!propagate(s, (T)x1, (T)x2, k)) return 0;
         store_state(s, st);
+        return 1;
+    };
+    return precision == 32 ? f(0.0f) : f(0.0);
+}
+
+// Rotate a state (20 values) at local x by the frame angle d; x is updated.
+int32_t orc_rotate(const orc_params* p, int32_t precision, double* st, double* x, double d) {
+    auto f = [&](auto zero) -> int32_t {
+        using T = decltype(zero);
+        Consts<T> k(*p);
+        State<T> s;
+        load_state(st, s);
+        T xx = (T)*x;
+        if (!rotate(s, xx, (T)std::cos(d), (T)std::sin(d), k)) return 0;
+        store_state(s, st);
+        *x = (double)xx;
         return 1;
     };
     return precision == 32 ? f(0.0f) : f(0.0);
