@@ -900,14 +900,17 @@ Result<T>* run(const orc_params& p, const Input& in) {
 // carried to the first row plane towards the target before the row steps.
 
 // chi2 of d = b - a with covariance Ca + Cb (LDL^T, fixed order); false if
-// the summed covariance is not positive definite.
+// the summed covariance is not positive definite or if the z or tan(lambda)
+// difference alone already exceeds `cut` (a quadratic form is at least any of
+// its one-parameter marginals, so such a pair is rejected before the solve).
 template <class T>
-bool pair_chi2(const State<T>& a, const State<T>& b, T& chi2) {
+bool pair_chi2(const State<T>& a, const State<T>& b, T cut, T& chi2) {
     T C[5][5], L[5][5], D[5], d[5], zz[5];
     for (int i = 0; i < 5; ++i) {
         d[i] = b.p[i] - a.p[i];
         for (int j = 0; j <= i; ++j) C[i][j] = a.C[pk(i, j)] + b.C[pk(i, j)];
     }
+    if (!(d[1] * d[1] <= cut * C[1][1]) || !(d[3] * d[3] <= cut * C[3][3])) return false;
     for (int j = 0; j < 5; ++j) {
         T v = C[j][j];
         for (int q = 0; q < j; ++q) v = v - (L[j][q] * L[j][q]) * D[q];
@@ -970,7 +973,7 @@ bool match_pair(const Consts<T>& k, const Result<T>& R, int64_t a, int64_t b, in
     State<T> sb;
     for (int i = 0; i < 5; ++i) sb.p[i] = R.trk_param[b * 5 + i];
     for (int i = 0; i < 15; ++i) sb.C[i] = R.trk_cov[b * 15 + i];
-    return pair_chi2(s, sb, chi2);
+    return pair_chi2(s, sb, k.chi2_merge, chi2);
 }
 
 template <class T>
@@ -1154,12 +1157,21 @@ void merge_tracks(const Consts<T>& k, const Input& in, const int32_t* inst_event
         std::vector<int32_t> h(R.trk_hit.begin() + R.trk_hit_start[t], R.trk_hit.begin() + R.trk_hit_start[t + 1]);
         emit((int32_t)t, 1, R.trk_inst[t], R.trk_x[t], R.trk_alpha[t], s, R.trk_chi2[t], R.trk_ndf[t], h);
     };
+    // refit every chain first; a chain whose refit fails leaves its segments
+    // as sector tracks. Output in track order: a merged track at its first
+    // segment, the other segments of a merged chain omitted.
+    struct Merged {
+        bool ok = false;
+        int nseg = 0;
+        State<T> s;
+        T chi2;
+        int ndf, row;
+        std::vector<int32_t> hits;
+    };
+    std::vector<Merged> mg(nt);
+    std::vector<uint8_t> absorbed(nt, 0);
     for (int64_t t = 0; t < nt; ++t) {
-        if (prev[t] >= 0) continue;  // not a first segment
-        if (R.mrg_next[t] < 0) {
-            emit_single(t);
-            continue;
-        }
+        if (prev[t] >= 0 || R.mrg_next[t] < 0) continue;  // not the first segment of a chain
         std::vector<int64_t> chain;
         for (int64_t u = t; u >= 0 && (int)chain.size() < 64; u = R.mrg_next[u]) chain.push_back(u);
         std::vector<MergedHit<T>> hits;
@@ -1186,12 +1198,25 @@ void merge_tracks(const Consts<T>& k, const Input& in, const int32_t* inst_event
         int nacc, row;
         std::vector<uint8_t> acc3;
         if (refit_merged(k, s, R.trk_row2[tail], hits, dirs, out, chi2, nacc, row, acc3)) {
-            std::vector<int32_t> h;
+            Merged& M = mg[t];
+            M.ok = true;
+            M.nseg = (int)chain.size();
+            M.s = out;
+            M.chi2 = chi2;
+            M.ndf = 2 * nacc - 5;
+            M.row = row;
             for (size_t i = 0; i < hits.size(); ++i)
-                if (acc3[i]) h.push_back(hits[i].id);
-            emit((int32_t)t, (int)chain.size(), R.trk_inst[t], k.X[row], R.trk_alpha[t], out, chi2, 2 * nacc - 5, h);
+                if (acc3[i]) M.hits.push_back(hits[i].id);
+            for (size_t f = 1; f < chain.size(); ++f) absorbed[chain[f]] = 1;
+        }
+    }
+    for (int64_t t = 0; t < nt; ++t) {
+        if (absorbed[t]) continue;
+        if (mg[t].ok) {
+            const Merged& M = mg[t];
+            emit((int32_t)t, M.nseg, R.trk_inst[t], k.X[M.row], R.trk_alpha[t], M.s, M.chi2, M.ndf, M.hits);
         } else {
-            for (int64_t u : chain) emit_single(u);
+            emit_single(t);
         }
     }
 }
