@@ -76,10 +76,13 @@ typedef struct {
     int32_t n_min;                /* min clusters of a tracklet and of a track, 10 */
     int32_t max_miss;             /* consecutive empty rows ending the following, 8 */
     uint32_t flags;               /* TPCCA_FLAG_* */
+    double chi2_merge;            /* cross-sector merge: max chi2 (five parameters) of a segment pair, 25 */
+    int32_t merge_max_gap;        /* cross-sector merge: max rows between a segment's end and the next, 24 */
 } tpcca_params;
 
 #define TPCCA_FLAG_STATS 1u       /* count work items (rows visited, candidates) for the byte model */
 #define TPCCA_FLAG_TIMING 2u      /* batched form runs uncaptured with HIP events between stages */
+#define TPCCA_FLAG_MERGE 8u       /* track calls keep what tpcca_merge needs (outward-pass states, rows) */
 
 /* Launch/tiling choices. They never change results (tested bit-exact). */
 typedef struct {
@@ -88,11 +91,22 @@ typedef struct {
     int32_t block_tracklet;   /* threads per block of the tracklet kernel (64..256), default 256 */
     int32_t block_refit;      /* threads per block of the refit kernel (64..256), default 128 */
     int32_t block_scan;       /* threads per block of scans/compactions, default 256 */
-    int32_t sort_seeds;       /* 1: process seeds in an order grouped by chain length (default 0) */
+    int32_t sort_seeds;       /* 1: each refit workgroup hands its chunk of consecutive tracks to its lanes
+                                 longest first (default 0: measured no faster, the refit waits on memory
+                                 more than on its longest lane) */
     int32_t tape_mb;          /* device memory for the differentiable refit's tape [MiB], default 32768;
                                  a larger set is recomputed batch by batch in tpcca_refit_bwd */
     int32_t xcd_remap;        /* 1: workgroups renumbered so that each of the 8 XCDs (own L2) works on
                                  contiguous instances (neighbour and tracklet kernels), default 1 */
+    int32_t ckpt;             /* differentiable refit: 0 = the forward records every operation on a tape
+                                 (default); 1 = the forward keeps a checkpoint at the start of each of
+                                 the three passes and the backward recomputes one pass at a time from
+                                 it, last pass first (a third of the tape; same gradients bit for bit) */
+    int32_t inward_wgs;       /* 0 (default): each tracklet's inward pass (Section 3) runs in the lane that
+                                 followed it outward; > 0: the outward kernel stops at the turn and a
+                                 persistent kernel of this many workgroups (block_tracklet threads, at
+                                 most 65536) runs the inward passes, each lane taking the next tracklet
+                                 as soon as its last one ends */
 } tpcca_tuning;
 
 /* Input clusters (device pointers, caller-owned). */
@@ -121,6 +135,15 @@ typedef struct {
     int64_t* hit_start;   /* [cap_tracks + 1] CSR into hit_id */
     int32_t* hit_id;      /* [cap_hits] cluster ids */
     double* chi2_total;   /* [2] FP64: sum of chi2, sum of ndf (deterministic order) */
+    float* z0;            /* [cap_tracks] or NULL: z of the track's closest approach to the beam line
+                             (Section 4: the primary-vertex z, i.e. the collision time, of a track in
+                             continuous readout), from the final fit's state, evaluated in FP64 */
+    int16_t* residuals;   /* [cap_hits * 2] or NULL: track-model compression residuals (Section 5.1),
+                             (y, z) per output cluster, parallel to hit_id: round((cluster - prediction)
+                             / 2^residual_step_log2) where the prediction carries the track's output
+                             parameters outward from x_ref row by row with the tracker's binary32 helix
+                             step; -32768 marks a value outside int16 or after a failed step */
+    int32_t residual_step_log2; /* host: quantisation step 2^k cm, k in [-20, 4] (e.g. -7) */
     int64_t n_tracks;     /* host, written on return: tracks found (even if above capacity) */
     int64_t n_hits;       /* host, written on return */
 } tpcca_tracks;
@@ -179,6 +202,36 @@ tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca
  * synchronising forms. Output buffers identical to tpcca_track_batched. */
 tpcca_status tpcca_track_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
                                int32_t* status, void* hip_stream);
+
+/* Cross-sector merge (the second phase of Section 2: the track segments found
+ * in the individual sectors are merged and fitted as one track; Section 4: the
+ * fit follows the helix through rotations between sector frames) of the
+ * output tracks of the last synchronous track call on ctx, which must have
+ * been created with TPCCA_FLAG_MERGE (the track calls then keep the
+ * outward-pass states and cluster rows the merge needs); that call's inputs
+ * and outputs must still be valid.
+ *   inst_event: device [n_inst] event (or time-frame) id of each instance:
+ *     only segments of one event in phi-neighbouring sectors of one side are
+ *     merged; an instance that is not the lowest of its (event, sector) is
+ *     left as it is.
+ * A segment continues as another when its state after the outward pass,
+ * rotated into the other's frame and carried row by row (at most
+ * params.merge_max_gap rows) to the other's reference row, agrees with the
+ * other's fitted state within chi2 <= params.chi2_merge (five parameters);
+ * mutual best pairs form chains of at most 8 segments, and each chain is
+ * refitted over all its clusters with the three passes of the final fit,
+ * rotating between frames. Output `merged` (tracks struct; z0, residuals
+ * and chi2_total are not written): in sector-track order, a merged track at
+ * its first segment (params in that segment's frame), other segments kept as
+ * they are; a chain whose refit fails keeps its segments. nseg (device
+ * [cap_tracks] or NULL): segments per output track. seg_next (device
+ * [sector tracks] or NULL): the sector track each one was paired with as its
+ * continuation (-1: none; also set for a chain whose refit failed).
+ * Synchronises the stream once (the counts).
+ * Errors: TPCCA_E_ARG (no usable previous call, flag missing, null
+ * pointers), TPCCA_E_CAPACITY (merged->n_tracks / n_hits hold the sizes). */
+tpcca_status tpcca_merge(tpcca_ctx* ctx, const int32_t* inst_event, tpcca_tracks* merged, int32_t* nseg,
+                         int32_t* seg_next, void* hip_stream);
 
 /* Allocation-free form of tpcca_track_async, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, harnesses
@@ -300,8 +353,10 @@ tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* clusters, con
  * L = sum_t grad_chi2[t] * chi2_track[t]. grad_chi2: device [n_tracks]
  * binary32. Outputs (FP64, device): grad_params0 [n_tracks * 5] = dL/dparams0;
  * grad_map [TPCCA_MAP_SIZE] = dL/dcoef (may be NULL; evaluated at the
- * forward's map, zero map if it was NULL; accumulated with FP64 atomics, so the
- * last bits depend on the order of accumulation); grad_hit_yz [n_hits * 2] =
+ * forward's map, zero map if it was NULL; deterministic: every contribution is
+ * rounded once to a 64-bit fixed-point integer scaled so that no partial sum can
+ * exceed 2^61, the sums are exact integer additions in any order, and the result
+ * is converted back to FP64); grad_hit_yz [n_hits * 2] =
  * dL/d(y', z') of each corrected cluster (may be NULL). Tracks whose refit
  * failed get zero gradients. Asynchronous; may be called again (another
  * grad_chi2) while the recorded forward stays valid. */

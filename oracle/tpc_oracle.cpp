@@ -976,6 +976,8 @@ bool match_pair(const Consts<T>& k, const Result<T>& R, int64_t a, int64_t b, in
     return pair_chi2(s, sb, k.chi2_merge, chi2);
 }
 
+constexpr int kMaxChain = 8;  // segments of one merged track; a longer chain is cut after the eighth
+
 template <class T>
 struct MergedHit {
     int row, frame;
@@ -1076,6 +1078,8 @@ void merge_tracks(const Consts<T>& k, const Input& in, const int32_t* inst_event
     auto candidates = [&](int64_t t, int side_dir, auto fn) {
         // side_dir +1: tracks that may continue t outward (t is A); -1: tracks t may continue (t is B)
         const int inst = R.trk_inst[t];
+        // an instance that is not the lowest of its (event, sector) takes no part
+        if (inst_of(inst_event[inst], in.inst_sector[inst]) != inst) return;
         const int sec = in.inst_sector[inst], side = sec / 18, phi = sec % 18;
         for (int dir = -1; dir <= 1; dir += 2) {
             const int nsec = side * 18 + (phi + dir + 18) % 18;
@@ -1173,7 +1177,7 @@ void merge_tracks(const Consts<T>& k, const Input& in, const int32_t* inst_event
     for (int64_t t = 0; t < nt; ++t) {
         if (prev[t] >= 0 || R.mrg_next[t] < 0) continue;  // not the first segment of a chain
         std::vector<int64_t> chain;
-        for (int64_t u = t; u >= 0 && (int)chain.size() < 64; u = R.mrg_next[u]) chain.push_back(u);
+        for (int64_t u = t; u >= 0 && (int)chain.size() < kMaxChain; u = R.mrg_next[u]) chain.push_back(u);
         std::vector<MergedHit<T>> hits;
         std::vector<int> dirs;
         for (size_t f = 0; f < chain.size(); ++f) {

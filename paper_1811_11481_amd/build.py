@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpcca.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "merge.hip", "api.hip"]
 ARCH = os.environ.get("TPCCA_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

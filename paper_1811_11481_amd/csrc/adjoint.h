@@ -21,8 +21,12 @@ enum : uint32_t {
 // words of the small status block (device): error bits, max operation count
 struct AdjStatus {
     uint32_t err;
-    int32_t max_ops;
+    int32_t max_ops;      // operations of the whole refit, largest over the set
+    int32_t max_seg_ops;  // operations of one pass segment (the walk belongs to the first), largest
+    int32_t pad;
 };
+
+constexpr int kCkptWords = 24;  // per pass start: state (5 + 15), reference point (2), row, pad
 
 struct AdjBufs {
     const DevConsts* K;
@@ -50,7 +54,10 @@ struct AdjBufs {
     double2* hit_grad;    // [3][n_hits] d/d(y', z') per pass
     int32_t* nops;        // [n_tracks] operations of the last recorded forward (-1: failed)
     uint32_t* tape;       // operation k of batch track b at word (b * tape_ops + k) * kTapeWords
-    int32_t tape_ops;     // operations per track the tape holds (the set's maximum)
+    int32_t tape_ops;     // operations per track the tape holds (the set's maximum, or a segment's)
+    float* ckpt;          // [3][n_tracks][kCkptWords] pass-start checkpoints, or null (full tape)
+    int32_t* seg_nops;    // [n_tracks] operations of the last recomputed segment
+    double* carry;        // [n_tracks][20] adjoint of (state, covariance) between segments
     AdjStatus* status;
     // outputs
     float* chi2_track;
@@ -68,11 +75,17 @@ struct AdjBufs {
 // the tape).
 void enqueue_refit_prepare(const AdjBufs& a, hipStream_t st);
 // Forward over tracks [t0, t1): chi2 per track (when `outputs`), operation
-// counts, and the tape of those tracks when a.tape is set.
+// counts, and the tape of those tracks when a.tape is set. With a.ckpt set the
+// full forward stores each pass's starting point there.
 void enqueue_refit_forward(const AdjBufs& a, int64_t t0, int64_t t1, bool outputs, hipStream_t st);
+// Recompute pass `seg` (seg 0 includes the walk to the outermost cluster) of
+// tracks [t0, t1) from its checkpoint, recording its operations on the tape.
+void enqueue_refit_segment(const AdjBufs& a, int64_t t0, int64_t t1, int seg, hipStream_t st);
 void enqueue_refit_total(const AdjBufs& a, hipStream_t st);
-// Reverse sweep over the taped tracks [t0, t1).
-void enqueue_refit_reverse(const AdjBufs& a, int64_t t0, int64_t t1, hipStream_t st);
+// Reverse sweep over the taped tracks [t0, t1): the whole refit (seg < 0), or
+// one recomputed pass segment, whose adjoint is carried to the next (earlier)
+// segment in a.carry.
+void enqueue_refit_reverse(const AdjBufs& a, int64_t t0, int64_t t1, int seg, hipStream_t st);
 // Map gradient (grad_map) and per-cluster gradient (sum over passes) from the
 // reverse sweeps; the map gradient uses map_grad_scratch_bytes(n_hits) of scratch.
 size_t map_grad_scratch_bytes(int64_t n_hits);

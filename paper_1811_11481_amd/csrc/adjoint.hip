@@ -433,7 +433,7 @@ __global__ void k_map_correct(AdjBufs a) {
 // span in steps, one update per set mask bit and (passes 2 and 3) a reset.
 __global__ void k_adj_count(AdjBufs a) {
     if (a.status->err) return;
-    int32_t m = 0;
+    int32_t m = 0, mseg = 0;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.n_tracks;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t off = a.hit_start[t];
@@ -454,8 +454,17 @@ __global__ void k_adj_count(AdjBufs a) {
         const int span = rows[n - 1] - rows[0];
         const int d0 = a.row0[t] - rows[n - 1];
         m = max(m, (d0 < 0 ? -d0 : d0) + 3 + 3 * span + used);
+        int u0 = 0, u1 = 0, u2 = 0;
+        for (int i = 0; i < n; ++i) {
+            const uint8_t mk = a.hit_mask[off + i];
+            u0 += mk & 1u;
+            u1 += (mk >> 1) & 1u;
+            u2 += (mk >> 2) & 1u;
+        }
+        mseg = max(mseg, max((d0 < 0 ? -d0 : d0) + 1 + span + u0, 1 + span + max(u1, u2)));
     }
     if (m > 0) atomicMax(&a.status->max_ops, m);
+    if (mseg > 0) atomicMax(&a.status->max_seg_ops, mseg);
 }
 
 // Record operation k of a track: five 16-byte words (covariance before it in
@@ -479,8 +488,18 @@ __device__ __forceinline__ void rec_op(uint4* tp, int k, const float* C, bool co
 // tracks [t0, t1): row steps to the outermost cluster, then three passes
 // (inward, outward, inward) each opening with a covariance reset; the next
 // cluster's row, coordinates and mask are loaded one cluster ahead.
+__device__ __forceinline__ float* ckpt_at(const AdjBufs& a, int pass, int64_t t) {
+    return a.ckpt + ((int64_t)pass * a.n_tracks + t) * kCkptWords;
+}
+
+// Passes [pass_lo, pass_hi) of the refit. pass_lo = 0 starts from the start
+// state and walks to the outermost cluster first; pass_lo > 0 starts from
+// that pass's checkpoint (a segment recompute, which then counts its own
+// operations in seg_nops). With a.ckpt set, the full run (0, 3) stores the
+// state, reference point and row at the start of every pass.
 template <bool kTape>
-__global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_t t1, int outputs) {
+__global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_t t1, int outputs, int pass_lo,
+                                                   int pass_hi) {
     const DevConsts& K = *a.K;
     const KfConsts kc = kf_consts(K);
     __shared__ float sX[kMaxRows];
@@ -495,15 +514,35 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
         const uint8_t* masks = a.hit_mask + off;
         const float2* yz = a.hit_yz + off;
         uint4* tp = kTape ? (uint4*)a.tape + (t - t0) * (int64_t)cap * (kTapeWords / 4) : nullptr;
+        const bool segment = !(pass_lo == 0 && pass_hi == 3);
+        if (segment && a.nops[t] < 0) {  // the recorded forward failed: nothing to recompute
+            a.seg_nops[t] = -1;
+            continue;
+        }
         KState s;
+        float ref_y, ref_z;
+        int cur;
+        if (pass_lo == 0) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) s.p[q] = a.params0[t * 5 + q];
+            for (int q = 0; q < 5; ++q) s.p[q] = a.params0[t * 5 + q];
 #pragma unroll
-        for (int q = 0; q < 15; ++q) s.C[q] = a.cov0[t * 15 + q];
-        float ref_y = s.p[0], ref_z = s.p[1];
-        s.p[0] = 0.0f;
-        s.p[1] = 0.0f;
-        int cur = a.row0[t], k = 0;
+            for (int q = 0; q < 15; ++q) s.C[q] = a.cov0[t * 15 + q];
+            ref_y = s.p[0];
+            ref_z = s.p[1];
+            s.p[0] = 0.0f;
+            s.p[1] = 0.0f;
+            cur = a.row0[t];
+        } else {
+            const float* c = ckpt_at(a, pass_lo, t);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) s.p[q] = c[q];
+#pragma unroll
+            for (int q = 0; q < 15; ++q) s.C[q] = c[5 + q];
+            ref_y = c[20];
+            ref_z = c[21];
+            cur = __float_as_int(c[22]);
+        }
+        int k = 0;
         bool ok = n > 0;
         float chi2 = 0.0f;
         auto step_to = [&](int target) {
@@ -518,8 +557,18 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
                 else cur = nx;
             }
         };
-        if (ok) step_to(rows[n - 1]);
-        for (int pass = 0; pass < 3 && ok; ++pass) {
+        if (ok && pass_lo == 0) step_to(rows[n - 1]);
+        for (int pass = pass_lo; pass < pass_hi && ok; ++pass) {
+            if (a.ckpt && !segment) {
+                float* c = ckpt_at(a, pass, t);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) c[q] = s.p[q];
+#pragma unroll
+                for (int q = 0; q < 15; ++q) c[5 + q] = s.C[q];
+                c[20] = ref_y;
+                c[21] = ref_z;
+                c[22] = __int_as_float(cur);
+            }
             if (kTape) {
                 if (k < cap) rec_op(tp, k, s.C, false, 0.0f, 0.0f, 0.0f, op_word(OP_RESET, pass, 0, 0, 0));
                 else set_err(a.status, AERR_TAPE);
@@ -557,7 +606,8 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
                 if (pass == 2) chi2 = chi2 + inn.chi2;
             }
         }
-        a.nops[t] = ok ? k : -1;
+        if (segment) a.seg_nops[t] = ok ? k : -1;
+        else a.nops[t] = ok ? k : -1;
         if (outputs) {
             a.chi2_track[t] = ok ? chi2 : 0.0f;
             if (a.track_ok) a.track_ok[t] = ok ? 1 : 0;
@@ -573,7 +623,7 @@ __device__ __forceinline__ void load_op(const uint4* tp, int k, uint4 w[kTapeWor
 
 // Reverse sweep over the taped tracks [t0, t1), one lane per track.
 template <class A>
-__global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_t t1) {
+__global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_t t1, int seg) {
     const DevConsts& K = *a.K;
     const KfConsts kc = kf_consts(K);
     __shared__ float sX[kMaxRows];
@@ -583,21 +633,35 @@ __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t off = a.hit_start[t];
         const int n = (int)(a.hit_start[t + 1] - off);
-        for (int p = 0; p < 3; ++p)
-            for (int i = 0; i < n; ++i) a.hit_grad[p * NH + off + i] = make_double2(0.0, 0.0);
-        const int nops = a.nops[t];
+        const bool first = seg < 0 || seg == 2;  // the last operations of the refit come first
+        const bool last = seg <= 0;              // ... and its start last
+        if (first)
+            for (int p = 0; p < 3; ++p)
+                for (int i = 0; i < n; ++i) a.hit_grad[p * NH + off + i] = make_double2(0.0, 0.0);
         double* gp = a.grad_params + t * 5;
-        if (nops <= 0) {
-            for (int q = 0; q < 5; ++q) gp[q] = 0.0;
+        if (a.nops[t] <= 0) {
+            if (last)
+                for (int q = 0; q < 5; ++q) gp[q] = 0.0;
             continue;
         }
+        const int nops = seg < 0 ? a.nops[t] : a.seg_nops[t];
         const uint4* tp = (const uint4*)a.tape + (t - t0) * (int64_t)a.tape_ops * (kTapeWords / 4);
         const A cb = A(a.grad_chi2[t]);
         A pb[5], Cb[15];
+        double* cy = a.carry ? a.carry + t * 20 : nullptr;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) pb[q] = A(0);
+        for (int q = 0; q < 5; ++q) pb[q] = first ? A(0) : A(cy[q]);
 #pragma unroll
-        for (int q = 0; q < 15; ++q) Cb[q] = A(0);
+        for (int q = 0; q < 15; ++q) Cb[q] = first ? A(0) : A(cy[5 + q]);
+        if (nops <= 0) {  // a segment without operations passes its adjoint on
+            if (last) {
+                for (int q = 0; q < 5; ++q) gp[q] = (double)pb[q];
+            } else {
+                for (int q = 0; q < 5; ++q) cy[q] = (double)pb[q];
+                for (int q = 0; q < 15; ++q) cy[5 + q] = (double)Cb[q];
+            }
+            continue;
+        }
         uint4 nxt[kTapeWords / 4];
         load_op(tp, nops - 1, nxt);
         for (int k = nops - 1; k >= 0; --k) {
@@ -627,8 +691,15 @@ __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_
                 a.hit_grad[pass * NH + off + hit] = make_double2((double)mb0, (double)mb1);
             }
         }
+        if (last) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) gp[q] = (double)pb[q];
+            for (int q = 0; q < 5; ++q) gp[q] = (double)pb[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) cy[q] = (double)pb[q];
+#pragma unroll
+            for (int q = 0; q < 15; ++q) cy[5 + q] = (double)Cb[q];
+        }
     }
 }
 
@@ -658,6 +729,21 @@ __global__ void k_hit_grad_out(AdjBufs a, double2* out) {
 //   then go to the global gradient with FP64 atomics.
 // Tracks of one sector touch ~5 of 16 phi and half of the z coefficients: the
 // global atomics drop from 192 per cluster to about one box per workgroup.
+//
+// Deterministic order: every contribution is rounded once to a fixed-point
+// integer (a multiple of 2^-S) and all sums, in LDS and in global memory, are
+// 64-bit integer additions, which are exact and associative, so the result
+// does not depend on the order in which waves and workgroups add. The scale
+// is chosen from an order-independent bound: no partial sum of a coefficient
+// exceeds the sum over slots of |g| (the B-spline weights of a slot are
+// non-negative and add up to one), which is at most n_slots * max|g|; S puts
+// that bound at 2^61. The integers are converted back to FP64 at the end.
+struct MapFixed {
+    unsigned long long max_bits;  // max |g| over slots and components, as the bits of a non-negative double
+    double scale;                 // 2^S
+    double inv_scale;             // 2^-S
+    unsigned long long sum[kMapSize];
+};
 constexpr int kMapScatterHits = 4096;
 constexpr int kMapScatterThreads = 256;
 constexpr int kMapGradLds = 7168;  // doubles (56 KB; with the staging buffer two workgroups fit a CU)
@@ -669,7 +755,8 @@ struct GradRec {  // 80 bytes
     double gc[3];
 };
 
-__global__ void k_grad_cells(AdjBufs a, GradRec* rec) {
+__global__ void k_grad_cells(AdjBufs a, GradRec* rec, MapFixed* fx) {
+    double gmax = 0.0;
     for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < a.n_hits;
          h += (int64_t)gridDim.x * blockDim.x) {
         const double2 g = hit_grad_sum(a, h);
@@ -693,18 +780,41 @@ __global__ void k_grad_cells(AdjBufs a, GradRec* rec) {
             r.gc[0] = -g.x * (double)y / (double)geo.r;
             r.gc[1] = -g.x * (double)geo.x / (double)geo.r;
             r.gc[2] = -g.y;
+            gmax = fmax(gmax, fmax(fabs(r.gc[0]), fmax(fabs(r.gc[1]), fabs(r.gc[2]))));
         }
         r.pad = 0;
         rec[h] = r;
     }
+    // the maximum is order-independent; non-negative doubles order as their bit patterns
+    for (int o = 32; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+    if ((threadIdx.x & 63) == 0 && gmax > 0.0) atomicMax(&fx->max_bits, (unsigned long long)__double_as_longlong(gmax));
+}
+
+__global__ void k_map_scale(MapFixed* fx, int64_t n_slots) {
+    if (threadIdx.x != 0) return;
+    const double bound = __longlong_as_double((long long)fx->max_bits) * (double)(n_slots > 0 ? n_slots : 1);
+    int e = 0;
+    if (bound > 0.0) frexp(bound, &e);  // bound < 2^e
+    const int S = 61 - e;
+    fx->scale = ldexp(1.0, S);
+    fx->inv_scale = ldexp(1.0, -S);
+}
+
+__device__ __forceinline__ unsigned long long to_fixed(double v, double scale) {
+    return (unsigned long long)__double2ll_rn(v * scale);
+}
+
+__global__ void k_map_from_fixed(AdjBufs a, const MapFixed* fx) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kMapSize; i += gridDim.x * blockDim.x)
+        a.grad_map[i] = (double)(long long)fx->sum[i] * fx->inv_scale;
 }
 
 __device__ __forceinline__ int wrap_dphi(int ip, int ref) {
     return ((ip - ref + 2 * kMapNphi + kMapNphi / 2) % kMapNphi) - kMapNphi / 2;  // in [-8, 8)
 }
 
-__global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, const GradRec* rec) {
-    __shared__ double acc[kMapGradLds + 192];  // the box, then one discard slot per lane and component
+__global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, const GradRec* rec, MapFixed* fx) {
+    __shared__ unsigned long long acc[kMapGradLds + 192];  // the box, then one discard slot per lane and component
     __shared__ GradRec stage[kMapScatterThreads / 64][64];
     __shared__ int lo[3], hi[3], ref;
     const int64_t h0 = (int64_t)blockIdx.x * kMapScatterHits;
@@ -751,10 +861,11 @@ __global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, c
     const int cstride = nr * np * nzs;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const int li = lane >> 4, lj = (lane >> 2) & 3, le = lane & 3;
+    const double scale = fx->scale;
     for (int z0 = lz; z0 <= hz; z0 += nzs) {
         const int nz = min(nzs, hz - z0 + 1);
         const int size = 3 * cstride;
-        for (int i = threadIdx.x; i < size; i += blockDim.x) acc[i] = 0.0;
+        for (int i = threadIdx.x; i < size; i += blockDim.x) acc[i] = 0ull;
         __syncthreads();
         // each wave stages 64 records with one coalesced load, then adds
         // them one at a time from LDS; the next record's fields are read
@@ -782,9 +893,9 @@ __global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, c
                 const int pj = full_phi ? (ip - 1 + lj + kMapNphi) % kMapNphi : wrap_dphi(ip, rf) - 1 + lj - lp;
                 const double w = ok ? (double)wr * (double)wp * (double)wz : 0.0;
                 const int base = ((ir + li - lr) * np + pj) * nzs + zz;
-                atomicAdd(&acc[ok ? base : kMapGradLds + lane], g0 * w);
-                atomicAdd(&acc[ok ? cstride + base : kMapGradLds + 64 + lane], g1 * w);
-                atomicAdd(&acc[ok ? 2 * cstride + base : kMapGradLds + 128 + lane], g2 * w);
+                atomicAdd(&acc[ok ? base : kMapGradLds + lane], to_fixed(g0 * w, scale));
+                atomicAdd(&acc[ok ? cstride + base : kMapGradLds + 64 + lane], to_fixed(g1 * w, scale));
+                atomicAdd(&acc[ok ? 2 * cstride + base : kMapGradLds + 128 + lane], to_fixed(g2 * w, scale));
                 cell = cell_n;
                 wr = wr_n;
                 wp = wp_n;
@@ -797,13 +908,13 @@ __global__ __launch_bounds__(kMapScatterThreads) void k_map_scatter(AdjBufs a, c
         }
         __syncthreads();
         for (int i = threadIdx.x; i < size; i += blockDim.x) {
-            const double v = acc[i];
-            if (v == 0.0) continue;
+            const unsigned long long v = acc[i];
+            if (v == 0ull) continue;
             const int zz = i % nzs, rest = i / nzs;
             const int pj = rest % np, rest2 = rest / np;
             const int rr = rest2 % nr, comp = rest2 / nr;
             const int iphi = full_phi ? pj : rf + lp + pj;  // map_index wraps it
-            unsafeAtomicAdd(a.grad_map + map_index(comp, lr + rr, iphi, z0 + zz), v);
+            atomicAdd(fx->sum + map_index(comp, lr + rr, iphi, z0 + zz), v);
         }
         __syncthreads();
     }
@@ -833,6 +944,7 @@ __global__ void k_clear_status(AdjStatus* st) {
     if (threadIdx.x == 0) {
         st->err = 0u;
         st->max_ops = 0;
+        st->max_seg_ops = 0;
     }
 }
 
@@ -858,34 +970,49 @@ void enqueue_refit_forward(const AdjBufs& a, int64_t t0, int64_t t1, bool output
     if (t1 <= t0) return;
     const dim3 g(blocks_for(t1 - t0, 128, 16384)), b(128);
     if (a.tape)
-        hipLaunchKernelGGL(k_refit_fwd<true>, g, b, 0, st, a, t0, t1, outputs ? 1 : 0);
+        hipLaunchKernelGGL(k_refit_fwd<true>, g, b, 0, st, a, t0, t1, outputs ? 1 : 0, 0, 3);
     else
-        hipLaunchKernelGGL(k_refit_fwd<false>, g, b, 0, st, a, t0, t1, outputs ? 1 : 0);
+        hipLaunchKernelGGL(k_refit_fwd<false>, g, b, 0, st, a, t0, t1, outputs ? 1 : 0, 0, 3);
+}
+
+void enqueue_refit_segment(const AdjBufs& a, int64_t t0, int64_t t1, int seg, hipStream_t st) {
+    if (t1 <= t0) return;
+    const dim3 g(blocks_for(t1 - t0, 128, 16384)), b(128);
+    hipLaunchKernelGGL(k_refit_fwd<true>, g, b, 0, st, a, t0, t1, 0, seg, seg + 1);
 }
 
 void enqueue_refit_total(const AdjBufs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_sum_chi2, dim3(1), dim3(1024), 0, st, a);
 }
 
-void enqueue_refit_reverse(const AdjBufs& a, int64_t t0, int64_t t1, hipStream_t st) {
+void enqueue_refit_reverse(const AdjBufs& a, int64_t t0, int64_t t1, int seg, hipStream_t st) {
     if (t1 <= t0) return;
     const dim3 g(blocks_for(t1 - t0, 128, 16384)), b(128);
     if (a.adj_f64)
-        hipLaunchKernelGGL(k_refit_bwd<double>, g, b, 0, st, a, t0, t1);
+        hipLaunchKernelGGL(k_refit_bwd<double>, g, b, 0, st, a, t0, t1, seg);
     else
-        hipLaunchKernelGGL(k_refit_bwd<float>, g, b, 0, st, a, t0, t1);
+        hipLaunchKernelGGL(k_refit_bwd<float>, g, b, 0, st, a, t0, t1, seg);
 }
 
-size_t map_grad_scratch_bytes(int64_t n_hits) { return sizeof(GradRec) * (size_t)n_hits; }
+size_t map_grad_scratch_bytes(int64_t n_hits) {
+    return (sizeof(MapFixed) + 255) / 256 * 256 + sizeof(GradRec) * (size_t)n_hits;
+}
 
 void enqueue_refit_map_grad(const AdjBufs& a, void* scratch, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(kMapSize, 256, 1024)), dim3(256), 0, st, a.grad_map,
                        (int64_t)kMapSize);
     if (a.n_hits <= 0) return;
-    GradRec* rec = (GradRec*)scratch;
-    hipLaunchKernelGGL(k_grad_cells, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a, rec);
+    MapFixed* fx = (MapFixed*)scratch;
+    GradRec* rec = (GradRec*)((char*)scratch + (sizeof(MapFixed) + 255) / 256 * 256);
+    // zero the fixed-point block (a fill kernel: also safe under graph capture)
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(sizeof(MapFixed) / 8, 256, 1024)), dim3(256), 0, st,
+                       (double*)fx, (int64_t)(sizeof(MapFixed) / 8));
+    hipLaunchKernelGGL(k_grad_cells, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a, rec, fx);
+    hipLaunchKernelGGL(k_map_scale, dim3(1), dim3(64), 0, st, fx, a.n_hits);
     hipLaunchKernelGGL(k_map_scatter, dim3((unsigned)((a.n_hits + kMapScatterHits - 1) / kMapScatterHits)),
-                       dim3(kMapScatterThreads), 0, st, a, (const GradRec*)rec);
+                       dim3(kMapScatterThreads), 0, st, a, (const GradRec*)rec, fx);
+    hipLaunchKernelGGL(k_map_from_fixed, dim3(blocks_for(kMapSize, 256, 1024)), dim3(256), 0, st, a,
+                       (const MapFixed*)fx);
 }
 
 void enqueue_refit_hit_grad(const AdjBufs& a, double* out, hipStream_t st) {

@@ -41,8 +41,8 @@ struct Arena {
 // Everything a captured launch sequence depends on: every device pointer its
 // kernels take (each in its own slot), the stream, sizes and tuning.
 struct GraphKey {
-    const void* p[19];
-    int64_t v[9];
+    const void* p[21];
+    int64_t v[10];
     bool operator==(const GraphKey& o) const {
         return std::memcmp(p, o.p, sizeof(p)) == 0 && std::memcmp(v, o.v, sizeof(v)) == 0;
     }
@@ -78,6 +78,8 @@ struct tpcca_ctx {
     bool events = false;
     float stage_ms[8] = {};
     void* noalloc = nullptr;  // this device's address of the static scratch array
+    void* mg_base = nullptr;  // scratch of the cross-sector merge, grown on demand
+    size_t mg_bytes = 0;
     // differentiable refit: per-track / per-cluster scratch, tape, status, last forward
     void* adj_base = nullptr;
     size_t adj_bytes = 0;
@@ -128,6 +130,11 @@ void build_consts(const tpcca_params& p, DevConsts& K) {
     }
     for (int s = 0; s < 18; ++s) K.alpha[s] = (float)((s + 0.5) * 20.0 * kPi / 180.0);
     K.kB = (float)(-0.00299792458 * p.bz);
+    K.kB_f64 = -0.00299792458 * p.bz;
+    K.chi2_merge = (float)p.chi2_merge;
+    K.merge_max_gap = p.merge_max_gap;
+    K.rot_c = (float)std::cos(20.0 * kPi / 180.0);
+    K.rot_s = (float)std::sin(20.0 * kPi / 180.0);
     const float sy = (float)p.sigma_y, sz = (float)p.sigma_z;
     K.vy = sy * sy;
     K.vz = sz * sz;
@@ -152,6 +159,8 @@ tpcca_status check_params(tpcca_ctx* ctx, const tpcca_params& p) {
     if (p.n_min < 3 || p.n_min > p.n_rows) return fail(ctx, TPCCA_E_ARG, "n_min must be in [3, n_rows]");
     if (p.max_miss < 1) return fail(ctx, TPCCA_E_ARG, "max_miss must be >= 1");
     if (!(p.u_max > 0 && p.u_max <= 0.5)) return fail(ctx, TPCCA_E_ARG, "u_max must be in (0, 0.5]");
+    if (!(p.chi2_merge > 0)) return fail(ctx, TPCCA_E_ARG, "chi2_merge must be positive");
+    if (p.merge_max_gap < 0 || p.merge_max_gap > 255) return fail(ctx, TPCCA_E_ARG, "merge_max_gap must be in [0, 255]");
     return TPCCA_OK;
 }
 
@@ -164,6 +173,8 @@ tpcca_status check_tuning(tpcca_ctx* ctx, const tpcca_tuning& t) {
         return fail(ctx, TPCCA_E_ARG, "tracklet and refit blocks hold at most 256 threads");
     if (t.tape_mb < 1) return fail(ctx, TPCCA_E_ARG, "tape_mb must be >= 1");
     if (t.xcd_remap != 0 && t.xcd_remap != 1) return fail(ctx, TPCCA_E_ARG, "xcd_remap must be 0 or 1");
+    if (t.ckpt != 0 && t.ckpt != 1) return fail(ctx, TPCCA_E_ARG, "ckpt must be 0 or 1");
+    if (t.inward_wgs < 0 || t.inward_wgs > 65536) return fail(ctx, TPCCA_E_ARG, "inward_wgs must be in [0, 65536]");
     return TPCCA_OK;
 }
 
@@ -193,10 +204,13 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     size_t o_tpp = L.add(4 * cap_s * nr), o_tpr = L.add((size_t)cap_s * nr);
     size_t o_w = L.add(4 * N), o_own = L.add(4 * cap_s), o_ownm = L.add(32 * cap_s);
     size_t o_sel = L.add(4 * cap_sel), o_soff = L.add(4 * cap_sel), o_sn = L.add(4 * cap_sel);
-    size_t o_spos = L.add(4 * N), o_syz = L.add(8 * N), o_srow = L.add(N), o_smask = L.add(N);
+    size_t o_spos = L.add(4 * N), o_syz = L.add(8 * N), o_srow = L.add(N), o_smask = L.add(N), o_sres = L.add(4 * N);
     size_t o_rs = L.add(80 * cap_sel), o_rc = L.add(4 * cap_sel), o_rn = L.add(4 * cap_sel),
            o_rr = L.add(4 * cap_sel), o_rok = L.add(4 * cap_sel), o_kt = L.add(4 * cap_sel), o_kho = L.add(4 * cap_sel);
     size_t o_part = L.add(8 * kScanBlocks);
+    const bool km = (ctx->params.flags & TPCCA_FLAG_MERGE) != 0;
+    size_t o_rs2 = L.add(km ? 80 * cap_sel : 0), o_rr2 = L.add(km ? 4 * cap_sel : 0),
+           o_tsi = L.add(km ? 4 * cap_sel : 0), o_thr = L.add(km ? N : 0);
     *total = L.total;
     if (!really) return;
     char* base = (char*)(at ? at : ctx->arena.base);
@@ -213,7 +227,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     b.starts = (int32_t*)(base + o_st);
     b.start_inst = (int32_t*)(base + o_sti);
     b.seed_order = (int32_t*)(base + o_so);
-    b.seed_len = (int32_t*)(base + o_sl);
+    b.tl_last = (int32_t*)(base + o_sl);
     b.tl_nhits = (int32_t*)(base + o_tn);
     b.tl_tid = (int32_t*)(base + o_tt);
     b.tl_row = (int32_t*)(base + o_tr);
@@ -231,6 +245,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     b.sel_yz = (float2*)(base + o_syz);
     b.sel_row = (uint8_t*)(base + o_srow);
     b.sel_mask = (uint8_t*)(base + o_smask);
+    b.sel_res = (uint32_t*)(base + o_sres);
     b.rf_state = (float*)(base + o_rs);
     b.rf_chi2 = (float*)(base + o_rc);
     b.rf_nacc = (int32_t*)(base + o_rn);
@@ -239,6 +254,11 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     b.trk_t = (int32_t*)(base + o_kt);
     b.trk_ho = (int32_t*)(base + o_kho);
     b.scan_part = (unsigned long long*)(base + o_part);
+    b.keep_merge = km ? 1 : 0;
+    b.rf_state2 = (float*)(base + o_rs2);
+    b.rf_row2 = (int32_t*)(base + o_rr2);
+    b.trk_si = (int32_t*)(base + o_tsi);
+    b.trk_hrow = (uint8_t*)(base + o_thr);
 }
 
 tpcca_status ensure_arena(tpcca_ctx* ctx, int64_t N, int64_t nseg, int64_t ninst) {
@@ -287,6 +307,8 @@ tpcca_status check_io(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_trac
                                 !out->chi2 || !out->ndf))
         return fail(ctx, TPCCA_E_ARG, "null track arrays");
     if (out->cap_hits > 0 && !out->hit_id) return fail(ctx, TPCCA_E_ARG, "null hit_id");
+    if (out->residuals && (out->residual_step_log2 < -20 || out->residual_step_log2 > 4))
+        return fail(ctx, TPCCA_E_ARG, "residual_step_log2 must be in [-20, 4]");
     return TPCCA_OK;
 }
 
@@ -341,11 +363,15 @@ Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out
     b.o_hit_start = out->hit_start;
     b.o_hit_id = out->hit_id;
     b.o_chi2_total = out->chi2_total;
+    b.o_z0 = out->z0;
+    b.o_res = out->residuals;
+    b.res_scale = std::ldexp(1.0f, -out->residual_step_log2);
     return b;
 }
 
 Launch make_launch(const tpcca_tuning& t) {
-    return Launch{t.block_links, t.block_tracklet, t.block_refit, t.block_scan, t.sort_seeds, t.xcd_remap};
+    return Launch{t.block_links, t.block_tracklet, t.block_refit, t.block_scan, t.sort_seeds, t.xcd_remap,
+                  t.inward_wgs};
 }
 
 // The whole pipeline for instances [i0, i1) with clusters [c0, c1).
@@ -356,7 +382,7 @@ void enqueue_range(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, i
     };
     enqueue_weights_clear(b, c0, c1, st);
     mark(0);
-    enqueue_grid(b, i0, i1, st);
+    enqueue_grid(b, i0, i1, max_row, st);
     mark(1);
     enqueue_links(b, L, i0, i1, max_row, st);
     mark(2);
@@ -399,16 +425,18 @@ tpcca_status finish_call(tpcca_ctx* ctx, const Bufs& b, tpcca_tracks* out, int64
 GraphKey graph_key(const tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out, hipStream_t st,
                    const int64_t* counts, const int32_t* status, int mrow) {
     GraphKey key{};
-    const void* ps[19] = {in->inst_sector, in->row_start, in->y,        in->z,        out->inst,
+    const void* ps[21] = {in->inst_sector, in->row_start, in->y,        in->z,        out->inst,
                           out->x_ref,       out->alpha,     out->param,   out->cov,     out->chi2,
                           out->ndf,         out->hit_start, out->hit_id,  out->chi2_total,
-                          ctx->arena.base,  (void*)st,      (void*)ctx->dK, counts,     status};
+                          ctx->arena.base,  (void*)st,      (void*)ctx->dK, counts,     status, out->z0,
+                          out->residuals};
     std::memcpy(key.p, ps, sizeof(ps));
-    const int64_t vs[9] = {in->n_inst, in->n_clusters, out->cap_tracks, out->cap_hits, mrow,
-                           ctx->tuning.hits_per_bin * 4 + ctx->tuning.xcd_remap * 2 + ctx->tuning.sort_seeds,
+    const int64_t vs[10] = {in->n_inst, in->n_clusters, out->cap_tracks, out->cap_hits, mrow,
+                           (ctx->tuning.inward_wgs * 64LL + ctx->tuning.hits_per_bin) * 4 + ctx->tuning.xcd_remap * 2 +
+                               ctx->tuning.sort_seeds,
                            ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
                            ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
-                           counts != nullptr ? 1 : 0};
+                           counts != nullptr ? 1 : 0, out->residual_step_log2};
     std::memcpy(key.v, vs, sizeof(vs));
     return key;
 }
@@ -594,7 +622,7 @@ tpcca_status run_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* o
 namespace {
 
 struct AdjLayout {
-    size_t o_inst, o_row, o_yz, o_grad, o_rec, o_nops, o_status, total;
+    size_t o_inst, o_row, o_yz, o_grad, o_rec, o_nops, o_status, o_ckpt, o_segn, o_carry, total;
 };
 
 AdjLayout adj_layout(int64_t cap_t, int64_t cap_h) {
@@ -607,6 +635,9 @@ AdjLayout adj_layout(int64_t cap_t, int64_t cap_h) {
     a.o_rec = L.add(map_grad_scratch_bytes(cap_h));
     a.o_nops = L.add(4 * cap_t);
     a.o_status = L.add(256);
+    a.o_ckpt = L.add(3 * 4 * kCkptWords * cap_t);
+    a.o_segn = L.add(4 * cap_t);
+    a.o_carry = L.add(8 * 20 * cap_t);
     a.total = L.total;
     return a;
 }
@@ -695,6 +726,8 @@ tpcca_status tpcca_default_params(tpcca_params* p) {
     p->n_min = 10;
     p->max_miss = 8;
     p->flags = 0;
+    p->chi2_merge = 25.0;
+    p->merge_max_gap = 24;
     return TPCCA_OK;
 }
 
@@ -708,6 +741,8 @@ tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
     t->sort_seeds = 0;
     t->tape_mb = 32768;
     t->xcd_remap = 1;
+    t->ckpt = 0;
+    t->inward_wgs = 0;
     return TPCCA_OK;
 }
 
@@ -760,6 +795,7 @@ tpcca_status tpcca_create(const tpcca_params* params, const tpcca_tuning* tuning
 void tpcca_destroy(tpcca_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    if (ctx->mg_base) (void)hipFree(ctx->mg_base);
     (void)hipDeviceSynchronize();
     if (ctx->has_graph) {
         (void)hipGraphExecDestroy(ctx->gexec);
@@ -815,6 +851,98 @@ tpcca_status tpcca_track_async_noalloc(tpcca_ctx* ctx, const tpcca_clusters* in,
                                        int32_t* status, void* hip_stream) {
     if (!ctx) return TPCCA_E_ARG;
     return run_noalloc(ctx, in, out, counts, status, hip_stream);
+}
+
+tpcca_status tpcca_merge(tpcca_ctx* ctx, const int32_t* inst_event, tpcca_tracks* merged, int32_t* nseg,
+                         int32_t* seg_next, void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    if (!(ctx->params.flags & TPCCA_FLAG_MERGE))
+        return fail(ctx, TPCCA_E_ARG, "the context was created without TPCCA_FLAG_MERGE");
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "tpcca_merge needs a completed synchronous track call");
+    if (!merged || !merged->hit_start) return fail(ctx, TPCCA_E_ARG, "null merged tracks or hit_start");
+    const Bufs& lb = ctx->last;
+    if (lb.n_inst > 0 && !inst_event) return fail(ctx, TPCCA_E_ARG, "null inst_event");
+    const unsigned long long tot = ctx->last_ctr.slot[SL_TRK][0];
+    const int64_t nt = (int64_t)(tot >> 32), nh = (int64_t)(tot & 0xFFFFFFFFull);
+    if (nt > lb.cap_tracks || nh > lb.cap_hits)
+        return fail(ctx, TPCCA_E_ARG, "the last track call did not fit its outputs");
+    if (merged->cap_tracks > 0 && (!merged->inst || !merged->x_ref || !merged->alpha || !merged->param ||
+                                   !merged->cov || !merged->chi2 || !merged->ndf))
+        return fail(ctx, TPCCA_E_ARG, "null merged track arrays");
+    if (merged->cap_hits > 0 && !merged->hit_id) return fail(ctx, TPCCA_E_ARG, "null merged hit_id");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t nkeys = (int64_t)lb.n_inst * lb.n_rows;
+    const int64_t t1 = std::max<int64_t>(nt, 1);
+    Layout L;
+    const size_t o_nb = L.add(8 * std::max<int64_t>(lb.n_inst, 1)), o_rc = L.add(4 * (nkeys + 1)),
+                 o_rs = L.add(4 * (nkeys + 1)), o_rf = L.add(4 * (nkeys + 1)), o_ri = L.add(4 * t1),
+                 o_bo = L.add(4 * t1), o_bi = L.add(8 * t1), o_nx = L.add(4 * t1), o_pv = L.add(4 * t1),
+                 o_ok = L.add(4 * t1), o_ab = L.add(t1), o_st = L.add(80 * t1), o_c2 = L.add(4 * t1),
+                 o_na = L.add(4 * t1), o_rw = L.add(4 * t1), o_ns = L.add(4 * t1),
+                 o_a3 = L.add(std::max<int64_t>(nh, 1)), o_ot = L.add(4 * t1), o_oh = L.add(8 * t1);
+    if (L.total > ctx->mg_bytes) {
+        if (ctx->mg_base) {
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipFree(ctx->mg_base));
+            ctx->mg_base = nullptr;
+            ctx->mg_bytes = 0;
+        }
+        const hipError_t e = hipMalloc(&ctx->mg_base, L.total);
+        if (e != hipSuccess) {
+            ctx->mg_base = nullptr;
+            return hip_fail(ctx, e, "merge scratch allocation");
+        }
+        ctx->mg_bytes = L.total;
+    }
+    char* base = (char*)ctx->mg_base;
+    MergeBufs m{};
+    m.b = lb;
+    m.inst_event = inst_event;
+    m.n_t = nt;
+    m.nb = (int32_t*)(base + o_nb);
+    m.rcnt = (int32_t*)(base + o_rc);
+    m.rstart = (int32_t*)(base + o_rs);
+    m.rfill = (int32_t*)(base + o_rf);
+    m.rids = (int32_t*)(base + o_ri);
+    m.best_out = (int32_t*)(base + o_bo);
+    m.best_in = (unsigned long long*)(base + o_bi);
+    m.next = (int32_t*)(base + o_nx);
+    m.prev = (int32_t*)(base + o_pv);
+    m.ok = (int32_t*)(base + o_ok);
+    m.absorbed = (uint8_t*)(base + o_ab);
+    m.state = (float*)(base + o_st);
+    m.chi2 = (float*)(base + o_c2);
+    m.nacc = (int32_t*)(base + o_na);
+    m.row = (int32_t*)(base + o_rw);
+    m.nseg = (int32_t*)(base + o_ns);
+    m.acc3 = (uint8_t*)(base + o_a3);
+    m.out_t = (int32_t*)(base + o_ot);
+    m.out_h = (int64_t*)(base + o_oh);
+    m.cap_tracks = merged->cap_tracks;
+    m.cap_hits = merged->cap_hits;
+    m.o_inst = merged->inst;
+    m.o_xref = merged->x_ref;
+    m.o_alpha = merged->alpha;
+    m.o_param = merged->param;
+    m.o_cov = merged->cov;
+    m.o_chi2 = merged->chi2;
+    m.o_ndf = merged->ndf;
+    m.o_hit_start = merged->hit_start;
+    m.o_hit_id = merged->hit_id;
+    m.o_nseg = nseg;
+    m.seg_next = seg_next;
+    enqueue_merge(m, st);
+    HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    const unsigned long long mt = ctx->hctr->slot[SL_MRG][0];
+    merged->n_tracks = (int64_t)(mt >> 32);
+    merged->n_hits = (int64_t)(mt & 0xFFFFFFFFull);
+    if (merged->n_tracks > merged->cap_tracks || merged->n_hits > merged->cap_hits)
+        return fail(ctx, TPCCA_E_CAPACITY, "merged output capacity too small (n_tracks / n_hits hold the sizes)");
+    ctx->err.clear();
+    return TPCCA_OK;
 }
 
 tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_t repeats, tpcca_tuning* out,
@@ -1061,15 +1189,20 @@ tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* in, const tpc
     a.track_ok = track_ok;
     a.chi2_total = chi2_total;
     a.adj_f64 = (ctx->params.flags & TPCCA_FLAG_ADJOINT_F64) ? 1 : 0;
+    const bool ckpt = ctx->tuning.ckpt != 0;
+    a.seg_nops = (int32_t*)(base + L.o_segn);
+    a.carry = (double*)(base + L.o_carry);
+    if (ckpt && record) a.ckpt = (float*)(base + L.o_ckpt);
     // validation, corrected clusters, operation counts; the host sizes the tape
     enqueue_refit_prepare(a, st);
     s = read_adj_status(ctx, a, st);
     if (s != TPCCA_OK) return s;
-    a.tape_ops = ctx->h_adj_status->max_ops;
+    // the tape holds a whole refit per track, or with checkpoints one pass segment
+    a.tape_ops = ckpt ? ctx->h_adj_status->max_seg_ops : ctx->h_adj_status->max_ops;
     const int64_t per_track = std::max<int64_t>(1, (int64_t)a.tape_ops * kTapeBytesPerOp);
     const int64_t budget = (int64_t)ctx->tuning.tape_mb << 20;
     const int64_t batch = std::min<int64_t>(std::max<int64_t>(1, budget / per_track), std::max<int64_t>(nt, 1));
-    const bool taped = record && batch >= nt;
+    const bool taped = record && !ckpt && batch >= nt;
     if (taped) {
         s = ensure_tape(ctx, (size_t)(per_track * std::max<int64_t>(nt, 1)));
         if (s != TPCCA_OK) return s;
@@ -1100,17 +1233,26 @@ tpcca_status tpcca_refit_bwd(tpcca_ctx* ctx, const float* grad_chi2, double* gra
     a.grad_params = grad_params0;
     a.grad_map = grad_map;
     if (ctx->adj_taped) {
-        enqueue_refit_reverse(a, 0, a.n_tracks, st);
+        enqueue_refit_reverse(a, 0, a.n_tracks, -1, st);
     } else {
-        // the set's tape exceeds the budget: record and reverse batch by batch
+        // record and reverse batch by batch: the whole refit when the set's
+        // tape exceeds the budget, or one pass segment at a time, last pass
+        // first, recomputed from its checkpoint
         const int64_t per_track = std::max<int64_t>(1, (int64_t)a.tape_ops * kTapeBytesPerOp);
         tpcca_status s = ensure_tape(ctx, (size_t)(per_track * ctx->adj_batch));
         if (s != TPCCA_OK) return s;
         a.tape = (uint32_t*)ctx->tape_base;
         for (int64_t t0 = 0; t0 < a.n_tracks; t0 += ctx->adj_batch) {
             const int64_t t1 = std::min(a.n_tracks, t0 + ctx->adj_batch);
-            enqueue_refit_forward(a, t0, t1, false, st);
-            enqueue_refit_reverse(a, t0, t1, st);
+            if (a.ckpt) {
+                for (int seg = 2; seg >= 0; --seg) {
+                    enqueue_refit_segment(a, t0, t1, seg, st);
+                    enqueue_refit_reverse(a, t0, t1, seg, st);
+                }
+            } else {
+                enqueue_refit_forward(a, t0, t1, false, st);
+                enqueue_refit_reverse(a, t0, t1, -1, st);
+            }
         }
     }
     if (grad_map) {

@@ -28,11 +28,12 @@ enum {
 // Running totals of the three compactions (starts, selected, tracks); each
 // slot holds {running total, base of the current range, count of the current
 // range} as packed (hi 32: items, lo 32: sub-items) 64-bit sums.
-enum { SL_START = 0, SL_SEL = 1, SL_TRK = 2 };
+enum { SL_START = 0, SL_SEL = 1, SL_TRK = 2, SL_MRG = 3 };
 struct Counters {
-    unsigned long long slot[3][3];
+    unsigned long long slot[4][3];
     unsigned int err;
     unsigned int pad;
+    unsigned int tlq[8];  // queues of the persistent inward-pass kernel (one per XCD)
     unsigned long long stats[ST_COUNT];
 };
 
@@ -72,7 +73,7 @@ struct Bufs {
     int32_t* starts;     // grid position of the start hit
     int32_t* start_inst;
     int32_t* seed_order; // processing order of tracklets (permutation of the start range)
-    int32_t* seed_len;   // chain length per start (for the order)
+    int32_t* tl_last;    // last row with a cluster after the outward following
     int32_t* tl_nhits;
     int32_t* tl_tid;
     int32_t* tl_row;
@@ -113,10 +114,62 @@ struct Bufs {
     int64_t* o_hit_start;
     int32_t* o_hit_id;
     double* o_chi2_total;
+    float* o_z0;         // may be null
+    int16_t* o_res;      // may be null: compression residuals [cap_hits * 2]
+    float res_scale;     // 1 / residual step (a power of two)
+    uint32_t* sel_res;   // [N] packed (y, z) int16 residuals per selected cluster
+    // kept for the cross-sector merge (TPCCA_FLAG_MERGE)
+    int keep_merge;
+    float* rf_state2;    // [cap_sel * 20] state after the outward pass (absolute y, z)
+    int32_t* rf_row2;    // [cap_sel] its row
+    int32_t* trk_si;     // [cap_sel] selected index of output track t
+    uint8_t* trk_hrow;   // [N] row of output cluster q
 };
 
+// The cross-sector merge of the last track call's output tracks.
+struct MergeBufs {
+    Bufs b;                       // the last track call (its inputs and outputs must still be valid)
+    const int32_t* inst_event;    // [n_inst] event of each instance
+    int64_t n_t;                  // sector tracks of that call
+    // scratch
+    int32_t* nb;                  // [n_inst * 2] neighbour instance per direction (-1: none)
+    int32_t* rcnt;                // [n_inst * n_rows + 1] tracks per (instance, reference row)
+    int32_t* rstart;              // [n_inst * n_rows + 1]
+    int32_t* rfill;               // [n_inst * n_rows]
+    int32_t* rids;                // [n_t] tracks bucketed by (instance, reference row)
+    int32_t* best_out;            // [n_t]
+    unsigned long long* best_in;  // [n_t] (chi2 bits << 32) | partner
+    int32_t* next;                // [n_t]
+    int32_t* prev;                // [n_t]
+    int32_t* ok;                  // [n_t] merged refit of the chain starting here succeeded
+    uint8_t* absorbed;            // [n_t] segment of a merged chain after its first
+    float* state;                 // [n_t * 20]
+    float* chi2;                  // [n_t]
+    int32_t* nacc;                // [n_t]
+    int32_t* row;                 // [n_t]
+    int32_t* nseg;                // [n_t]
+    uint8_t* acc3;                // [n_hits] kept by the merged refit's last pass
+    int32_t* out_t;               // [n_t] output index
+    int64_t* out_h;               // [n_t] first output cluster
+    // outputs
+    int64_t cap_tracks, cap_hits;
+    int32_t* o_inst;
+    float* o_xref;
+    float* o_alpha;
+    float* o_param;
+    float* o_cov;
+    float* o_chi2;
+    int32_t* o_ndf;
+    int64_t* o_hit_start;
+    int32_t* o_hit_id;
+    int32_t* o_nseg;              // may be null
+    int32_t* seg_next;            // may be null: [n_t] outer partner of each sector track in the output
+};
+
+void enqueue_merge(const MergeBufs& m, hipStream_t st);
+
 struct Launch {
-    int block_links, block_tracklet, block_refit, block_scan, sort_seeds, xcd_remap;
+    int block_links, block_tracklet, block_refit, block_scan, sort_seeds, xcd_remap, inward_wgs;
 };
 
 constexpr int kScanBlocks = 1024;
@@ -124,7 +177,7 @@ constexpr int kScanBlocks = 1024;
 // Instance range [i0, i1) with its cluster range [c0, c1) (host values).
 void enqueue_reset(const Bufs& b, hipStream_t st);
 void enqueue_weights_clear(const Bufs& b, int64_t c0, int64_t c1, hipStream_t st);
-void enqueue_grid(const Bufs& b, int i0, int i1, hipStream_t st);
+void enqueue_grid(const Bufs& b, int i0, int i1, int max_row, hipStream_t st);  // max_row: largest row (bound)
 void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, int max_row, hipStream_t st);
 void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, hipStream_t st);
 void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st);

@@ -625,6 +625,30 @@ __global__ void k_sel_fill(Bufs b) {
     }
 }
 
+// z of the point of closest approach of the helix (state p at local x) to
+// the beam line, the z axis of every sector frame: the turning angle d from
+// the state solves A cos d + (B + 1/c) sin d = 0 with A = x cos phi + y sin phi,
+// B = -x sin phi + y cos phi and curvature c = kB q/pT, so d = atan2(-A c,
+// 1 + B c) and z0 = z + tan(lambda) d / c (as A/(1 + B c) atan(w)/w, w = -A c /
+// (1 + B c), where 1 + B c > 0: exact in the straight-line limit). FP64: a
+// derived output, evaluated once per track, not part of the Kalman filter.
+__device__ __forceinline__ float vertex_z(double kB, double x, const float* p) {
+    const double y = p[0], z = p[1], sp = p[2], tl = p[3], q = p[4];
+    const double cp = sqrt(1.0 - sp * sp);
+    const double c = kB * q;
+    const double A = x * cp + y * sp, B = -x * sp + y * cp;
+    const double den = 1.0 + B * c;
+    double s;
+    if (den > 0.0) {
+        const double w = -A * c / den;
+        const double g = (w == 0.0) ? 1.0 : atan(w) / w;
+        s = -A / den * g;
+    } else {
+        s = atan2(-A * c, den) / c;
+    }
+    return (float)(z + tl * s);
+}
+
 // Output tracks, over the current range of selected tracklets.
 struct TrackOp {
     Bufs b;
@@ -659,6 +683,8 @@ struct TrackOp {
         b.o_chi2[t] = b.rf_chi2[si];
         b.o_ndf[t] = 2 * nacc - 5;
         b.o_hit_start[t] = ho;
+        if (b.keep_merge) b.trk_si[t] = (int32_t)si;
+        if (b.o_z0) b.o_z0[t] = vertex_z(K.kB_f64, (double)K.X[b.rf_row[si]], b.rf_state + si * 20);
     }
 };
 
@@ -684,7 +710,12 @@ __global__ void k_trk_fill(Bufs b) {
             const int i = c + lane;
             const bool use = i < n && (b.sel_mask[off + i] & 4);
             const unsigned long long bal = __ballot(use);
-            if (use) b.o_hit_id[ho + run + __popcll(bal & below)] = b.sid[b.sel_pos[off + i]];
+            if (use) {
+                const int64_t at = ho + run + __popcll(bal & below);
+                b.o_hit_id[at] = b.sid[b.sel_pos[off + i]];
+                if (b.o_res) reinterpret_cast<uint32_t*>(b.o_res)[at] = b.sel_res[off + i];
+                if (b.keep_merge) b.trk_hrow[at] = b.sel_row[off + i];
+            }
             run += __popcll(bal);
         }
     }
@@ -827,6 +858,76 @@ __device__ __forceinline__ int lower_bound_inst(const int32_t* a, int64_t lo, in
 
 // One lane per start hit: seed, stage 1 (chain), stage 2 (outward), turn,
 // stage 3 (inward re-pick), weights.
+// Stage-3 pick store: picks leave four at a time (one 16-byte and one 4-byte
+// store) from a shift register, newest in p0; rows pack oldest-lowest.
+struct PickRing {
+    int32_t p0, p1, p2, p3;
+    uint32_t rows4;
+};
+
+__device__ __forceinline__ void pick_store(const Bufs& b, int64_t j, int nr, int nh, int32_t pos, int r, bool vec,
+                                           PickRing& pr) {
+    if (vec) {
+        pr.p3 = pr.p2;
+        pr.p2 = pr.p1;
+        pr.p1 = pr.p0;
+        pr.p0 = pos;
+        pr.rows4 = (pr.rows4 >> 8) | ((uint32_t)r << 24);
+        if (((nh + 1) & 3) == 0) {
+            *reinterpret_cast<int4*>(b.tl_pick_pos + j * nr + nh - 3) = make_int4(pr.p3, pr.p2, pr.p1, pr.p0);
+            *reinterpret_cast<uint32_t*>(b.tl_pick_row + j * nr + nh - 3) = pr.rows4;
+        }
+    } else {
+        b.tl_pick_pos[j * nr + nh] = pos;
+        b.tl_pick_row[j * nr + nh] = (uint8_t)r;
+    }
+}
+
+// The last picks (fewer than four), the pick count and the packed weights of
+// a finished tracklet.
+__device__ __forceinline__ void tracklet_finish(const Bufs& b, int64_t j, int nr, int nh, int tid, bool vec,
+                                                const PickRing& pr, int n_min) {
+    if (vec) {
+        const int k = nh & 3;
+        int32_t* pp = b.tl_pick_pos + j * nr + (nh - k);
+        uint8_t* prow = b.tl_pick_row + j * nr + (nh - k);
+        if (k == 3) {
+            pp[0] = pr.p2;
+            pp[1] = pr.p1;
+            pp[2] = pr.p0;
+        } else if (k == 2) {
+            pp[0] = pr.p1;
+            pp[1] = pr.p0;
+        } else if (k == 1) {
+            pp[0] = pr.p0;
+        }
+        for (int i = 0; i < k; ++i) prow[i] = (uint8_t)(pr.rows4 >> (8 * (4 - k + i)));
+    }
+    b.tl_nhits[j] = nh;
+    if (nh >= n_min) {
+        // weights: the picks are read back eight per memory round trip
+        // (atomic max: the order of the tracklets does not matter)
+        const uint32_t w = packed_weight(nh, tid);
+        const int32_t* pp = b.tl_pick_pos + j * nr;
+        if ((nr & 3) == 0) {
+            for (int q = 0; q < nh; q += 8) {
+                const int4 a = *reinterpret_cast<const int4*>(pp + q);
+                int4 c = make_int4(0, 0, 0, 0);
+                if (q + 4 < nh) c = *reinterpret_cast<const int4*>(pp + q + 4);  // q + 8 <= nr
+                const int32_t v[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (q + i < nh) atomicMax(&b.weight[v[i]], w);
+            }
+        } else {
+            for (int q = 0; q < nh; ++q) atomicMax(&b.weight[pp[q]], w);
+        }
+    }
+}
+
+// kSplit = 1: stop at the turn (the state, the row it reached and the last
+// row with a cluster are stored) and leave the inward stage to k_tracklet_in.
+template <int kSplit>
 __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
@@ -837,6 +938,7 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
     if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;  // never hit: N/3 bound
+    if (blockIdx.x == 0 && threadIdx.x < 8) b.ctr->tlq[threadIdx.x] = 0u;  // queues of k_tracklet_in
     unsigned int st_chain = 0, st_rows = 0, st_cand = 0, st_picks = 0;  // per lane: 32 bits suffice
     // logical workgroup (seeds are ordered by instance): with the XCD
     // renumbering over the workgroups that have seeds, each XCD follows the
@@ -944,98 +1046,52 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
 #pragma unroll
             for (int q = 0; q < 15; ++q) o[5 + q] = s.C[q];
             b.tl_row[j] = cur;
-            // turn, stage 3
-            kf_reset(s, kc);
-            bool down_ok = true;
-            for (int r = cur - 1; r >= last; --r) {
-                if (!kf_propagate(s, sX[r + 1], sX[r], kc)) {
-                    down_ok = false;
-                    break;
-                }
-                cur = r;
-            }
-            if (down_ok) {
-                miss = 0;
-                // picks leave four at a time (one 16-byte and one 4-byte store)
-                // from a shift register, newest in p0; rows pack oldest-lowest
-                const bool vec = (nr & 3) == 0;  // 16-byte aligned per-tracklet rows
-                int32_t p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-                uint32_t rows4 = 0;
-                SegHdr hn3 = load_hdr(b, seg0 + last);
-                for (int r = last; r >= 0; --r) {
-                    const SegHdr h = hn3;
-                    hn3 = load_hdr(b, seg0 + max(r - 1, 0));
-                    if (r != cur) {
-                        if (!kf_propagate(s, sX[cur], sX[r], kc)) break;
-                        cur = r;
-                    }
-                    ++st_rows;
-                    Pick pk_;
-                    if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
-                        kf_update(s, pk_.inn);
-                        if (vec) {
-                            p3 = p2;
-                            p2 = p1;
-                            p1 = p0;
-                            p0 = pk_.pos;
-                            rows4 = (rows4 >> 8) | ((uint32_t)r << 24);
-                            if (((nh + 1) & 3) == 0) {
-                                *reinterpret_cast<int4*>(b.tl_pick_pos + j * nr + nh - 3) = make_int4(p3, p2, p1, p0);
-                                *reinterpret_cast<uint32_t*>(b.tl_pick_row + j * nr + nh - 3) = rows4;
-                            }
-                        } else {
-                            b.tl_pick_pos[j * nr + nh] = pk_.pos;
-                            b.tl_pick_row[j * nr + nh] = (uint8_t)r;
-                        }
-                        ++nh;
-                        miss = 0;
-                    } else if (++miss >= kc.max_miss) {
+            if (kSplit) b.tl_last[j] = last;
+            if (!kSplit) {
+                // turn, stage 3
+                kf_reset(s, kc);
+                bool down_ok = true;
+                for (int r = cur - 1; r >= last; --r) {
+                    if (!kf_propagate(s, sX[r + 1], sX[r], kc)) {
+                        down_ok = false;
                         break;
                     }
+                    cur = r;
                 }
-                if (vec) {  // the last picks, fewer than four
-                    const int k = nh & 3;
-                    int32_t* pp = b.tl_pick_pos + j * nr + (nh - k);
-                    uint8_t* pr = b.tl_pick_row + j * nr + (nh - k);
-                    if (k == 3) {
-                        pp[0] = p2;
-                        pp[1] = p1;
-                        pp[2] = p0;
-                    } else if (k == 2) {
-                        pp[0] = p1;
-                        pp[1] = p0;
-                    } else if (k == 1) {
-                        pp[0] = p0;
+                if (down_ok) {
+                    miss = 0;
+                    const bool vec = (nr & 3) == 0;  // 16-byte aligned per-tracklet rows
+                    PickRing pr{0, 0, 0, 0, 0u};
+                    SegHdr hn3 = load_hdr(b, seg0 + last);
+                    for (int r = last; r >= 0; --r) {
+                        const SegHdr h = hn3;
+                        hn3 = load_hdr(b, seg0 + max(r - 1, 0));
+                        if (r != cur) {
+                            if (!kf_propagate(s, sX[cur], sX[r], kc)) break;
+                            cur = r;
+                        }
+                        ++st_rows;
+                        Pick pk_;
+                        if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
+                            kf_update(s, pk_.inn);
+                            pick_store(b, j, nr, nh, pk_.pos, r, vec, pr);
+                            ++nh;
+                            miss = 0;
+                        } else if (++miss >= kc.max_miss) {
+                            break;
+                        }
                     }
-                    for (int i = 0; i < k; ++i) pr[i] = (uint8_t)(rows4 >> (8 * (4 - k + i)));
+                    tracklet_finish(b, j, nr, nh, tid, vec, pr, kc.n_min);
+                    st_picks += nh;
+                    continue;
                 }
             }
         }
         b.tl_nhits[j] = nh;
-        st_picks += nh;
         if (!ok) {
             float* o = b.tl_state + j * 20;
 #pragma unroll
             for (int q = 0; q < 20; ++q) o[q] = 0.0f;
-        }
-        if (nh >= kc.n_min) {
-            // weights: the picks are read back eight per memory round trip
-            // (atomic max: the order of the tracklets does not matter)
-            const uint32_t w = packed_weight(nh, tid);
-            const int32_t* pp = b.tl_pick_pos + j * nr;
-            if ((nr & 3) == 0) {
-                for (int q = 0; q < nh; q += 8) {
-                    const int4 a = *reinterpret_cast<const int4*>(pp + q);
-                    int4 c = make_int4(0, 0, 0, 0);
-                    if (q + 4 < nh) c = *reinterpret_cast<const int4*>(pp + q + 4);  // q + 8 <= nr
-                    const int32_t v[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (q + i < nh) atomicMax(&b.weight[v[i]], w);
-                }
-            } else {
-                for (int q = 0; q < nh; ++q) atomicMax(&b.weight[pp[q]], w);
-            }
         }
     }
     if (stats) {
@@ -1046,21 +1102,177 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     }
 }
 
+// The inward pass (stage 3) of the tracklets that k_tracklet<1> stopped at the
+// turn. Persistent: a lane whose tracklet ends takes the next one at once, so
+// that a wave is not held by its longest tracklet. Every lane runs the same
+// operations on a tracklet, in the same order, as the single-kernel form.
+// The tracklets are split into eight queues of consecutive seeds (seeds are
+// ordered by instance); a workgroup drains the queue of its own XCD first
+// (workgroups are dispatched to the XCDs round robin), then the others, so an
+// XCD's L2 mostly holds the grid of about one eighth of the instances.
+__global__ __launch_bounds__(256) void k_tracklet_in(Bufs b) {
+    const DevConsts& K = *b.K;
+    const int nr = K.n_rows;
+    const KfConsts kc = kf_consts(K);
+    const int stats = K.stats;
+    __shared__ float sX[kMaxRows];
+    kf_load_rows(sX, K);
+    const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
+    if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;
+    const bool vec = (nr & 3) == 0;
+    const int lane = (int)(threadIdx.x & 63);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned int st_rows = 0, st_cand = 0, st_picks = 0;
+    // wave-uniform queue cursor
+    int q = (int)(blockIdx.x & 7), tried = 0;
+    // lane state: 0 = needs a tracklet, 1 = down to the last row, 2 = inward
+    // picking, 3 = the queues are empty
+    int phase = 0;
+    int64_t j = 0, seg0 = 0;
+    int cur = 0, last = 0, r = 0, miss = 0, nh = 0, tid = 0;
+    KState s;
+    PickRing pr{0, 0, 0, 0, 0u};
+    SegHdr hn3{};
+    while (true) {
+        // lanes without a tracklet take the next ones of the current queue;
+        // a queue found empty moves the whole wave to the next
+        unsigned long long need = __ballot(phase == 0);
+        while (need != 0ull) {
+            if (tried == 8) {
+                if (phase == 0) phase = 3;
+                break;
+            }
+            const int64_t qlo = (int64_t)q * cnt / 8, qhi = (int64_t)(q + 1) * cnt / 8;
+            const int leader = __ffsll((long long)need) - 1;
+            unsigned int got = 0u;
+            if (lane == leader) got = atomicAdd(&b.ctr->tlq[q], (unsigned int)__popcll(need));
+            got = __shfl(got, leader, 64);
+            if (qlo + (int64_t)got + __popcll(need) > qhi) {  // the queue ran out while taking
+                q = (q + 1) & 7;
+                ++tried;
+            }
+            if (phase == 0) {
+                const int64_t k = qlo + (int64_t)got + __popcll(need & below);
+                if (k < qhi) {
+                    j = base + k;
+                    cur = b.tl_row[j];
+                    if (cur >= 0) {  // a tracklet whose outward following ended well
+                        const float* st = b.tl_state + j * 20;
+#pragma unroll
+                        for (int i = 0; i < 5; ++i) s.p[i] = st[i];
+#pragma unroll
+                        for (int i = 0; i < 15; ++i) s.C[i] = st[5 + i];
+                        kf_reset(s, kc);
+                        last = b.tl_last[j];
+                        tid = b.tl_tid[j];
+                        seg0 = (int64_t)b.start_inst[j] * nr;
+                        r = cur - 1 >= last ? cur - 1 : last;
+                        phase = cur - 1 >= last ? 1 : 2;
+                        miss = 0;
+                        nh = 0;
+                        hn3 = load_hdr(b, seg0 + last);
+                    }
+                }
+            }
+            need = __ballot(phase == 0);
+        }
+        if (__ballot(phase == 1 || phase == 2) == 0ull) break;
+        // one row: propagate (both phases), then pick (inward phase)
+        bool end = false;
+        if (phase == 1 || phase == 2) {
+            if (r != cur) {
+                if (!kf_propagate(s, sX[cur], sX[r], kc)) end = true;
+                else cur = r;
+            }
+            if (phase == 1 && !end) {
+                if (r == last) phase = 2;  // the inward picking starts on this row
+                else --r;
+            }
+            if (phase == 2 && !end) {
+                const SegHdr h = hn3;
+                hn3 = load_hdr(b, seg0 + max(r - 1, 0));
+                ++st_rows;
+                Pick pk_;
+                if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
+                    kf_update(s, pk_.inn);
+                    pick_store(b, j, nr, nh, pk_.pos, r, vec, pr);
+                    ++nh;
+                    miss = 0;
+                } else if (++miss >= kc.max_miss) {
+                    end = true;
+                }
+                if (--r < 0) end = true;
+            }
+        }
+        if (end) {
+            if (phase == 2) {  // a failed step on the way down leaves the tracklet without picks
+                tracklet_finish(b, j, nr, nh, tid, vec, pr, kc.n_min);
+                st_picks += nh;
+            }
+            phase = 0;
+        }
+    }
+    if (stats) {
+        stat_add(b.ctr, ST_TL_ROWS, st_rows);
+        stat_add(b.ctr, ST_TL_CAND, st_cand);
+        stat_add(b.ctr, ST_TL_PICKS, st_picks);
+    }
+}
+
 // ------------------------------------------------------------------ refit
 // One lane per selected tracklet: move to the outermost hit, then three
 // passes inward, outward, inward, each after a covariance reset; a hit is
 // used iff its predicted chi2 <= chi2_rej.
-__global__ __launch_bounds__(256) void k_refit(Bufs b) {
+//
+// A wave lasts as long as its longest track, and track lengths vary from ten
+// to a few hundred row steps. Each workgroup takes a chunk of consecutive
+// tracks (their cluster lists are adjacent in memory); with rank_by_work it
+// hands them to its lanes longest first (a rank by an estimate of the row
+// steps of the walk and the three passes, plus the updates), so that the
+// tracks of one wave have similar lengths. Every track is independent and
+// writes its own slots: the assignment changes no result. Measured: no faster
+// on the central events (the refit waits on memory more than on its longest
+// lane), so it is a tuning option, off by default.
+__device__ __forceinline__ int refit_work(const Bufs& b, int64_t si) {
+    const int off = b.sel_off[si], n = b.sel_n[si];
+    if (n <= 0) return 0;
+    const int lo = b.sel_row[off], hi = b.sel_row[off + n - 1];
+    return abs(b.tl_row[b.sel_tl[si]] - hi) + 3 * (hi - lo) + 3 * n;
+}
+
+__global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
     const DevConsts& K = *b.K;
     const KfConsts kc = kf_consts(K);
     const int stats = K.stats;
     __shared__ float sX[kMaxRows];
+    __shared__ int skey[256];
+    __shared__ int sorder[256];
     kf_load_rows(sX, K);
     const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
     if (base + cnt > b.cap_sel) cnt = b.cap_sel > base ? b.cap_sel - base : 0;  // never hit: N/n_min bound
     unsigned int st_rows = 0, st_hits = 0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cnt; k += (int64_t)gridDim.x * blockDim.x) {
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int64_t nchunk = (cnt + nt - 1) / nt;
+    for (int64_t chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {  // uniform over the workgroup
+        const int64_t k0 = chunk * nt;
+        int64_t k = k0 + tid;
+        if (rank_by_work) {  // uniform
+            const int key = (k0 + tid < cnt) ? refit_work(b, base + k0 + tid) : -1;
+            skey[tid] = key;
+            __syncthreads();
+            int rank = 0;  // longer first; equal work in chunk order
+            for (int j = 0; j < nt; ++j) {
+                const int kj = skey[j];
+                rank += (kj > key || (kj == key && j < tid)) ? 1 : 0;
+            }
+            sorder[rank] = tid;
+            __syncthreads();
+            k = k0 + sorder[tid];
+            __syncthreads();  // skey and sorder are rewritten by the next chunk
+        }
+        if (k >= cnt) continue;
         const int64_t si = base + k;
         const int32_t tl = b.sel_tl[si];
         const int off = b.sel_off[si], n = b.sel_n[si];
@@ -1132,6 +1344,16 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
                     }
                 }
             }
+            if (pass == 1 && b.keep_merge && ok) {  // the outward pass ends at the outermost cluster
+                float* o2 = b.rf_state2 + si * 20;
+                o2[0] = ref_y + s.p[0];
+                o2[1] = ref_z + s.p[1];
+#pragma unroll
+                for (int q = 2; q < 5; ++q) o2[q] = s.p[q];
+#pragma unroll
+                for (int q = 0; q < 15; ++q) o2[5 + q] = s.C[q];
+                b.rf_row2[si] = cur;
+            }
         }
         s.p[0] = ref_y + s.p[0];
         s.p[1] = ref_z + s.p[1];
@@ -1144,6 +1366,34 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
         b.rf_nacc[si] = nacc;
         b.rf_row[si] = cur;
         b.rf_ok[si] = (ok && nacc >= kc.n_min) ? 1 : 0;
+        if (b.o_res && ok && nacc >= kc.n_min) {
+            // track-model compression residuals of the clusters the last pass
+            // kept: the output parameters carried outward row by row from
+            // the output row by the same helix step
+            float q[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) q[c] = s.p[c];
+            int rc = cur;
+            bool okc = true;
+            for (int i = 0; i < n; ++i) {
+                if (!(b.sel_mask[off + i] & 4)) continue;
+                const int r = b.sel_row[off + i];
+                while (okc && rc < r) {
+                    if (!kf_step_state(q, sX[rc], sX[rc + 1], kc)) okc = false;
+                    else ++rc;
+                }
+                uint32_t packed = 0x80008000u;  // both escaped
+                if (okc) {
+                    const float2 c = b.sel_yz[off + i];
+                    const float qy = __builtin_rintf((c.x - q[0]) * b.res_scale);
+                    const float qz = __builtin_rintf((c.y - q[1]) * b.res_scale);
+                    const uint32_t uy = (qy >= -32767.0f && qy <= 32767.0f) ? (uint32_t)(uint16_t)(int16_t)qy : 0x8000u;
+                    const uint32_t uz = (qz >= -32767.0f && qz <= 32767.0f) ? (uint32_t)(uint16_t)(int16_t)qz : 0x8000u;
+                    packed = uy | (uz << 16);
+                }
+                b.sel_res[off + i] = packed;
+            }
+        }
     }
     if (stats) {
         stat_add(b.ctr, ST_RF_ROWS, st_rows);
@@ -1152,23 +1402,13 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b) {
 }
 
 // ------------------------------------------------------------------ finish
-// FP64 totals in a fixed order (one workgroup: strided per-lane sums, then a
-// fixed tree), and the closing entry of the output CSR.
-__global__ __launch_bounds__(1024) void k_finish(Bufs b) {
-    __shared__ double shc[1024];
-    __shared__ double shn[1024];
-    const unsigned long long tot = b.ctr->slot[SL_TRK][0];
-    const int64_t nt = (int64_t)(tot >> 32);
-    const int64_t nh = (int64_t)(tot & 0xFFFFFFFFull);
-    const int64_t n = nt < b.cap_tracks ? nt : b.cap_tracks;
-    double c = 0.0, d = 0.0;
-    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
-        c += (double)b.o_chi2[t];
-        d += (double)b.o_ndf[t];
-    }
-    shc[threadIdx.x] = c;
-    shn[threadIdx.x] = d;
-    __syncthreads();
+// FP64 totals in a fixed order: kFinishParts workgroups each sum a fixed
+// contiguous chunk of the tracks (strided per-lane sums, then a fixed tree),
+// one workgroup sums the parts by the same tree; it also writes the closing
+// entry of the output CSR.
+constexpr int kFinishParts = 256;
+
+__device__ __forceinline__ void tree_sum2(double* shc, double* shn) {
     for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             shc[threadIdx.x] += shc[threadIdx.x + s];
@@ -1176,6 +1416,43 @@ __global__ __launch_bounds__(1024) void k_finish(Bufs b) {
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_finish_part(Bufs b) {
+    __shared__ double shc[256];
+    __shared__ double shn[256];
+    const unsigned long long tot = b.ctr->slot[SL_TRK][0];
+    const int64_t nt = (int64_t)(tot >> 32);
+    const int64_t n = nt < b.cap_tracks ? nt : b.cap_tracks;
+    const int64_t chunk = (n + kFinishParts - 1) / kFinishParts;
+    const int64_t lo = blockIdx.x * chunk, hi = min(lo + chunk, n);
+    double c = 0.0, d = 0.0;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        c += (double)b.o_chi2[t];
+        d += (double)b.o_ndf[t];
+    }
+    shc[threadIdx.x] = c;
+    shn[threadIdx.x] = d;
+    __syncthreads();
+    tree_sum2(shc, shn);
+    if (threadIdx.x == 0) {
+        double* part = reinterpret_cast<double*>(b.scan_part);  // free once the scans are done
+        part[2 * blockIdx.x] = shc[0];
+        part[2 * blockIdx.x + 1] = shn[0];
+    }
+}
+
+__global__ __launch_bounds__(kFinishParts) void k_finish(Bufs b) {
+    __shared__ double shc[kFinishParts];
+    __shared__ double shn[kFinishParts];
+    const unsigned long long tot = b.ctr->slot[SL_TRK][0];
+    const int64_t nt = (int64_t)(tot >> 32);
+    const int64_t nh = (int64_t)(tot & 0xFFFFFFFFull);
+    const double* part = reinterpret_cast<const double*>(b.scan_part);
+    shc[threadIdx.x] = part[2 * threadIdx.x];
+    shn[threadIdx.x] = part[2 * threadIdx.x + 1];
+    __syncthreads();
+    tree_sum2(shc, shn);
     if (threadIdx.x == 0) {
         if (b.o_chi2_total) {
             b.o_chi2_total[0] = shc[0];
@@ -1333,11 +1610,13 @@ void enqueue_weights_clear(const Bufs& b, int64_t c0, int64_t c1, hipStream_t st
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(c1 - c0, 256, 4096)), dim3(256), 0, st, b.weight + c0, c1 - c0, 0u);
 }
 
-void enqueue_grid(const Bufs& b, int i0, int i1, hipStream_t st) {
+void enqueue_grid(const Bufs& b, int i0, int i1, int max_row, hipStream_t st) {
     const int64_t seg0 = (int64_t)i0 * b.n_rows, nseg = (int64_t)(i1 - i0) * b.n_rows;
     if (nseg <= 0) return;
     hipLaunchKernelGGL(k_grid<kSmallRow>, dim3((unsigned)nseg), dim3(256), 0, st, b, seg0);
-    hipLaunchKernelGGL(k_grid<kLargeRow>, dim3((unsigned)nseg), dim3(256), 0, st, b, seg0);
+    // the large-row variant only when a row may exceed the small one's capacity
+    if (max_row > kSmallRow)
+        hipLaunchKernelGGL(k_grid<kLargeRow>, dim3((unsigned)nseg), dim3(256), 0, st, b, seg0);
 }
 
 void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, int max_row, hipStream_t st) {
@@ -1361,8 +1640,13 @@ void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_
 }
 
 void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
-    hipLaunchKernelGGL(k_tracklet, dim3(grid_for(bound, L.block_tracklet, 16384)), dim3(L.block_tracklet), 0, st, b,
-                       L.xcd_remap);
+    const dim3 grid(grid_for(bound, L.block_tracklet, 16384));
+    if (L.inward_wgs > 0) {
+        hipLaunchKernelGGL(k_tracklet<1>, grid, dim3(L.block_tracklet), 0, st, b, L.xcd_remap);
+        hipLaunchKernelGGL(k_tracklet_in, dim3(L.inward_wgs), dim3(L.block_tracklet), 0, st, b);
+    } else {
+        hipLaunchKernelGGL(k_tracklet<0>, grid, dim3(L.block_tracklet), 0, st, b, L.xcd_remap);
+    }
 }
 
 void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
@@ -1373,7 +1657,8 @@ void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t s
 }
 
 void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(bound, L.block_refit, 16384)), dim3(L.block_refit), 0, st, b);
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(bound, L.block_refit, 16384)), dim3(L.block_refit), 0, st, b,
+                       L.sort_seeds);
 }
 
 void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
@@ -1383,7 +1668,9 @@ void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st
 }
 
 void enqueue_finish(const Bufs& b, hipStream_t st) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, b);
+    static_assert(2 * kFinishParts <= kScanBlocks, "finish parts live in the scan scratch");
+    hipLaunchKernelGGL(k_finish_part, dim3(kFinishParts), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishParts), 0, st, b);
 }
 
 void enqueue_check_csr(const Bufs& b, hipStream_t st) {

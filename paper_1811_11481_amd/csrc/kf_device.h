@@ -26,6 +26,9 @@ struct DevConsts {
     float alpha[18];                          // sector rotation angles
     float kB, vy, vz, smax, nsig, chi2_pick, chi2_rej, sinphi_max, cov_reset, q_max, u_max2;
     float c0[5];
+    double kB_f64;                            // -0.00299792458 * Bz in FP64 (vertex z only)
+    float chi2_merge, rot_c, rot_s;           // cross-sector merge cut; cos, sin of 20 degrees
+    int merge_max_gap;                        // rows between a continued segment's end and the next
 };
 
 // The scalar constants of the row steps, copied into registers once per
@@ -158,6 +161,29 @@ __device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, cons
     }
 #pragma unroll
     for (int q = 0; q < 15; ++q) s.C[q] = Cn[q];
+    return true;
+}
+
+// The state part of kf_propagate alone (the same expressions, so the same
+// binary32 results): the track model of the compression residuals.
+template <class KC>
+__device__ __forceinline__ bool kf_step_state(float* p, float x1, float x2, const KC& K) {
+    const float dx = x2 - x1;
+    const float s1 = p[2];
+    const float kq = K.kB * p[4];
+    const float s2 = __builtin_fmaf(kq, dx, s1);
+    if (!(__builtin_fabsf(s2) < K.sinphi_max)) return false;
+    const float c1 = __builtin_sqrtf(__builtin_fmaf(-s1, s1, 1.0f));
+    const float c2 = __builtin_sqrtf(__builtin_fmaf(-s2, s2, 1.0f));
+    const float tt = (s1 + s2) / (c1 + c2);
+    const float w = __builtin_fmaf(tt, tt, 1.0f);
+    const float lc = dx * __builtin_sqrtf(w);
+    const float u = (kq * lc) * 0.5f;
+    if (!(u * u <= K.u_max2)) return false;
+    const float arc = lc * asin_over_u(u);
+    p[0] = __builtin_fmaf(dx, tt, p[0]);
+    p[1] = __builtin_fmaf(p[3], arc, p[1]);
+    p[2] = s2;
     return true;
 }
 

@@ -20,6 +20,7 @@ OK, E_ARG, E_CAPACITY, E_DEVICE, E_OOM, E_INTERNAL = range(6)
 FLAG_STATS = 1
 FLAG_TIMING = 2
 FLAG_ADJOINT_F64 = 4
+FLAG_MERGE = 8
 MAP_SHAPE = (3, 16, 16, 32)  # (delta r, delta r*phi, delta z) x r x phi x z
 MAP_SIZE = 3 * 16 * 16 * 32
 MAX_ROW_CLUSTERS = 16384
@@ -29,7 +30,7 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_CAPACITY", 3: "E_DEVICE", 4: "E_OOM",
 EXPORTED = [
     "tpcca_default_params", "tpcca_default_tuning", "tpcca_create", "tpcca_destroy", "tpcca_last_error",
     "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_track", "tpcca_track_batched", "tpcca_track_async",
-    "tpcca_track_async_noalloc", "tpcca_autotune",
+    "tpcca_track_async_noalloc", "tpcca_merge", "tpcca_autotune",
     "tpcca_export_sizes", "tpcca_export_grid", "tpcca_export_links", "tpcca_export_tracklets",
     "tpcca_export_selected", "tpcca_get_stats", "tpcca_get_stage_times", "tpcca_fp32_selfcheck",
     "tpcca_refit_fwd", "tpcca_refit_bwd",
@@ -65,6 +66,8 @@ class Params(ctypes.Structure):
         ("n_min", ctypes.c_int32),
         ("max_miss", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("chi2_merge", ctypes.c_double),
+        ("merge_max_gap", ctypes.c_int32),
     ]
 
 
@@ -78,6 +81,8 @@ class Tuning(ctypes.Structure):
         ("sort_seeds", ctypes.c_int32),
         ("tape_mb", ctypes.c_int32),
         ("xcd_remap", ctypes.c_int32),
+        ("ckpt", ctypes.c_int32),
+        ("inward_wgs", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -109,6 +114,9 @@ class TracksC(ctypes.Structure):
         ("hit_start", ctypes.c_void_p),
         ("hit_id", ctypes.c_void_p),
         ("chi2_total", ctypes.c_void_p),
+        ("z0", ctypes.c_void_p),
+        ("residuals", ctypes.c_void_p),
+        ("residual_step_log2", ctypes.c_int32),
         ("n_tracks", ctypes.c_int64),
         ("n_hits", ctypes.c_int64),
     ]
@@ -176,6 +184,8 @@ def load():
         for fn in ("tpcca_track_async", "tpcca_track_async_noalloc"):
             getattr(L, fn).restype = st
             getattr(L, fn).argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(TracksC), vp, vp, vp]
+        L.tpcca_merge.restype = st
+        L.tpcca_merge.argtypes = [vp, vp, ctypes.POINTER(TracksC), vp, vp, vp]
         L.tpcca_autotune.restype = st
         L.tpcca_autotune.argtypes = [vp, ctypes.POINTER(Clusters), i32, ctypes.POINTER(Tuning), vp]
         L.tpcca_export_sizes.restype = st
@@ -290,15 +300,27 @@ class Tracks:
         self.hit_start = torch.empty(ct + 1, dtype=torch.int64, device=device)
         self.hit_id = torch.empty(max(self.cap_hits, 1), dtype=torch.int32, device=device)
         self.chi2_total = torch.empty(2, dtype=torch.float64, device=device)
+        self.z0 = torch.empty(ct, dtype=torch.float32, device=device)
+        self.residuals = None  # int16 [cap_hits * 2] when compression residuals are wanted
+        self.residual_step_log2 = -7
         self.n_tracks = 0
         self.n_hits = 0
 
     def c_struct(self) -> TracksC:
         t = TracksC()
         t.cap_tracks, t.cap_hits = self.cap_tracks, self.cap_hits
-        for k in ("inst", "x_ref", "alpha", "param", "cov", "chi2", "ndf", "hit_start", "hit_id", "chi2_total"):
+        for k in ("inst", "x_ref", "alpha", "param", "cov", "chi2", "ndf", "hit_start", "hit_id", "chi2_total", "z0"):
             setattr(t, k, getattr(self, k).data_ptr())
+        t.residuals = self.residuals.data_ptr() if self.residuals is not None else None
+        t.residual_step_log2 = self.residual_step_log2
         return t
+
+    def want_residuals(self, step_log2: int = -7):
+        """Ask the track calls for track-model compression residuals (step 2^k cm)."""
+        torch = _torch()
+        self.residuals = torch.empty(max(self.cap_hits, 1) * 2, dtype=torch.int16, device=self.hit_id.device)
+        self.residual_step_log2 = int(step_log2)
+        return self
 
     def to_numpy(self) -> dict:
         n, h = self.n_tracks, self.n_hits
@@ -308,6 +330,9 @@ class Tracks:
             "cov": self.cov[:n * 15].cpu().numpy().reshape(n, 15), "chi2": self.chi2[:n].cpu().numpy(),
             "ndf": self.ndf[:n].cpu().numpy(), "hit_start": self.hit_start[:n + 1].cpu().numpy(),
             "hit_id": self.hit_id[:h].cpu().numpy(), "chi2_total": self.chi2_total.cpu().numpy(),
+            "z0": self.z0[:n].cpu().numpy(),
+            **({"residuals": self.residuals[:2 * h].cpu().numpy().reshape(h, 2)} if self.residuals is not None
+               else {}),
         }
 
 
@@ -378,6 +403,22 @@ class Tracker:
         self._check(self.lib.tpcca_track_async_noalloc(self.h, ctypes.byref(cin), ctypes.byref(cout), _ptr(counts),
                                                        _ptr(status), _stream(stream)))
         return out
+
+    def merge(self, inst_event, stream=None):
+        """Cross-sector merge of the last synchronous track call's tracks (the
+        context needs FLAG_MERGE). inst_event: int32 device tensor [n_inst].
+        Returns (merged Tracks, nseg per merged track, seg_next per sector track)."""
+        torch = _torch()
+        sz = self.sizes()
+        nt, nh = sz["n_tracks"], sz["n_track_hits"]
+        out = Tracks(max(nt, 1), max(nh, 1), device=inst_event.device)
+        nseg = torch.empty(max(nt, 1), dtype=torch.int32, device=inst_event.device)
+        nxt = torch.empty(max(nt, 1), dtype=torch.int32, device=inst_event.device)
+        c = out.c_struct()
+        self._check(self.lib.tpcca_merge(self.h, _ptr(inst_event), ctypes.byref(c), _ptr(nseg), _ptr(nxt),
+                                         _stream(stream)))
+        out.n_tracks, out.n_hits = int(c.n_tracks), int(c.n_hits)
+        return out, nseg[:out.n_tracks], nxt[:nt]
 
     def autotune(self, clusters: DeviceClusters, repeats: int = 3, stream=None) -> Tuning:
         t = Tuning()

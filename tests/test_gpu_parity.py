@@ -123,7 +123,8 @@ def test_batched_graph_follows_new_output_buffers(c1):
 
 
 @pytest.mark.parametrize("tune", [dict(hits_per_bin=2), dict(hits_per_bin=3, block_tracklet=64, xcd_remap=0),
-                                  dict(hits_per_bin=8, block_links=64, block_refit=256, block_scan=512)])
+                                  dict(hits_per_bin=8, block_links=64, block_refit=256, block_scan=512, sort_seeds=1),
+                                  dict(inward_wgs=1024), dict(inward_wgs=3, block_tracklet=64, xcd_remap=0)])
 def test_results_independent_of_tuning(c1, c1_oracle, tune):
     from paper_1811_11481_amd import default_tuning
     log("C1 tuning %s" % tune)
@@ -138,6 +139,16 @@ def test_c2_full_event_bit_exact(c2, c2_oracle):
     log("C2 plain (per-instance launches)")
     p = run_gpu(c2, batched=False, exports=False)
     assert tracks_equal(g, p)
+
+
+def test_c2_persistent_inward_pass_bit_exact(c2, c2_oracle):
+    # the inward pass in its own persistent kernel: same stages bit for bit,
+    # with a full grid and with a grid of a few waves that drains all eight queues
+    from paper_1811_11481_amd import default_tuning
+    for wgs in (1024, 5):
+        log("C2 batched, inward pass in %d persistent workgroups" % wgs)
+        g = run_gpu(c2, tuning=default_tuning(inward_wgs=wgs))
+        compare_with_oracle(g, c2_oracle)
 
 
 def test_c2_parameters_against_fp64_replay(c2, c2_oracle):
@@ -235,3 +246,15 @@ def test_c4_uneven_instances_sampled_parity():
     log("C4 plain vs batched")
     p = run_gpu(cs, batched=False, exports=False)
     assert tracks_equal(g, p)
+
+
+def test_vertex_z_of_every_track(c2):
+    """Each output track's closest-approach z (FP64 on the GPU from its binary32
+    final state) against the oracle's FP64 formula on the same state."""
+    log("C2 vertex z")
+    g = run_gpu(c2, exports=False)
+    T = g["tracks"]
+    ref = oracle.vertex_z(T["x_ref"].astype(np.float64), T["param"].astype(np.float64))
+    assert np.isfinite(T["z0"]).all()
+    err = np.abs(T["z0"].astype(np.float64) - ref) / np.maximum(np.abs(ref), 1.0)
+    assert err.max() <= 1e-6, err.max()
