@@ -78,6 +78,14 @@ typedef struct {
     uint32_t flags;               /* TPCCA_FLAG_* */
     double chi2_merge;            /* cross-sector merge: max chi2 (five parameters) of a segment pair, 25 */
     int32_t merge_max_gap;        /* cross-sector merge: max rows between a segment's end and the next, 24 */
+    /* Native cluster coordinates (tpcca_track_native; Sections 4 and 6: pad, row and time). */
+    float pad_width[256];         /* pad pitch along local y per row [cm]; default 0.416 (rows 0-62), 0.42
+                                     (63-126), 0.46 (127-151) */
+    float pad_center[256];        /* pad coordinate of local y = 0 per row; default (n_pads - 1) / 2 with
+                                     n_pads = 2 ceil(row_x tan(10 deg) / pad_width), the pads that cover the
+                                     row's width */
+    double z_per_bin;             /* drift length per time bin [cm], 0.516 (2.58 cm/us drift, 200 ns bins) */
+    double z_readout;             /* |z| of the readout planes [cm], 250 */
 } tpcca_params;
 
 #define TPCCA_FLAG_STATS 1u       /* count work items (rows visited, candidates) for the byte model */
@@ -202,6 +210,41 @@ tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca
  * synchronising forms. Output buffers identical to tpcca_track_batched. */
 tpcca_status tpcca_track_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,
                                int32_t* status, void* hip_stream);
+
+/* Clusters in native coordinates (Sections 4 and 6: the tracking reads pad,
+ * row and time and transforms to space on the GPU). Device pointers,
+ * caller-owned; the same CSR over (instance, row) as tpcca_clusters. */
+typedef struct {
+    int32_t n_inst;             /* number of sector instances (>= 0) */
+    const int32_t* inst_sector; /* [n_inst] geometric sector 0..35 (0..17: A side, z > 0; 18..35: C side) */
+    const int64_t* row_start;   /* [n_inst * n_rows + 1] CSR over (instance, row), as in tpcca_clusters */
+    const float* pad;           /* [n_clusters] pad coordinate along the row (pad centres are integers) */
+    const float* time;          /* [n_clusters] time since the start of the time frame [time bins] */
+    int64_t n_clusters;         /* host value */
+} tpcca_native_clusters;
+
+/* The native-to-local transform, in binary32 with the operations in this
+ * order: y = (pad - pad_center[row]) * pad_width[row];
+ * z = side * (z_readout - z_per_bin * time), side = +1 on the A side, -1 on
+ * the C side. The time is scaled linearly to z as if the chamber were
+ * arbitrarily long (Section 4, the first step for continuous readout): the
+ * clusters of a collision at time t_c appear shifted by -side * z_per_bin *
+ * t_c, which the vertex z (tracks' z0) recovers. Writes y, z (device
+ * [n_clusters] binary32, caller-owned). Errors: TPCCA_E_ARG (null pointers,
+ * sizes; a malformed CSR leaves y, z of the clusters outside every row
+ * unwritten), TPCCA_E_DEVICE. Does not synchronise. */
+tpcca_status tpcca_native_to_local(tpcca_ctx* ctx, const tpcca_native_clusters* in, float* y, float* z,
+                                   void* hip_stream);
+
+/* Batched form of the track call on native clusters: no transformed copy of
+ * the input is made; the grid kernel transforms each cluster as it reads it
+ * (tpcca_native_to_local's arithmetic) and every later stage works on the
+ * grid. Output bit for bit that of tpcca_track_batched on the clusters
+ * tpcca_native_to_local gives, with z in the linear time scale (z0 is then
+ * the vertex z in that scale). tpcca_merge may follow it as after the other
+ * synchronous forms. Same errors and synchronisations as tpcca_track_batched. */
+tpcca_status tpcca_track_native(tpcca_ctx* ctx, const tpcca_native_clusters* in, tpcca_tracks* out,
+                                void* hip_stream);
 
 /* Cross-sector merge (the second phase of Section 2: the track segments found
  * in the individual sectors are merged and fitted as one track; Section 4: the

@@ -110,6 +110,8 @@ def lib():
         L.orc_track_decode.argtypes = [ctypes.POINTER(Params), vp, i32, i32, vp, vp, i32, vp, vp]
         L.orc_vertex_z.restype = dbl
         L.orc_vertex_z.argtypes = [ctypes.POINTER(Params), dbl, vp]
+        L.orc_native_to_local.restype = None
+        L.orc_native_to_local.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -504,3 +506,37 @@ def track_decode(params5, rows, q, step_log2=-7, params=None, row0=None):
                            int(step_log2), ys.ctypes.data, zs.ctypes.data)
     return ys[:len(rows)], zs[:len(rows)]
 
+
+# ---------------------------------------------------------------- native coordinates
+def native_geometry(row_x=None) -> dict:
+    """Pad geometry and drift constants of native cluster coordinates (the
+    readings for Sections 4 and 6): pad pitch 0.416 cm on rows 0-62, 0.42 cm on
+    63-126 and 0.46 cm on 127-151 (the four readout regions of 63, 34, 30 and 25
+    rows); each row has the even number of pads that covers its full width
+    2 x tan(10 deg) at its plane, and pad coordinate (n_pads - 1) / 2 is local
+    y = 0; drift 2.58 cm/us sampled every 200 ns (0.516 cm per time bin);
+    readout planes at |z| = 250 cm. Values as binary32, as the tracker uses them."""
+    import math
+    if row_x is None:
+        row_x = [float(np.float32(85.0 + i * 162.0 / 151.0)) for i in range(152)]
+    t10 = math.tan(10.0 * math.pi / 180.0)
+    width = np.array([0.416 if i < 63 else 0.42 if i < 127 else 0.46 for i in range(len(row_x))])
+    n_pads = np.array([2.0 * math.ceil(float(x) * t10 / w) for x, w in zip(row_x, width)])
+    return dict(pad_width=width.astype(np.float32), pad_center=((n_pads - 1.0) * 0.5).astype(np.float32),
+                n_pads=n_pads.astype(np.int64), z_per_bin=np.float32(2.58 * 0.2), z_readout=np.float32(250.0))
+
+
+def native_to_local(n_rows, inst_sector, row_start, pad, time, geo=None):
+    """Local (y, z) binary32 of clusters given in native (pad, time) (orc_native_to_local)."""
+    geo = geo or native_geometry()
+    sec = np.ascontiguousarray(inst_sector, np.int32)
+    rs = np.ascontiguousarray(row_start, np.int64)
+    pad = np.ascontiguousarray(pad, np.float32)
+    time = np.ascontiguousarray(time, np.float32)
+    pw = np.ascontiguousarray(geo["pad_width"], np.float32)
+    pc = np.ascontiguousarray(geo["pad_center"], np.float32)
+    y = np.zeros(len(pad), np.float32)
+    z = np.zeros(len(pad), np.float32)
+    lib().orc_native_to_local(int(n_rows), len(sec), _ptr(sec), _ptr(rs), _ptr(pw), _ptr(pc),
+                              float(geo["z_per_bin"]), float(geo["z_readout"]), _ptr(pad), _ptr(time), _ptr(y), _ptr(z))
+    return y, z

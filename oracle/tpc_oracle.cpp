@@ -1631,6 +1631,30 @@ void orc_refit_frozen_f64(const orc_params* p, int64_t n_tracks, const double* s
 // 1 + B c > 0 (straight line: s = -A), and z0 = z + tan(lambda) s.
 extern "C" {
 
+// Native cluster coordinates to local ones (Sections 4 and 6: the tracker is
+// to take pad, row and time and transform them to space itself). In binary32,
+// one rounding per operation: y = (pad - pad_center[row]) * pad_width[row];
+// z = side * (z_readout - z_per_bin * time) with side +1 for sectors 0..17
+// (A side) and -1 for 18..35 (C side). The time is scaled linearly to z as
+// for an arbitrarily long chamber (Section 4, continuous readout): a
+// collision at time t shifts its clusters by -side * z_per_bin * t.
+void orc_native_to_local(int32_t n_rows, int32_t n_inst, const int32_t* inst_sector, const int64_t* row_start,
+                         const float* pad_width, const float* pad_center, float z_per_bin, float z_readout,
+                         const float* pad, const float* time, float* y, float* z) {
+    for (int32_t i = 0; i < n_inst; ++i) {
+        const float side = inst_sector[i] < 18 ? 1.0f : -1.0f;
+        for (int32_t r = 0; r < n_rows; ++r) {
+            const int64_t seg = (int64_t)i * n_rows + r;
+            for (int64_t c = row_start[seg]; c < row_start[seg + 1]; ++c) {
+                const float u = pad[c] - pad_center[r];
+                y[c] = u * pad_width[r];
+                const float drift = z_per_bin * time[c];
+                z[c] = side * (z_readout - drift);
+            }
+        }
+    }
+}
+
 double orc_vertex_z(const orc_params* p, double x, const double* state5) {
     const double kB = -0.00299792458 * p->bz;
     const double y = state5[0], z = state5[1], sp = state5[2], tl = state5[3], q = state5[4];

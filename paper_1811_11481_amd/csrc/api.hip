@@ -133,6 +133,12 @@ void build_consts(const tpcca_params& p, DevConsts& K) {
     K.kB_f64 = -0.00299792458 * p.bz;
     K.chi2_merge = (float)p.chi2_merge;
     K.merge_max_gap = p.merge_max_gap;
+    for (int i = 0; i < p.n_rows; ++i) {
+        K.pad_w[i] = p.pad_width[i];
+        K.pad_c[i] = p.pad_center[i];
+    }
+    K.z_per_bin = (float)p.z_per_bin;
+    K.z_readout = (float)p.z_readout;
     K.rot_c = (float)std::cos(20.0 * kPi / 180.0);
     K.rot_s = (float)std::sin(20.0 * kPi / 180.0);
     const float sy = (float)p.sigma_y, sz = (float)p.sigma_z;
@@ -161,6 +167,11 @@ tpcca_status check_params(tpcca_ctx* ctx, const tpcca_params& p) {
     if (!(p.u_max > 0 && p.u_max <= 0.5)) return fail(ctx, TPCCA_E_ARG, "u_max must be in (0, 0.5]");
     if (!(p.chi2_merge > 0)) return fail(ctx, TPCCA_E_ARG, "chi2_merge must be positive");
     if (p.merge_max_gap < 0 || p.merge_max_gap > 255) return fail(ctx, TPCCA_E_ARG, "merge_max_gap must be in [0, 255]");
+    for (int i = 0; i < p.n_rows; ++i)
+        if (!(p.pad_width[i] > 0.0f && p.pad_width[i] < 1e30f) || !(std::fabs(p.pad_center[i]) < 1e30f))
+            return fail(ctx, TPCCA_E_ARG, "pad_width must be positive and pad_center finite on every row");
+    if (!(p.z_per_bin > 0 && p.z_per_bin < 1e30) || !(std::fabs(p.z_readout) < 1e30))
+        return fail(ctx, TPCCA_E_ARG, "z_per_bin must be positive and z_readout finite");
     return TPCCA_OK;
 }
 
@@ -336,7 +347,7 @@ tpcca_status load_rowstart(tpcca_ctx* ctx, const tpcca_clusters* in, hipStream_t
 }
 
 Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out, void* at = nullptr,
-               int64_t N = -1, int64_t nseg = -1, int64_t ninst = -1) {
+               int64_t N = -1, int64_t nseg = -1, int64_t ninst = -1, int native = 0) {
     Bufs b{};
     size_t total;
     if (at) carve(ctx, b, N, nseg, ninst, true, &total, at);
@@ -350,6 +361,7 @@ Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out
     b.row_start = in->row_start;
     b.y = in->y;
     b.z = in->z;
+    b.native = native;
     b.hits_per_bin = ctx->tuning.hits_per_bin;
     b.cap_tracks = out->cap_tracks;
     b.cap_hits = out->cap_hits;
@@ -423,7 +435,7 @@ tpcca_status finish_call(tpcca_ctx* ctx, const Bufs& b, tpcca_tracks* out, int64
 // Everything a captured launch sequence depends on: every device pointer its
 // kernels take, the stream, the sizes and the tuning.
 GraphKey graph_key(const tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out, hipStream_t st,
-                   const int64_t* counts, const int32_t* status, int mrow) {
+                   const int64_t* counts, const int32_t* status, int mrow, int native = 0) {
     GraphKey key{};
     const void* ps[21] = {in->inst_sector, in->row_start, in->y,        in->z,        out->inst,
                           out->x_ref,       out->alpha,     out->param,   out->cov,     out->chi2,
@@ -436,7 +448,7 @@ GraphKey graph_key(const tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_t
                                ctx->tuning.sort_seeds,
                            ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
                            ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
-                           counts != nullptr ? 1 : 0, out->residual_step_log2};
+                           (counts != nullptr ? 1 : 0) + 2 * native, out->residual_step_log2};
     std::memcpy(key.v, vs, sizeof(vs));
     return key;
 }
@@ -480,7 +492,8 @@ void enqueue_async_body(const Bufs& b, const Launch& L, const tpcca_clusters* in
     enqueue_async_status(b, counts, status, st);
 }
 
-tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* stream, bool batched) {
+tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* stream, bool batched,
+                 int native = 0) {
     tpcca_status s = check_io(ctx, in, out);
     if (s != TPCCA_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -491,7 +504,7 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
     if (s != TPCCA_OK) return s;
     s = ensure_arena(ctx, std::max<int64_t>(N, 1), std::max<int64_t>(nseg, 1), std::max<int64_t>(in->n_inst, 1));
     if (s != TPCCA_OK) return s;
-    const Bufs b = make_bufs(ctx, in, out);
+    const Bufs b = make_bufs(ctx, in, out, nullptr, -1, -1, -1, native);
     const Launch L = make_launch(ctx->tuning);
     const bool timing = (ctx->params.flags & TPCCA_FLAG_TIMING) != 0;
     if (timing && !ctx->events) {
@@ -531,7 +544,7 @@ tpcca_status run(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, vo
         st = ctx->own_stream;
     }
     const int mrow = max_row(0, in->n_inst);  // sizes the neighbour kernel's LDS staging
-    const GraphKey key = graph_key(ctx, in, out, st, nullptr, nullptr, mrow);
+    const GraphKey key = graph_key(ctx, in, out, st, nullptr, nullptr, mrow, native);
     s = replay_graph(ctx, key, st, [&] {
         enqueue_reset(b, st);
         enqueue_range(b, L, 0, in->n_inst, 0, N, ctx->params.n_min, mrow, st, nullptr);
@@ -728,6 +741,18 @@ tpcca_status tpcca_default_params(tpcca_params* p) {
     p->flags = 0;
     p->chi2_merge = 25.0;
     p->merge_max_gap = 24;
+    // pad widths of the four readout regions (63, 34, 30 and 25 rows), pads
+    // covering each row's full width (2 x tan(10 deg) at the plane)
+    const double tan10 = std::tan(10.0 * kPi / 180.0);
+    for (int i = 0; i < 256; ++i) {
+        const double w = i < 63 ? 0.416 : i < 127 ? 0.42 : 0.46;
+        const double x = i < p->n_rows ? (double)p->row_x[i] : 0.0;
+        const double np = 2.0 * std::ceil(x * tan10 / w);
+        p->pad_width[i] = (float)w;
+        p->pad_center[i] = (float)((np - 1.0) * 0.5);
+    }
+    p->z_per_bin = 2.58 * 0.2;
+    p->z_readout = 250.0;
     return TPCCA_OK;
 }
 
@@ -839,6 +864,54 @@ tpcca_status tpcca_track(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks*
 tpcca_status tpcca_track_batched(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, void* hip_stream) {
     if (!ctx) return TPCCA_E_ARG;
     return run(ctx, in, out, hip_stream, true);
+}
+
+// The native clusters seen through the local-coordinate struct: pad and time
+// take the places of y and z (the kernels know them by Bufs::native).
+tpcca_clusters native_view(const tpcca_native_clusters* in) {
+    tpcca_clusters c{};
+    c.n_inst = in->n_inst;
+    c.inst_sector = in->inst_sector;
+    c.row_start = in->row_start;
+    c.y = in->pad;
+    c.z = in->time;
+    c.n_clusters = in->n_clusters;
+    return c;
+}
+
+tpcca_status tpcca_track_native(tpcca_ctx* ctx, const tpcca_native_clusters* in, tpcca_tracks* out,
+                                void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    if (!in) return fail(ctx, TPCCA_E_ARG, "null clusters");
+    const tpcca_clusters c = native_view(in);
+    return run(ctx, &c, out, hip_stream, true, 1);
+}
+
+tpcca_status tpcca_native_to_local(tpcca_ctx* ctx, const tpcca_native_clusters* in, float* y, float* z,
+                                   void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    if (!in) return fail(ctx, TPCCA_E_ARG, "null clusters");
+    if (in->n_inst < 0 || in->n_clusters < 0) return fail(ctx, TPCCA_E_ARG, "negative sizes");
+    if (in->n_clusters >= (int64_t)1 << 31) return fail(ctx, TPCCA_E_ARG, "more than 2^31-1 clusters");
+    if (in->n_inst > 0 && (!in->row_start || !in->inst_sector))
+        return fail(ctx, TPCCA_E_ARG, "null row_start or inst_sector");
+    if (in->n_clusters > 0 && (!in->pad || !in->time || !y || !z))
+        return fail(ctx, TPCCA_E_ARG, "null cluster coordinates");
+    if (in->n_inst == 0) return TPCCA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    Bufs b{};
+    b.K = ctx->dK;
+    b.n_rows = ctx->params.n_rows;
+    b.n_inst = in->n_inst;
+    b.n_clusters = in->n_clusters;
+    b.inst_sector = in->inst_sector;
+    b.row_start = in->row_start;
+    b.y = in->pad;
+    b.z = in->time;
+    b.native = 1;
+    enqueue_native_local(b, (int64_t)in->n_inst * ctx->params.n_rows, y, z, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    return TPCCA_OK;
 }
 
 tpcca_status tpcca_track_async(tpcca_ctx* ctx, const tpcca_clusters* in, tpcca_tracks* out, int64_t* counts,

@@ -54,8 +54,9 @@ struct Bufs {
     int64_t n_clusters;
     const int32_t* inst_sector;
     const int64_t* row_start;
-    const float* y;
-    const float* z;
+    const float* y;      // local y, or the pad coordinate when native
+    const float* z;      // local z, or the time when native
+    int native;          // 1: (y, z) hold native (pad, time), transformed where the grid reads them
     // grid
     float2* yz;        // (y, z) at grid position
     int32_t* sid;      // cluster id at grid position
@@ -189,6 +190,9 @@ void enqueue_finish(const Bufs& b, hipStream_t st);
 void enqueue_check_csr(const Bufs& b, hipStream_t st);
 // counts (n_tracks, n_hits) and a tpcca_status code left on the device
 void enqueue_async_status(const Bufs& b, int64_t* counts, int32_t* status, hipStream_t st);
+
+// native (pad, time) -> local (y, z) of every cluster (b.native must be 1)
+void enqueue_native_local(const Bufs& b, int64_t nseg, float* y, float* z, hipStream_t st);
 
 // exports (cluster-id space)
 void enqueue_export_grid(const Bufs& b, int32_t* sorted_id, int32_t* bin_start, int32_t* ny, int32_t* nz,

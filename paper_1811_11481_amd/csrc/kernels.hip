@@ -90,6 +90,51 @@ __device__ __forceinline__ GridView grid_view(const Bufs& b, int64_t seg, const 
 
 __device__ __forceinline__ GridView grid_view(const Bufs& b, int64_t seg) { return grid_view(b, seg, load_hdr(b, seg)); }
 
+// ------------------------------------------------------------------ native coordinates
+// Per-row constants of the native-to-local transform (side: +1 on the A
+// side, sectors 0..17, -1 on the C side).
+struct NativeRow {
+    float pc, pw, zr, zpb, side;
+    int on;
+};
+
+__device__ __forceinline__ NativeRow native_row(const Bufs& b, int64_t seg) {
+    NativeRow t{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, b.native};
+    if (t.on) {
+        const DevConsts& K = *b.K;
+        const int nr = K.n_rows;
+        const int row = (int)(seg % nr);
+        t.pc = K.pad_c[row];
+        t.pw = K.pad_w[row];
+        t.zr = K.z_readout;
+        t.zpb = K.z_per_bin;
+        t.side = b.inst_sector[seg / nr] < 18 ? 1.0f : -1.0f;
+    }
+    return t;
+}
+
+// Local (y, z) of cluster i: the input as it is, or native (pad, time)
+// transformed (pad offset times pitch; time scaled linearly to the drift
+// length from the readout plane).
+__device__ __forceinline__ float2 cluster_yz(const Bufs& b, const NativeRow& t, int64_t i) {
+    const float u = b.y[i], v = b.z[i];
+    if (!t.on) return make_float2(u, v);
+    return make_float2((u - t.pc) * t.pw, t.side * (t.zr - t.zpb * v));
+}
+
+__global__ __launch_bounds__(256) void k_native_local(Bufs b, int64_t nseg, float* y, float* z) {
+    for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const int64_t a = b.row_start[seg], e = b.row_start[seg + 1];
+        if (a < 0 || e < a || e > b.n_clusters) continue;  // malformed CSR: nothing written
+        const NativeRow t = native_row(b, seg);
+        for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
+            const float2 c = cluster_yz(b, t, i);
+            y[i] = c.x;
+            z[i] = c.y;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ grid
 // One workgroup per (instance, row): exact ranges, bin layout, stable sort of
 // (bin, cluster index) keys by a bitonic network in LDS, gather of the sorted
@@ -118,11 +163,13 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
     if (bad && tid == 0) raise_err(b.ctr, ERR_ARG);
     const int n = (int)n64;
     const int nr = b.K->n_rows;
+    const NativeRow nat = native_row(b, seg);
     // ranges
     float ymn = __builtin_inff(), ymx = -__builtin_inff(), zmn = __builtin_inff(), zmx = -__builtin_inff();
     bool nonfinite = false;
     for (int i = tid; i < n; i += nt) {
-        const float yv = b.y[a + i], zv = b.z[a + i];
+        const float2 c = cluster_yz(b, nat, a + i);
+        const float yv = c.x, zv = c.y;
         nonfinite |= !(__builtin_fabsf(yv) <= 3.0e38f) || !(__builtin_fabsf(zv) <= 3.0e38f);
         ymn = fminf(ymn, yv); ymx = fmaxf(ymx, yv);
         zmn = fminf(zmn, zv); zmx = fmaxf(zmx, zv);
@@ -181,8 +228,9 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
     while (P < n) P <<= 1;
     for (int i = tid; i < P; i += nt) {
         if (i < n) {
-            const int by = bin_of(b.y[a + i], ymin, iy, ny);
-            const int bz = bin_of(b.z[a + i], zmin, iz, nz);
+            const float2 c = cluster_yz(b, nat, a + i);
+            const int by = bin_of(c.x, ymin, iy, ny);
+            const int bz = bin_of(c.y, zmin, iz, nz);
             key[i] = ((uint32_t)(bz * ny + by) << kKeyShift) | (uint32_t)i;
         } else {
             key[i] = 0xFFFFFFFFu;
@@ -237,7 +285,7 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
         const uint32_t kk = key[p];
         const int i = (int)(kk & ((1u << kKeyShift) - 1));
         const int bin = (int)(kk >> kKeyShift);
-        b.yz[a + p] = make_float2(b.y[a + i], b.z[a + i]);
+        b.yz[a + p] = cluster_yz(b, nat, a + i);
         b.sid[a + p] = (int32_t)(a + i);
         b.pos_of[a + i] = (int32_t)(a + p);
         const int prev = (p == 0) ? -1 : (int)(key[p - 1] >> kKeyShift);
@@ -1127,7 +1175,11 @@ __global__ __launch_bounds__(256) void k_tracklet_in(Bufs b) {
     // wave-uniform queue cursor
     int q = (int)(blockIdx.x & 7), tried = 0;
     // lane state: 0 = needs a tracklet, 1 = down to the last row, 2 = inward
-    // picking, 3 = the queues are empty
+    // picking, 3 = the queues are empty, 4 = ended, its picks and weights not
+    // yet written. Ended lanes wait until kRefill lanes of the wave are idle:
+    // the stores, the weight atomics and the loads of the next tracklets then
+    // run once for all of them instead of once per lane.
+    constexpr int kRefill = 16;
     int phase = 0;
     int64_t j = 0, seg0 = 0;
     int cur = 0, last = 0, r = 0, miss = 0, nh = 0, tid = 0;
@@ -1135,52 +1187,60 @@ __global__ __launch_bounds__(256) void k_tracklet_in(Bufs b) {
     PickRing pr{0, 0, 0, 0, 0u};
     SegHdr hn3{};
     while (true) {
-        // lanes without a tracklet take the next ones of the current queue;
-        // a queue found empty moves the whole wave to the next
-        unsigned long long need = __ballot(phase == 0);
-        while (need != 0ull) {
-            if (tried == 8) {
-                if (phase == 0) phase = 3;
-                break;
+        const unsigned long long act = __ballot(phase == 1 || phase == 2);
+        if (act == 0ull || __popcll(__ballot(phase == 0 || phase == 4)) >= kRefill) {
+            if (phase == 4) {
+                tracklet_finish(b, j, nr, nh, tid, vec, pr, kc.n_min);
+                st_picks += nh;
+                phase = 0;
             }
-            const int64_t qlo = (int64_t)q * cnt / 8, qhi = (int64_t)(q + 1) * cnt / 8;
-            const int leader = __ffsll((long long)need) - 1;
-            unsigned int got = 0u;
-            if (lane == leader) got = atomicAdd(&b.ctr->tlq[q], (unsigned int)__popcll(need));
-            got = __shfl(got, leader, 64);
-            if (qlo + (int64_t)got + __popcll(need) > qhi) {  // the queue ran out while taking
-                q = (q + 1) & 7;
-                ++tried;
-            }
-            if (phase == 0) {
-                const int64_t k = qlo + (int64_t)got + __popcll(need & below);
-                if (k < qhi) {
-                    j = base + k;
-                    cur = b.tl_row[j];
-                    if (cur >= 0) {  // a tracklet whose outward following ended well
-                        const float* st = b.tl_state + j * 20;
+            // idle lanes take the next tracklets of the current queue; a
+            // queue found empty moves the whole wave to the next
+            unsigned long long need = __ballot(phase == 0);
+            while (need != 0ull) {
+                if (tried == 8) {
+                    if (phase == 0) phase = 3;
+                    break;
+                }
+                const int64_t qlo = (int64_t)q * cnt / 8, qhi = (int64_t)(q + 1) * cnt / 8;
+                const int leader = __ffsll((long long)need) - 1;
+                unsigned int got = 0u;
+                if (lane == leader) got = atomicAdd(&b.ctr->tlq[q], (unsigned int)__popcll(need));
+                got = __shfl(got, leader, 64);
+                if (qlo + (int64_t)got + __popcll(need) > qhi) {  // the queue ran out while taking
+                    q = (q + 1) & 7;
+                    ++tried;
+                }
+                if (phase == 0) {
+                    const int64_t k = qlo + (int64_t)got + __popcll(need & below);
+                    if (k < qhi) {
+                        j = base + k;
+                        cur = b.tl_row[j];
+                        if (cur >= 0) {  // a tracklet whose outward following ended well
+                            const float* st = b.tl_state + j * 20;
 #pragma unroll
-                        for (int i = 0; i < 5; ++i) s.p[i] = st[i];
+                            for (int i = 0; i < 5; ++i) s.p[i] = st[i];
 #pragma unroll
-                        for (int i = 0; i < 15; ++i) s.C[i] = st[5 + i];
-                        kf_reset(s, kc);
-                        last = b.tl_last[j];
-                        tid = b.tl_tid[j];
-                        seg0 = (int64_t)b.start_inst[j] * nr;
-                        r = cur - 1 >= last ? cur - 1 : last;
-                        phase = cur - 1 >= last ? 1 : 2;
-                        miss = 0;
-                        nh = 0;
-                        hn3 = load_hdr(b, seg0 + last);
+                            for (int i = 0; i < 15; ++i) s.C[i] = st[5 + i];
+                            kf_reset(s, kc);
+                            last = b.tl_last[j];
+                            tid = b.tl_tid[j];
+                            seg0 = (int64_t)b.start_inst[j] * nr;
+                            r = cur - 1 >= last ? cur - 1 : last;
+                            phase = cur - 1 >= last ? 1 : 2;
+                            miss = 0;
+                            nh = 0;
+                            hn3 = load_hdr(b, seg0 + last);
+                        }
                     }
                 }
+                need = __ballot(phase == 0);
             }
-            need = __ballot(phase == 0);
+            if (__ballot(phase == 1 || phase == 2) == 0ull) break;
         }
-        if (__ballot(phase == 1 || phase == 2) == 0ull) break;
         // one row: propagate (both phases), then pick (inward phase)
-        bool end = false;
         if (phase == 1 || phase == 2) {
+            bool end = false;
             if (r != cur) {
                 if (!kf_propagate(s, sX[cur], sX[r], kc)) end = true;
                 else cur = r;
@@ -1204,13 +1264,8 @@ __global__ __launch_bounds__(256) void k_tracklet_in(Bufs b) {
                 }
                 if (--r < 0) end = true;
             }
-        }
-        if (end) {
-            if (phase == 2) {  // a failed step on the way down leaves the tracklet without picks
-                tracklet_finish(b, j, nr, nh, tid, vec, pr, kc.n_min);
-                st_picks += nh;
-            }
-            phase = 0;
+            // a failed step on the way down leaves the tracklet without picks
+            if (end) phase = phase == 2 ? 4 : 0;
         }
     }
     if (stats) {
@@ -1608,6 +1663,11 @@ void enqueue_reset(const Bufs& b, hipStream_t st) {
 void enqueue_weights_clear(const Bufs& b, int64_t c0, int64_t c1, hipStream_t st) {
     if (c1 > c0)
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(c1 - c0, 256, 4096)), dim3(256), 0, st, b.weight + c0, c1 - c0, 0u);
+}
+
+void enqueue_native_local(const Bufs& b, int64_t nseg, float* y, float* z, hipStream_t st) {
+    if (nseg <= 0) return;
+    hipLaunchKernelGGL(k_native_local, dim3((unsigned)(nseg < 65536 ? nseg : 65536)), dim3(256), 0, st, b, nseg, y, z);
 }
 
 void enqueue_grid(const Bufs& b, int i0, int i1, int max_row, hipStream_t st) {

@@ -29,6 +29,8 @@ struct DevConsts {
     double kB_f64;                            // -0.00299792458 * Bz in FP64 (vertex z only)
     float chi2_merge, rot_c, rot_s;           // cross-sector merge cut; cos, sin of 20 degrees
     int merge_max_gap;                        // rows between a continued segment's end and the next
+    float pad_w[kMaxRows], pad_c[kMaxRows];   // native input: pad pitch, pad coordinate of y = 0
+    float z_per_bin, z_readout;               // native input: drift length per time bin, |z| of the readout
 };
 
 // The scalar constants of the row steps, copied into registers once per

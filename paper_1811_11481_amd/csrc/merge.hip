@@ -389,8 +389,9 @@ __global__ __launch_bounds__(256) void k_mrg_refit(MergeBufs m) {
             chain_hit(c, i, f, q);
             row = b.trk_hrow[q];
             const int32_t id = b.o_hit_id[q];
-            y = b.y[id];
-            z = b.z[id];
+            const float2 c = b.yz[b.pos_of[id]];  // as the grid holds it (native input transformed)
+            y = c.x;
+            z = c.y;
         };
         bool ok = c.n > 0;
         float chi2sum = 0.0f;

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_CAPACITY", 3: "E_DEVICE", 4: "E_OOM",
 EXPORTED = [
     "tpcca_default_params", "tpcca_default_tuning", "tpcca_create", "tpcca_destroy", "tpcca_last_error",
     "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_track", "tpcca_track_batched", "tpcca_track_async",
-    "tpcca_track_async_noalloc", "tpcca_merge", "tpcca_autotune",
+    "tpcca_track_async_noalloc", "tpcca_merge", "tpcca_track_native", "tpcca_native_to_local", "tpcca_autotune",
     "tpcca_export_sizes", "tpcca_export_grid", "tpcca_export_links", "tpcca_export_tracklets",
     "tpcca_export_selected", "tpcca_get_stats", "tpcca_get_stage_times", "tpcca_fp32_selfcheck",
     "tpcca_refit_fwd", "tpcca_refit_bwd",
@@ -68,6 +68,10 @@ class Params(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("chi2_merge", ctypes.c_double),
         ("merge_max_gap", ctypes.c_int32),
+        ("pad_width", ctypes.c_float * 256),
+        ("pad_center", ctypes.c_float * 256),
+        ("z_per_bin", ctypes.c_double),
+        ("z_readout", ctypes.c_double),
     ]
 
 
@@ -96,6 +100,17 @@ class Clusters(ctypes.Structure):
         ("row_start", ctypes.c_void_p),
         ("y", ctypes.c_void_p),
         ("z", ctypes.c_void_p),
+        ("n_clusters", ctypes.c_int64),
+    ]
+
+
+class NativeClustersC(ctypes.Structure):
+    _fields_ = [
+        ("n_inst", ctypes.c_int32),
+        ("inst_sector", ctypes.c_void_p),
+        ("row_start", ctypes.c_void_p),
+        ("pad", ctypes.c_void_p),
+        ("time", ctypes.c_void_p),
         ("n_clusters", ctypes.c_int64),
     ]
 
@@ -184,6 +199,10 @@ def load():
         for fn in ("tpcca_track_async", "tpcca_track_async_noalloc"):
             getattr(L, fn).restype = st
             getattr(L, fn).argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(TracksC), vp, vp, vp]
+        L.tpcca_track_native.restype = st
+        L.tpcca_track_native.argtypes = [vp, ctypes.POINTER(NativeClustersC), ctypes.POINTER(TracksC), vp]
+        L.tpcca_native_to_local.restype = st
+        L.tpcca_native_to_local.argtypes = [vp, ctypes.POINTER(NativeClustersC), vp, vp, vp]
         L.tpcca_merge.restype = st
         L.tpcca_merge.argtypes = [vp, vp, ctypes.POINTER(TracksC), vp, vp, vp]
         L.tpcca_autotune.restype = st
@@ -279,6 +298,44 @@ class DeviceClusters:
         c.row_start = self.row_start.data_ptr()
         c.y = self.y.data_ptr() if self.n_clusters else None
         c.z = self.z.data_ptr() if self.n_clusters else None
+        c.n_clusters = self.n_clusters
+        return c
+
+
+@dataclass
+class DeviceNativeClusters:
+    """Clusters in native coordinates (pad, time per cluster) in device memory."""
+
+    n_inst: int
+    inst_sector: "object"  # int32 [n_inst]
+    row_start: "object"  # int64 [n_inst * n_rows + 1]
+    pad: "object"  # float32 [N]
+    time: "object"  # float32 [N]
+
+    @property
+    def n_clusters(self) -> int:
+        return int(self.pad.shape[0])
+
+    @property
+    def y(self):  # for capacity sizing and the device of outputs
+        return self.pad
+
+    @classmethod
+    def from_host(cls, n_inst, inst_sector, row_start, pad, time, device="cuda"):
+        torch = _torch()
+        return cls(int(n_inst),
+                   torch.as_tensor(np.asarray(inst_sector, np.int32), device=device),
+                   torch.as_tensor(np.asarray(row_start, np.int64), device=device),
+                   torch.as_tensor(np.asarray(pad, np.float32), device=device),
+                   torch.as_tensor(np.asarray(time, np.float32), device=device))
+
+    def c_struct(self) -> NativeClustersC:
+        c = NativeClustersC()
+        c.n_inst = self.n_inst
+        c.inst_sector = self.inst_sector.data_ptr() if self.n_inst else None
+        c.row_start = self.row_start.data_ptr()
+        c.pad = self.pad.data_ptr() if self.n_clusters else None
+        c.time = self.time.data_ptr() if self.n_clusters else None
         c.n_clusters = self.n_clusters
         return c
 
@@ -387,6 +444,28 @@ class Tracker:
             self._check(st)
         out.status = st
         return out
+
+    def track_native(self, clusters: DeviceNativeClusters, out: Tracks | None = None, stream=None,
+                     check: bool = True) -> Tracks:
+        """Batched track call on native (pad, time) clusters, transformed by the grid kernel."""
+        out = out if out is not None else self.alloc_tracks(clusters)
+        cin, cout = clusters.c_struct(), out.c_struct()
+        st = self.lib.tpcca_track_native(self.h, ctypes.byref(cin), ctypes.byref(cout), _stream(stream))
+        out.n_tracks, out.n_hits = int(cout.n_tracks), int(cout.n_hits)
+        if check:
+            self._check(st)
+        out.status = st
+        return out
+
+    def native_to_local(self, clusters: DeviceNativeClusters, stream=None):
+        """Local (y, z) float32 device tensors of native clusters (the library's transform)."""
+        torch = _torch()
+        n = clusters.n_clusters
+        y = torch.empty(max(n, 1), dtype=torch.float32, device=clusters.pad.device)
+        z = torch.empty(max(n, 1), dtype=torch.float32, device=clusters.pad.device)
+        c = clusters.c_struct()
+        self._check(self.lib.tpcca_native_to_local(self.h, ctypes.byref(c), _ptr(y), _ptr(z), _stream(stream)))
+        return y[:n], z[:n]
 
     def track_async(self, clusters: DeviceClusters, out: Tracks, counts, status, stream=None) -> Tracks:
         """Batched form with nothing read back: `counts` (int64[2] device tensor)

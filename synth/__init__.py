@@ -217,3 +217,17 @@ def generate(config: str, event: int = 0) -> ClusterSet:
 def row_plane_x(i):
     """Pad-row plane position X_i = 85 + i * 162 / 151 cm (FP64)."""
     return 85.0 + np.asarray(i, dtype=np.float64) * 162.0 / 151.0
+
+
+def to_native(cs: ClusterSet, pad_width, pad_center, z_per_bin, z_readout):
+    """Native (pad, time) float32 readout coordinates of the clusters of `cs`
+    for a pad geometry (pitch and centre pad per row) and drift constants: the
+    readout model inverted in FP64 (pad = y / pitch + centre, time = (readout
+    |z| - side * z) / drift per bin, side +1 on sectors 0..17, -1 on 18..35),
+    then rounded to binary32. Input generation only."""
+    pw = np.asarray(pad_width, np.float64)[cs.row]
+    pc = np.asarray(pad_center, np.float64)[cs.row]
+    side = np.where(cs.inst_sector[cs.instance_of()] < 18, 1.0, -1.0)
+    pad = cs.y.astype(np.float64) / pw + pc
+    time = (float(z_readout) - side * cs.z.astype(np.float64)) / float(z_per_bin)
+    return pad.astype(np.float32), time.astype(np.float32)
