@@ -126,6 +126,23 @@ def measured_traffic(kernel: str, workload: str):
     return int(d["traffic_bytes_per_launch"])
 
 
+def measured_issue(kernel: str, workload: str, launch_ms: float):
+    """VALU issue of the dominant kernel from the committed rocprofv3 SQ
+    counters (wave-level VALU instructions per launch, fraction of lanes
+    enabled) and the live launch time: the fraction of the 1024 SIMDs' issue
+    slots (one wave64 instruction per 4 cycles at 2.4 GHz) it kept busy. None
+    when there is no summary or the kernels have changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel.replace("k_", ""), workload))
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_sha256") != kernel_source_sha256() or "valu_insts_per_launch" not in d or launch_ms <= 0:
+        return None
+    n = float(d["valu_insts_per_launch"])
+    return {"valu_wave_insts": int(n), "lanes_active": d.get("lanes_active"),
+            "busy_frac": round(n * 4 / (1024 * 2.4e9 * launch_ms * 1e-3), 4)}
+
+
 def stage_roofline(trk, dc, cs, workload, warmup, steps):
     """Per-stage kernel time (HIP events between the stages, on the launch
     stream), algorithmic bytes from the work counters, and the roofline of the
@@ -162,7 +179,8 @@ def stage_roofline(trk, dc, cs, workload, warmup, steps):
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(kname, workload),
                 "alg_bytes_per_launch": dom_bytes, "impl_bytes_per_launch": stages[dom]["impl_bytes"],
-                "avg_launch_ms": stages[dom]["ms"], "work_counters": st}
+                "avg_launch_ms": stages[dom]["ms"], "valu_issue": measured_issue(kname, workload, stages[dom]["ms"]),
+                "work_counters": st}
     return stages, roofline
 
 
@@ -223,6 +241,61 @@ def diff_leg(args, torch, np, synth):
     return res
 
 
+def next_leg(torch, np, synth, cs, dc, warmup, steps):
+    """The steps that follow the sector tracking, each timed on the headline
+    workload (device time around the call, inputs resident): the cross-sector
+    merge after a track call (its one count read-back included), the batched
+    track call on native (pad, time) clusters, and the batched track call that
+    also writes the compression residuals (every call writes z0)."""
+    from paper_1811_11481_amd import FLAG_MERGE, DeviceNativeClusters, Tracker, default_params
+
+    def timed(fn):
+        for _ in range(max(1, warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    res = {}
+    # merge: events of 36 sector instances each (mode-1 generator layout)
+    mp = default_params(flags=FLAG_MERGE)
+    trk = Tracker(params=mp)
+    out = trk.alloc_tracks(dc)
+    trk.track(dc, out, batched=True)
+    ev = torch.as_tensor((np.arange(cs.n_inst) // 36).astype(np.int32), device="cuda")
+    state = {}
+
+    def do_merge():
+        state["m"] = trk.merge(ev)
+
+    mms = timed(do_merge)
+    M, nseg, _ = state["m"]
+    res["merge"] = {"ms": round(mms, 4), "sector_tracks": out.n_tracks, "merged_tracks": M.n_tracks,
+                    "tracks_with_2plus_segments": int((nseg > 1).sum().item())}
+    del state, M, nseg, trk, out
+    # native (pad, time) input, transformed by the grid kernel
+    p = default_params()
+    pad, tm = synth.to_native(cs, np.array(p.pad_width[:152]), np.array(p.pad_center[:152]), p.z_per_bin,
+                              p.z_readout)
+    dn = DeviceNativeClusters.from_host(cs.n_inst, cs.inst_sector, cs.row_start, pad, tm)
+    trk = Tracker()
+    out = trk.alloc_tracks(dn)
+    nms = timed(lambda: trk.track_native(dn, out))
+    res["native_input"] = {"ms_per_step": round(nms, 4), "clusters_per_s": round(cs.n_clusters / (nms * 1e-3), 1),
+                           "n_tracks": out.n_tracks}
+    del dn, out
+    # compression residuals (int16 per cluster and coordinate, step 2^-7 cm)
+    out = trk.alloc_tracks(dc).want_residuals(-7)
+    rms = timed(lambda: trk.track(dc, out, batched=True))
+    res["residuals"] = {"ms_per_step": round(rms, 4), "n_tracks": out.n_tracks, "n_hits": out.n_hits}
+    print("[bench] next steps: merge %.3f ms, native %.3f ms/step, residuals %.3f ms/step"
+          % (mms, nms, rms), file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +308,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick tiling with tpcca_autotune before timing")
     ap.add_argument("--extra", default="C2,C4,C3", help="comma-separated extra workloads timed in the batched form")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable-refit leg (C5)")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the merge / native-input / residuals timings on the headline workload")
     ap.add_argument("--diff-tracks", type=int, default=100000)
     ap.add_argument("--diff-only", action="store_true",
                     help="run only the differentiable-refit leg and print its JSON object")
@@ -326,6 +401,10 @@ def main():
         print("[bench] %s batched: %.3f ms/step" % (wl, ems), file=sys.stderr, flush=True)
         del edc, eout
 
+    nxt = None
+    if not args.no_next:
+        nxt = next_leg(torch, np, synth, cs, dc, args.warmup, max(3, args.steps // 2))
+
     diff = None
     if not args.no_diff:
         diff = diff_leg(args, torch, np, synth)
@@ -383,6 +462,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "differentiable_refit": diff,
+        "next_steps": nxt,
     }
     print(json.dumps(line), flush=True)
 
