@@ -953,7 +953,8 @@ tpcca_status tpcca_merge(tpcca_ctx* ctx, const int32_t* inst_event, tpcca_tracks
                  o_bo = L.add(4 * t1), o_bi = L.add(8 * t1), o_nx = L.add(4 * t1), o_pv = L.add(4 * t1),
                  o_ok = L.add(4 * t1), o_ab = L.add(t1), o_st = L.add(80 * t1), o_c2 = L.add(4 * t1),
                  o_na = L.add(4 * t1), o_rw = L.add(4 * t1), o_ns = L.add(4 * t1),
-                 o_a3 = L.add(std::max<int64_t>(nh, 1)), o_ot = L.add(4 * t1), o_oh = L.add(8 * t1);
+                 o_a3 = L.add(std::max<int64_t>(nh, 1)), o_ot = L.add(4 * t1), o_oh = L.add(8 * t1),
+                 o_hyz = L.add(8 * std::max<int64_t>(nh, 1)), o_hd = L.add(4 * t1), o_nhd = L.add(4);
     if (L.total > ctx->mg_bytes) {
         if (ctx->mg_base) {
             HIP_TRY(hipStreamSynchronize(st));
@@ -973,6 +974,7 @@ tpcca_status tpcca_merge(tpcca_ctx* ctx, const int32_t* inst_event, tpcca_tracks
     m.b = lb;
     m.inst_event = inst_event;
     m.n_t = nt;
+    m.n_h = nh;
     m.nb = (int32_t*)(base + o_nb);
     m.rcnt = (int32_t*)(base + o_rc);
     m.rstart = (int32_t*)(base + o_rs);
@@ -992,6 +994,9 @@ tpcca_status tpcca_merge(tpcca_ctx* ctx, const int32_t* inst_event, tpcca_tracks
     m.acc3 = (uint8_t*)(base + o_a3);
     m.out_t = (int32_t*)(base + o_ot);
     m.out_h = (int64_t*)(base + o_oh);
+    m.hyz = (float2*)(base + o_hyz);
+    m.heads = (int32_t*)(base + o_hd);
+    m.nheads = (unsigned int*)(base + o_nhd);
     m.cap_tracks = merged->cap_tracks;
     m.cap_hits = merged->cap_hits;
     m.o_inst = merged->inst;

@@ -132,6 +132,7 @@ struct MergeBufs {
     Bufs b;                       // the last track call (its inputs and outputs must still be valid)
     const int32_t* inst_event;    // [n_inst] event of each instance
     int64_t n_t;                  // sector tracks of that call
+    int64_t n_h;                  // their output clusters
     // scratch
     int32_t* nb;                  // [n_inst * 2] neighbour instance per direction (-1: none)
     int32_t* rcnt;                // [n_inst * n_rows + 1] tracks per (instance, reference row)
@@ -150,6 +151,9 @@ struct MergeBufs {
     int32_t* row;                 // [n_t]
     int32_t* nseg;                // [n_t]
     uint8_t* acc3;                // [n_hits] kept by the merged refit's last pass
+    float2* hyz;                  // [n_hits] coordinates of each output cluster
+    int32_t* heads;               // [n_t] chain heads (first nheads entries)
+    unsigned int* nheads;         // [1]
     int32_t* out_t;               // [n_t] output index
     int64_t* out_h;               // [n_t] first output cluster
     // outputs

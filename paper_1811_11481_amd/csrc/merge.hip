@@ -158,21 +158,35 @@ __global__ void k_mrg_clear(int32_t* p, int64_t n) {
 // For every instance, the lowest instance of the same event in the
 // phi-neighbouring sector of the same side, one per direction; an instance
 // that is not the lowest of its (event, sector) takes no part in the merge.
-__global__ void k_mrg_neighbours(MergeBufs m) {
+constexpr int kNbLds = 4096;  // instances whose (event, sector) a workgroup stages in LDS
+
+__global__ __launch_bounds__(256) void k_mrg_neighbours(MergeBufs m) {
     const Bufs& b = m.b;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < b.n_inst; i += gridDim.x * blockDim.x) {
-        const int sec = b.inst_sector[i], side = sec / 18, phi = sec % 18;
+    __shared__ int2 es[kNbLds];  // (event, sector) per instance
+    const int n = b.n_inst;
+    const bool lds = n <= kNbLds;
+    if (lds)
+        for (int j = threadIdx.x; j < n; j += blockDim.x) es[j] = make_int2(m.inst_event[j], b.inst_sector[j]);
+    __syncthreads();
+    auto at = [&](int j) { return lds ? es[j] : make_int2(m.inst_event[j], b.inst_sector[j]); };
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int2 me = at(i);
+        const int sec = me.y, side = sec / 18, phi = sec % 18;
         int canon = 1;
-        for (int j = 0; j < i; ++j)
-            if (m.inst_event[j] == m.inst_event[i] && b.inst_sector[j] == sec) canon = 0;
+        for (int j = 0; j < i && canon; ++j) {
+            const int2 o = at(j);
+            if (o.x == me.x && o.y == sec) canon = 0;
+        }
         for (int k = 0; k < 2; ++k) {
             const int want = side * 18 + (phi + (k ? 1 : -1) + 18) % 18;
             int best = -1;
-            for (int j = 0; j < b.n_inst; ++j)
-                if (j != i && m.inst_event[j] == m.inst_event[i] && b.inst_sector[j] == want) {
+            for (int j = 0; j < n && canon; ++j) {
+                const int2 o = at(j);
+                if (j != i && o.x == me.x && o.y == want) {
                     best = j;
                     break;
                 }
+            }
             m.nb[2 * i + k] = canon ? best : -1;
         }
     }
@@ -310,66 +324,94 @@ __global__ void k_mrg_cycles(MergeBufs m) {
 }
 
 // -------------------------------------------------------------- merged refit
-struct ChainHits {
-    int32_t seg[kMaxChain];
-    int64_t h0[kMaxChain];  // first output cluster of the segment
-    int n0[kMaxChain + 1];  // clusters before the segment in the chain
-    int nseg, n;
-};
-
-__device__ __forceinline__ void chain_hit(const ChainHits& c, int i, int& f, int64_t& q) {
-    f = 0;
-    while (f + 1 < c.nseg && c.n0[f + 1] <= i) ++f;
-    q = c.h0[f] + (i - c.n0[f]);
+// Coordinates of every output cluster of the last track call, gathered once in
+// cluster order (as the grid holds them: native input transformed), so that a
+// chain's refit reads one array at a computed index.
+__global__ void k_mrg_gather(MergeBufs m, int64_t nh) {
+    const Bufs& b = m.b;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x)
+        m.hyz[q] = b.yz[b.pos_of[b.o_hit_id[q]]];
 }
 
-// One lane per chain (first segment with a partner): the three passes of the
-// sector refit over all clusters of the chain, rotating between frames.
-__global__ __launch_bounds__(256) void k_mrg_refit(MergeBufs m) {
+// The chain heads (a segment with a partner and none before it), in any order:
+// each chain's refit depends on its own segments only.
+__global__ void k_mrg_heads(MergeBufs m) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m.n_t; t += (int64_t)gridDim.x * blockDim.x)
+        if (m.prev[t] < 0 && m.next[t] >= 0) m.heads[atomicAdd(m.nheads, 1u)] = (int32_t)t;
+}
+
+// Position in a chain's cluster stream: the segment, its index in the chain
+// (its frame), the output cluster and the segment's cluster range.
+struct ChainCursor {
+    int32_t seg;
+    int f;
+    int64_t q, lo, hi;
+};
+
+__device__ __forceinline__ void cursor_at(const MergeBufs& m, ChainCursor& c, int32_t seg, int f, bool last) {
+    c.seg = seg;
+    c.f = f;
+    c.lo = m.b.o_hit_start[seg];
+    c.hi = m.b.o_hit_start[seg + 1];
+    c.q = last ? c.hi - 1 : c.lo;
+}
+
+// the next cluster inward (towards the chain's first segment) or outward
+__device__ __forceinline__ void cursor_step(const MergeBufs& m, ChainCursor& c, bool inward) {
+    if (inward) {
+        if (c.q > c.lo) --c.q;
+        else cursor_at(m, c, m.prev[c.seg], c.f - 1, true);
+    } else {
+        if (c.q + 1 < c.hi) ++c.q;
+        else cursor_at(m, c, m.next[c.seg], c.f + 1, false);
+    }
+}
+
+// One lane per chain: the three passes of the sector refit over all clusters
+// of the chain, rotating between frames; the next cluster's row and
+// coordinates are loaded one step ahead.
+__global__ __launch_bounds__(128) void k_mrg_refit(MergeBufs m) {
     const Bufs& b = m.b;
     const DevConsts& K = *b.K;
     const KfConsts kc = kf_consts(K);
     __shared__ float sX[kMaxRows];
     kf_load_rows(sX, K);
     const int nr = K.n_rows;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m.n_t; t += (int64_t)gridDim.x * blockDim.x) {
-        if (m.prev[t] >= 0 || m.next[t] < 0) continue;
-        ChainHits c;
-        c.nseg = 0;
-        c.n = 0;
-        int dirs[kMaxChain];
-        for (int64_t u = t; u >= 0 && c.nseg < kMaxChain; u = m.next[u]) {
-            c.seg[c.nseg] = (int32_t)u;
-            c.h0[c.nseg] = b.o_hit_start[u];
-            c.n0[c.nseg] = c.n;
-            c.n += (int)(b.o_hit_start[u + 1] - b.o_hit_start[u]);
-            ++c.nseg;
+    const int64_t nheads = (int64_t)*m.nheads;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nheads; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t t = m.heads[k];
+        // the chain: at most kMaxChain segments from t along next
+        int nseg = 1, n = (int)(b.o_hit_start[t + 1] - b.o_hit_start[t]);
+        int32_t tail = t;
+        for (int32_t u = m.next[t]; u >= 0 && nseg < kMaxChain; u = m.next[u]) {
+            tail = u;
+            n += (int)(b.o_hit_start[u + 1] - b.o_hit_start[u]);
+            ++nseg;
         }
-        c.n0[c.nseg] = c.n;
-        for (int f = 0; f + 1 < c.nseg; ++f)
-            dirs[f] = sector_step(b.inst_sector[b.o_inst[c.seg[f]]], b.inst_sector[b.o_inst[c.seg[f + 1]]]);
-        for (int i = 0; i < c.n; ++i) {
-            int f;
-            int64_t q;
-            chain_hit(c, i, f, q);
-            m.acc3[q] = 0;
+        {
+            int32_t u = t;
+            for (int f = 0; f < nseg; ++f, u = m.next[u])
+                for (int64_t q = b.o_hit_start[u]; q < b.o_hit_start[u + 1]; ++q) m.acc3[q] = 0;
         }
-        const int32_t tail_si = b.trk_si[c.seg[c.nseg - 1]];
+        const int32_t tail_si = b.trk_si[tail];
         KState s;
         load_state(s, b.rf_state2 + (int64_t)tail_si * 20);
         int cur = b.rf_row2[tail_si];
-        int frame = c.nseg - 1;
+        int frame = nseg - 1;
+        int32_t frame_seg = tail;  // the segment whose frame the state is in
         float ref_y = s.p[0], ref_z = s.p[1];
         s.p[0] = 0.0f;
         s.p[1] = 0.0f;
-        auto move_to = [&](int target, int tframe) -> bool {
+        auto move_to = [&](int target, int tframe, int32_t tseg) -> bool {
             if (tframe != frame) {
                 s.p[0] = ref_y + s.p[0];
                 s.p[1] = ref_z + s.p[1];
                 float x = sX[cur];
-                const int dir = tframe > frame ? dirs[frame] : -dirs[tframe];
+                const int sa = b.inst_sector[b.o_inst[frame_seg]], sb = b.inst_sector[b.o_inst[tseg]];
+                const int dir = tframe > frame ? sector_step(sa, sb) : -sector_step(sb, sa);
                 if (!kf_rotate(s, x, K.rot_c, dir > 0 ? K.rot_s : -K.rot_s, kc)) return false;
                 frame = tframe;
+                frame_seg = tseg;
                 ref_y = s.p[0];
                 ref_z = s.p[1];
                 s.p[0] = 0.0f;
@@ -385,37 +427,35 @@ __global__ __launch_bounds__(256) void k_mrg_refit(MergeBufs m) {
             }
             return true;
         };
-        auto hit_of = [&](int i, int& row, int& f, float& y, float& z, int64_t& q) {
-            chain_hit(c, i, f, q);
-            row = b.trk_hrow[q];
-            const int32_t id = b.o_hit_id[q];
-            const float2 c = b.yz[b.pos_of[id]];  // as the grid holds it (native input transformed)
-            y = c.x;
-            z = c.y;
-        };
-        bool ok = c.n > 0;
+        bool ok = n > 0;
+        if (ok) {  // to the chain's last cluster, in the tail's frame
+            const int64_t q = b.o_hit_start[tail + 1] - 1;
+            ok = move_to(b.trk_hrow[q], nseg - 1, tail);
+        }
         float chi2sum = 0.0f;
         int nacc = 0;
-        if (ok) {
-            int row, f;
-            float y, z;
-            int64_t q;
-            hit_of(c.n - 1, row, f, y, z, q);
-            ok = move_to(row, f);
-        }
         for (int pass = 0; pass < 3 && ok; ++pass) {
             kf_reset(s, kc);
             const bool inward = pass != 1;
-            for (int qq = 0; qq < c.n && ok; ++qq) {
-                const int i = inward ? c.n - 1 - qq : qq;
-                int row, f;
-                float y, z;
-                int64_t q;
-                hit_of(i, row, f, y, z, q);
-                if (!move_to(row, f)) {
+            ChainCursor cu;
+            if (inward) cursor_at(m, cu, tail, nseg - 1, true);
+            else cursor_at(m, cu, t, 0, false);
+            int row_n = b.trk_hrow[cu.q];
+            float2 c_n = m.hyz[cu.q];
+            for (int qq = 0; qq < n; ++qq) {
+                const ChainCursor cc = cu;
+                const int row = row_n;
+                const float2 c = c_n;
+                if (qq + 1 < n) {
+                    cursor_step(m, cu, inward);
+                    row_n = b.trk_hrow[cu.q];
+                    c_n = m.hyz[cu.q];
+                }
+                if (!move_to(row, cc.f, cc.seg)) {
                     ok = false;
                     break;
                 }
+                const float y = c.x, z = c.y;
                 const Innov inn = kf_innovation(s, y - ref_y, z - ref_z, kc);
                 if (inn.chi2 <= kc.chi2_rej) {
                     kf_update(s, inn);
@@ -426,14 +466,14 @@ __global__ __launch_bounds__(256) void k_mrg_refit(MergeBufs m) {
                     if (pass == 2) {
                         chi2sum = chi2sum + inn.chi2;
                         ++nacc;
-                        m.acc3[q] = 1;
+                        m.acc3[cc.q] = 1;
                     }
                 }
             }
         }
         ok = ok && frame == 0 && nacc >= kc.n_min;
         if (!ok) continue;
-        float* o = m.state + t * 20;
+        float* o = m.state + (int64_t)t * 20;
         o[0] = ref_y + s.p[0];
         o[1] = ref_z + s.p[1];
 #pragma unroll
@@ -443,9 +483,12 @@ __global__ __launch_bounds__(256) void k_mrg_refit(MergeBufs m) {
         m.chi2[t] = chi2sum;
         m.nacc[t] = nacc;
         m.row[t] = cur;
-        m.nseg[t] = c.nseg;
+        m.nseg[t] = nseg;
         m.ok[t] = 1;
-        for (int f = 1; f < c.nseg; ++f) m.absorbed[c.seg[f]] = 1;
+        {
+            int32_t u = m.next[t];
+            for (int f = 1; f < nseg; ++f, u = m.next[u]) m.absorbed[u] = 1;
+        }
     }
 }
 
@@ -582,7 +625,7 @@ inline int grid_of(int64_t n, int block, int cap) {
 
 void enqueue_merge(const MergeBufs& m, hipStream_t st) {
     const int nkeys = m.b.n_inst * m.b.n_rows;
-    hipLaunchKernelGGL(k_mrg_neighbours, dim3(grid_of(m.b.n_inst, 64, 1024)), dim3(64), 0, st, m);
+    hipLaunchKernelGGL(k_mrg_neighbours, dim3(grid_of(m.b.n_inst, 256, 1024)), dim3(256), 0, st, m);
     // bucket counts cleared by a kernel (graph-capture safe)
     hipLaunchKernelGGL(k_mrg_clear, dim3(grid_of(nkeys + 1, 256, 1024)), dim3(256), 0, st, m.rcnt, (int64_t)nkeys + 1);
     if (m.n_t > 0) {
@@ -593,6 +636,9 @@ void enqueue_merge(const MergeBufs& m, hipStream_t st) {
         hipLaunchKernelGGL(k_mrg_match, dim3(g), dim3(256), 0, st, m);
         hipLaunchKernelGGL(k_mrg_link, dim3(g), dim3(256), 0, st, m);
         hipLaunchKernelGGL(k_mrg_cycles, dim3(g), dim3(256), 0, st, m);
+        hipLaunchKernelGGL(k_mrg_gather, dim3(grid_of(m.n_h, 256, 16384)), dim3(256), 0, st, m, m.n_h);
+        hipLaunchKernelGGL(k_mrg_clear, dim3(1), dim3(64), 0, st, (int32_t*)m.nheads, (int64_t)1);
+        hipLaunchKernelGGL(k_mrg_heads, dim3(g), dim3(256), 0, st, m);
         hipLaunchKernelGGL(k_mrg_refit, dim3(grid_of(m.n_t, 128, 4096)), dim3(128), 0, st, m);
     }
     MergeOp op{m};
