@@ -317,8 +317,9 @@ def main():
                     help="first run one device copy of MIB MiB (reference for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the tracker shards by sector instance with no communication, "
-              "and this build runs on a single MI355X (--gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): the tracker shards by sector instance with no "
+              "communication, so several GPUs run independent instance sets; multi-GPU runs are not measured.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
