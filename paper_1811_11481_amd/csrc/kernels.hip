@@ -26,7 +26,7 @@ namespace {
 
 constexpr float kBinMargin = 0.01f;  // cm: bin ranges of window queries are widened by this
 constexpr int kCandChunk = 8;         // window candidates loaded per memory round trip
-constexpr int kNbKeep = 4;            // neighbour candidates in row r-1 kept in registers per hit
+constexpr int kNbKeep = 8;            // neighbour candidates in row r-1 kept in registers per hit
 constexpr int kSmallRow = 4096;
 constexpr int kLargeRow = 16384;      // TPCCA_MAX_ROW_CLUSTERS
 constexpr int kKeyShift = 14;         // key = bin << 14 | local index (both < 16384)
@@ -388,8 +388,13 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
             // the d candidates inside their box, scanned once: up to kNbKeep kept
             // in registers (a shift register, no indexed register access)
             int nd = 0;
-            int dt0 = 0, dt1 = 0, dt2 = 0, dt3 = 0;
-            float2 dc0 = make_float2(0.0f, 0.0f), dc1 = dc0, dc2 = dc0, dc3 = dc0;
+            int dt[kNbKeep];
+            float2 dc[kNbKeep];
+#pragma unroll
+            for (int i = 0; i < kNbKeep; ++i) {
+                dt[i] = 0;
+                dc[i] = make_float2(0.0f, 0.0f);
+            }
             const bool short_d = dz1 - dz0 <= 1;
             if (short_d) {
                 const int d00 = bsd[dz0 * gd.ny + dy0], d01 = bsd[dz0 * gd.ny + dy1 + 1];
@@ -403,10 +408,13 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     const int t = k < na ? d00 + k : d10 + (k - na);
                     const float2 pd = cd[t];
                     if (!(__builtin_fabsf(pd.x - yh) <= wyd && __builtin_fabsf(pd.y - zh) <= wzd)) continue;
-                    dt3 = dt2; dc3 = dc2;
-                    dt2 = dt1; dc2 = dc1;
-                    dt1 = dt0; dc1 = dc0;
-                    dt0 = t; dc0 = pd;
+#pragma unroll
+                    for (int i = kNbKeep - 1; i > 0; --i) {
+                        dt[i] = dt[i - 1];
+                        dc[i] = dc[i - 1];
+                    }
+                    dt[0] = t;
+                    dc[0] = pd;
                     ++nd;
                 }
             }
@@ -419,10 +427,9 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     if (!(__builtin_fabsf(yu - yh) <= wyu && __builtin_fabsf(zu - zh) <= wzu)) continue;
                     ++n_cu;
                     if (kept) {
-                        if (nd > 0) pair(q, yu, zu, dt0, dc0.x, dc0.y);
-                        if (nd > 1) pair(q, yu, zu, dt1, dc1.x, dc1.y);
-                        if (nd > 2) pair(q, yu, zu, dt2, dc2.x, dc2.y);
-                        if (nd > 3) pair(q, yu, zu, dt3, dc3.x, dc3.y);
+#pragma unroll
+                        for (int i = 0; i < kNbKeep; ++i)
+                            if (nd > i) pair(q, yu, zu, dt[i], dc[i].x, dc[i].y);
                         continue;
                     }
                     for (int dz = dz0; dz <= dz1; ++dz) {
