@@ -112,9 +112,10 @@ def kernel_source_sha256() -> str:
 
 
 def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary (FETCH_SIZE
-    and WRITE_SIZE scaled by a copy of known size), or None when there is none
-    for this kernel and workload or the kernels have changed since."""
+    """HBM bytes per launch of a stage's kernels from the committed rocprofv3
+    PMC summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
+    None when there is none for this stage and workload or the kernels have
+    changed since."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel.replace("k_", ""), workload))
     if not os.path.exists(path):
         path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel, workload))
@@ -127,11 +128,11 @@ def measured_traffic(kernel: str, workload: str):
 
 
 def measured_issue(kernel: str, workload: str, launch_ms: float):
-    """VALU issue of the dominant kernel from the committed rocprofv3 SQ
-    counters (wave-level VALU instructions per launch, fraction of lanes
+    """VALU issue of the dominant stage's kernels from the committed rocprofv3
+    SQ counters (wave-level VALU instructions per launch, fraction of lanes
     enabled) and the live launch time: the fraction of the 1024 SIMDs' issue
-    slots (one wave64 instruction per 4 cycles at 2.4 GHz) it kept busy. None
-    when there is no summary or the kernels have changed since."""
+    slots (one wave64 instruction per 4 cycles at 2.4 GHz) they kept busy.
+    None when there is no summary or the kernels have changed since."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel.replace("k_", ""), workload))
     if not os.path.exists(path):
         return None
@@ -141,6 +142,18 @@ def measured_issue(kernel: str, workload: str, launch_ms: float):
     n = float(d["valu_insts_per_launch"])
     return {"valu_wave_insts": int(n), "lanes_active": d.get("lanes_active"),
             "busy_frac": round(n * 4 / (1024 * 2.4e9 * launch_ms * 1e-3), 4)}
+
+
+def stage_kernels(stage, tuning):
+    """The kernels one launch of a stage runs (their times add up to the
+    stage's event-timed duration)."""
+    if stage == "tracklets":
+        if tuning.inward_wgs > 0:
+            return ["k_tracklet<1>", "k_tracklet_in"]
+        if tuning.inward_sort:
+            return ["k_tracklet<1>", "k_tl_order", "k_tracklet_inward"]
+        return ["k_tracklet<0>"]
+    return [{"refit": "k_refit", "links": "k_links", "grid": "k_grid<4096>"}.get(stage, stage)]
 
 
 def stage_roofline(trk, dc, cs, workload, warmup, steps):
@@ -175,7 +188,9 @@ def stage_roofline(trk, dc, cs, workload, warmup, steps):
     dom_bytes = stages[dom]["alg_bytes"]
     achieved = dom_bytes / (stages[dom]["ms"] * 1e-3) / 1e9
     kname = {"tracklets": "k_tracklet", "refit": "k_refit", "links": "k_links", "grid": "k_grid"}.get(dom, dom)
-    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+    kernels = stage_kernels(dom, trk.tuning)
+    roofline = {"bound": "hbm", "kernel": " + ".join(kernels), "stage": dom, "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(kname, workload),
                 "alg_bytes_per_launch": dom_bytes, "impl_bytes_per_launch": stages[dom]["impl_bytes"],

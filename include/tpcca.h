@@ -96,7 +96,7 @@ typedef struct {
 typedef struct {
     int32_t hits_per_bin;     /* grid occupancy target per bin (>= 1), default 1 */
     int32_t block_links;      /* threads per block of the neighbour kernel (64..1024), default 256 */
-    int32_t block_tracklet;   /* threads per block of the tracklet kernel (64..256), default 256 */
+    int32_t block_tracklet;   /* threads per block of the tracklet kernels (64..256), default 64 */
     int32_t block_refit;      /* threads per block of the refit kernel (64..256), default 128 */
     int32_t block_scan;       /* threads per block of scans/compactions, default 256 */
     int32_t sort_seeds;       /* 1: each refit workgroup hands its chunk of consecutive tracks to its lanes
@@ -110,11 +110,15 @@ typedef struct {
                                  (default); 1 = the forward keeps a checkpoint at the start of each of
                                  the three passes and the backward recomputes one pass at a time from
                                  it, last pass first (a third of the tape; same gradients bit for bit) */
-    int32_t inward_wgs;       /* 0 (default): each tracklet's inward pass (Section 3) runs in the lane that
-                                 followed it outward; > 0: the outward kernel stops at the turn and a
+    int32_t inward_wgs;       /* 0 (default): see inward_sort; > 0: the outward kernel stops at the turn and a
                                  persistent kernel of this many workgroups (block_tracklet threads, at
                                  most 65536) runs the inward passes, each lane taking the next tracklet
                                  as soon as its last one ends */
+    int32_t inward_sort;      /* 1 (default; with inward_wgs = 0): the outward kernel stops at the turn; the
+                                 tracklets are ordered within chunks of 1024 seeds by the row their outward
+                                 following reached, and a second kernel runs the inward passes in that
+                                 order (lanes of a wave then have passes of similar length); 0: one kernel
+                                 runs each tracklet's outward and inward passes in one lane */
 } tpcca_tuning;
 
 /* Input clusters (device pointers, caller-owned). */

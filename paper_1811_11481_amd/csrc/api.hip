@@ -186,6 +186,7 @@ tpcca_status check_tuning(tpcca_ctx* ctx, const tpcca_tuning& t) {
     if (t.xcd_remap != 0 && t.xcd_remap != 1) return fail(ctx, TPCCA_E_ARG, "xcd_remap must be 0 or 1");
     if (t.ckpt != 0 && t.ckpt != 1) return fail(ctx, TPCCA_E_ARG, "ckpt must be 0 or 1");
     if (t.inward_wgs < 0 || t.inward_wgs > 65536) return fail(ctx, TPCCA_E_ARG, "inward_wgs must be in [0, 65536]");
+    if (t.inward_sort != 0 && t.inward_sort != 1) return fail(ctx, TPCCA_E_ARG, "inward_sort must be 0 or 1");
     return TPCCA_OK;
 }
 
@@ -383,7 +384,7 @@ Bufs make_bufs(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_tracks* out
 
 Launch make_launch(const tpcca_tuning& t) {
     return Launch{t.block_links, t.block_tracklet, t.block_refit, t.block_scan, t.sort_seeds, t.xcd_remap,
-                  t.inward_wgs};
+                  t.inward_wgs, t.inward_sort};
 }
 
 // The whole pipeline for instances [i0, i1) with clusters [c0, c1).
@@ -444,8 +445,8 @@ GraphKey graph_key(const tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_t
                           out->residuals};
     std::memcpy(key.p, ps, sizeof(ps));
     const int64_t vs[10] = {in->n_inst, in->n_clusters, out->cap_tracks, out->cap_hits, mrow,
-                           (ctx->tuning.inward_wgs * 64LL + ctx->tuning.hits_per_bin) * 4 + ctx->tuning.xcd_remap * 2 +
-                               ctx->tuning.sort_seeds,
+                           ((ctx->tuning.inward_wgs * 2LL + ctx->tuning.inward_sort) * 64 + ctx->tuning.hits_per_bin) * 4 +
+                               ctx->tuning.xcd_remap * 2 + ctx->tuning.sort_seeds,
                            ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
                            ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
                            (counts != nullptr ? 1 : 0) + 2 * native, out->residual_step_log2};
@@ -760,7 +761,7 @@ tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
     if (!t) return TPCCA_E_ARG;
     t->hits_per_bin = 1;
     t->block_links = 256;
-    t->block_tracklet = 256;
+    t->block_tracklet = 64;
     t->block_refit = 128;
     t->block_scan = 256;
     t->sort_seeds = 0;
@@ -768,6 +769,7 @@ tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
     t->xcd_remap = 1;
     t->ckpt = 0;
     t->inward_wgs = 0;
+    t->inward_sort = 1;
     return TPCCA_OK;
 }
 

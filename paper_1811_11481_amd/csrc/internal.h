@@ -73,7 +73,7 @@ struct Bufs {
     int64_t cap_starts;
     int32_t* starts;     // grid position of the start hit
     int32_t* start_inst;
-    int32_t* seed_order; // processing order of tracklets (permutation of the start range)
+    int32_t* seed_order; // split form: processing order of the inward passes (permutation of the start range)
     int32_t* tl_last;    // last row with a cluster after the outward following
     int32_t* tl_nhits;
     int32_t* tl_tid;
@@ -174,7 +174,7 @@ struct MergeBufs {
 void enqueue_merge(const MergeBufs& m, hipStream_t st);
 
 struct Launch {
-    int block_links, block_tracklet, block_refit, block_scan, sort_seeds, xcd_remap, inward_wgs;
+    int block_links, block_tracklet, block_refit, block_scan, sort_seeds, xcd_remap, inward_wgs, inward_sort;
 };
 
 constexpr int kScanBlocks = 1024;

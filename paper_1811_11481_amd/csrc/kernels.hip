@@ -980,8 +980,56 @@ __device__ __forceinline__ void tracklet_finish(const Bufs& b, int64_t j, int nr
     }
 }
 
+// The turn and stage 3 of one tracklet: covariance reset, the state carried
+// from the row the outward following reached down to its last cluster's row,
+// then the inward re-pick down to row 0 (or max_miss empty rows); picks,
+// pick count and weights written. A failed step on the way down leaves the
+// tracklet without picks.
+__device__ __forceinline__ void inward_pass(const Bufs& b, const KfConsts& kc, const float* sX, KState& s, int cur,
+                                            int last, int64_t seg0, int64_t j, int nr, int tid, unsigned int& st_rows,
+                                            unsigned int& st_cand, unsigned int& st_picks) {
+    kf_reset(s, kc);
+    bool down_ok = true;
+    for (int r = cur - 1; r >= last; --r) {
+        if (!kf_propagate(s, sX[r + 1], sX[r], kc)) {
+            down_ok = false;
+            break;
+        }
+        cur = r;
+    }
+    if (!down_ok) {
+        b.tl_nhits[j] = 0;
+        return;
+    }
+    int nh = 0, miss = 0;
+    const bool vec = (nr & 3) == 0;  // 16-byte aligned per-tracklet rows
+    PickRing pr{0, 0, 0, 0, 0u};
+    SegHdr hn3 = load_hdr(b, seg0 + last);
+    for (int r = last; r >= 0; --r) {
+        const SegHdr h = hn3;
+        hn3 = load_hdr(b, seg0 + max(r - 1, 0));
+        if (r != cur) {
+            if (!kf_propagate(s, sX[cur], sX[r], kc)) break;
+            cur = r;
+        }
+        ++st_rows;
+        Pick pk_;
+        if (pick_on_row(b, kc, s, seg0 + r, h, pk_, st_cand)) {
+            kf_update(s, pk_.inn);
+            pick_store(b, j, nr, nh, pk_.pos, r, vec, pr);
+            ++nh;
+            miss = 0;
+        } else if (++miss >= kc.max_miss) {
+            break;
+        }
+    }
+    tracklet_finish(b, j, nr, nh, tid, vec, pr, kc.n_min);
+    st_picks += nh;
+}
+
 // kSplit = 1: stop at the turn (the state, the row it reached and the last
-// row with a cluster are stored) and leave the inward stage to k_tracklet_in.
+// row with a cluster are stored) and leave the inward stage to k_tracklet_in
+// or k_tracklet_inward.
 template <int kSplit>
 __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     const DevConsts& K = *b.K;
@@ -1103,7 +1151,8 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
             b.tl_row[j] = cur;
             if (kSplit) b.tl_last[j] = last;
             if (!kSplit) {
-                // turn, stage 3
+                // turn, stage 3: the operations of inward_pass, written out here
+                // (called, it needs 7 more VGPRs here: 2 waves per SIMD instead of 3)
                 kf_reset(s, kc);
                 bool down_ok = true;
                 for (int r = cur - 1; r >= last; --r) {
@@ -1151,6 +1200,86 @@ __global__ __launch_bounds__(256) void k_tracklet(Bufs b, int remap) {
     }
     if (stats) {
         stat_add(b.ctr, ST_CHAIN_HITS, st_chain);
+        stat_add(b.ctr, ST_TL_ROWS, st_rows);
+        stat_add(b.ctr, ST_TL_CAND, st_cand);
+        stat_add(b.ctr, ST_TL_PICKS, st_picks);
+    }
+}
+
+// Order of the inward passes in the split form: within each chunk of
+// kOrderChunk consecutive seeds (one instance or a few: the grid stays in
+// the XCD's L2), the tracklets by the row their outward following reached,
+// highest first, so that the lanes of a wave have inward passes of similar
+// length; failed tracklets last. Any order gives the same results (each
+// tracklet's pass is its own; weights are an atomic max).
+constexpr int kOrderChunk = 1024;
+
+__global__ __launch_bounds__(256) void k_tl_order(Bufs b) {
+    __shared__ int hist[kMaxRows + 1];
+    const int nr = b.n_rows;
+    const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
+    if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;
+    for (int64_t c0 = (int64_t)blockIdx.x * kOrderChunk; c0 < cnt; c0 += (int64_t)gridDim.x * kOrderChunk) {
+        const int n = (int)min((int64_t)kOrderChunk, cnt - c0);
+        for (int i = threadIdx.x; i <= nr; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int row = b.tl_row[base + c0 + i];
+            atomicAdd(&hist[row >= 0 ? nr - 1 - row : nr], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int run = 0;
+            for (int k = 0; k <= nr; ++k) {
+                const int v = hist[k];
+                hist[k] = run;
+                run += v;
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int row = b.tl_row[base + c0 + i];
+            const int at = atomicAdd(&hist[row >= 0 ? nr - 1 - row : nr], 1);
+            b.seed_order[base + c0 + at] = (int32_t)(c0 + i);
+        }
+        __syncthreads();
+    }
+}
+
+// The inward passes of the split form, one lane per tracklet in the order of
+// k_tl_order (workgroups renumbered per XCD as in k_tracklet).
+__global__ __launch_bounds__(256) void k_tracklet_inward(Bufs b, int remap) {
+    const DevConsts& K = *b.K;
+    const int nr = K.n_rows;
+    const KfConsts kc = kf_consts(K);
+    const int stats = K.stats;
+    __shared__ float sX[kMaxRows];
+    kf_load_rows(sX, K);
+    const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
+    if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;
+    unsigned int st_rows = 0, st_cand = 0, st_picks = 0;
+    int64_t lg = blockIdx.x, period = gridDim.x;
+    if (remap && gridDim.x >= 8) {
+        const int64_t active = (cnt + blockDim.x - 1) / blockDim.x;
+        period = min((active + 7) / 8 * 8, (int64_t)(gridDim.x & ~7u));
+        lg = blockIdx.x < period ? xcd_logical(blockIdx.x, period) : cnt;
+    }
+    for (int64_t k = lg * blockDim.x + threadIdx.x; k < cnt; k += period * blockDim.x) {
+        const int64_t j = base + b.seed_order[base + k];
+        const int cur = b.tl_row[j];
+        if (cur < 0) continue;
+        KState s;
+        const float* st = b.tl_state + j * 20;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) s.p[i] = st[i];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) s.C[i] = st[5 + i];
+        inward_pass(b, kc, sX, s, cur, b.tl_last[j], (int64_t)b.start_inst[j] * nr, j, nr, b.tl_tid[j], st_rows,
+                    st_cand, st_picks);
+    }
+    if (stats) {
         stat_add(b.ctr, ST_TL_ROWS, st_rows);
         stat_add(b.ctr, ST_TL_CAND, st_cand);
         stat_add(b.ctr, ST_TL_PICKS, st_picks);
@@ -1711,6 +1840,10 @@ void enqueue_tracklets(const Bufs& b, const Launch& L, int64_t bound, hipStream_
     if (L.inward_wgs > 0) {
         hipLaunchKernelGGL(k_tracklet<1>, grid, dim3(L.block_tracklet), 0, st, b, L.xcd_remap);
         hipLaunchKernelGGL(k_tracklet_in, dim3(L.inward_wgs), dim3(L.block_tracklet), 0, st, b);
+    } else if (L.inward_sort) {
+        hipLaunchKernelGGL(k_tracklet<1>, grid, dim3(L.block_tracklet), 0, st, b, L.xcd_remap);
+        hipLaunchKernelGGL(k_tl_order, dim3(grid_for(bound, kOrderChunk, 4096)), dim3(256), 0, st, b);
+        hipLaunchKernelGGL(k_tracklet_inward, grid, dim3(L.block_tracklet), 0, st, b, L.xcd_remap);
     } else {
         hipLaunchKernelGGL(k_tracklet<0>, grid, dim3(L.block_tracklet), 0, st, b, L.xcd_remap);
     }

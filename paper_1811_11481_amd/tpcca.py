@@ -87,6 +87,7 @@ class Tuning(ctypes.Structure):
         ("xcd_remap", ctypes.c_int32),
         ("ckpt", ctypes.c_int32),
         ("inward_wgs", ctypes.c_int32),
+        ("inward_sort", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -124,7 +124,9 @@ def test_batched_graph_follows_new_output_buffers(c1):
 
 @pytest.mark.parametrize("tune", [dict(hits_per_bin=2), dict(hits_per_bin=3, block_tracklet=64, xcd_remap=0),
                                   dict(hits_per_bin=8, block_links=64, block_refit=256, block_scan=512, sort_seeds=1),
-                                  dict(inward_wgs=1024), dict(inward_wgs=3, block_tracklet=64, xcd_remap=0)])
+                                  dict(inward_wgs=1024), dict(inward_wgs=3, block_tracklet=64, xcd_remap=0),
+                                  dict(inward_sort=0, block_tracklet=256), dict(inward_sort=0, block_tracklet=64, xcd_remap=0),
+                                  dict(inward_sort=1, block_tracklet=256, xcd_remap=0)])
 def test_results_independent_of_tuning(c1, c1_oracle, tune):
     from paper_1811_11481_amd import default_tuning
     log("C1 tuning %s" % tune)
@@ -141,13 +143,16 @@ def test_c2_full_event_bit_exact(c2, c2_oracle):
     assert tracks_equal(g, p)
 
 
-def test_c2_persistent_inward_pass_bit_exact(c2, c2_oracle):
-    # the inward pass in its own persistent kernel: same stages bit for bit,
-    # with a full grid and with a grid of a few waves that drains all eight queues
+def test_c2_split_inward_pass_bit_exact(c2, c2_oracle):
+    # the single tracklet kernel, and the inward pass in its own kernel: ordered
+    # by the row the outward pass reached (the default at 64 threads, here at
+    # 256), and persistent with a full grid and with a grid of a few waves that
+    # drains all eight queues; same stages bit for bit
     from paper_1811_11481_amd import default_tuning
-    for wgs in (1024, 5):
-        log("C2 batched, inward pass in %d persistent workgroups" % wgs)
-        g = run_gpu(c2, tuning=default_tuning(inward_wgs=wgs))
+    for tune in (dict(inward_sort=0), dict(inward_sort=1, block_tracklet=256), dict(inward_wgs=1024),
+                 dict(inward_wgs=5)):
+        log("C2 batched, split inward pass %s" % tune)
+        g = run_gpu(c2, tuning=default_tuning(**tune))
         compare_with_oracle(g, c2_oracle)
 
 
