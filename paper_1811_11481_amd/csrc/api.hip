@@ -187,6 +187,7 @@ tpcca_status check_tuning(tpcca_ctx* ctx, const tpcca_tuning& t) {
     if (t.ckpt != 0 && t.ckpt != 1) return fail(ctx, TPCCA_E_ARG, "ckpt must be 0 or 1");
     if (t.inward_wgs < 0 || t.inward_wgs > 65536) return fail(ctx, TPCCA_E_ARG, "inward_wgs must be in [0, 65536]");
     if (t.inward_sort != 0 && t.inward_sort != 1) return fail(ctx, TPCCA_E_ARG, "inward_sort must be 0 or 1");
+    if (t.sort_seeds != 0 && t.sort_seeds != 1) return fail(ctx, TPCCA_E_ARG, "sort_seeds must be 0 or 1");
     return TPCCA_OK;
 }
 
@@ -445,8 +446,8 @@ GraphKey graph_key(const tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_t
                           out->residuals};
     std::memcpy(key.p, ps, sizeof(ps));
     const int64_t vs[10] = {in->n_inst, in->n_clusters, out->cap_tracks, out->cap_hits, mrow,
-                           ((ctx->tuning.inward_wgs * 2LL + ctx->tuning.inward_sort) * 64 + ctx->tuning.hits_per_bin) * 4 +
-                               ctx->tuning.xcd_remap * 2 + ctx->tuning.sort_seeds,
+                           ((ctx->tuning.inward_wgs * 2LL + ctx->tuning.inward_sort) * 64 + ctx->tuning.hits_per_bin) * 8 +
+                               ctx->tuning.xcd_remap * 4 + ctx->tuning.sort_seeds,
                            ctx->tuning.block_links * 100000LL + ctx->tuning.block_tracklet,
                            ctx->tuning.block_refit * 100000LL + ctx->tuning.block_scan,
                            (counts != nullptr ? 1 : 0) + 2 * native, out->residual_step_log2};
