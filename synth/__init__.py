@@ -6,17 +6,17 @@ oracle tests and the GPU path consume these arrays.
 Named workloads (seed = 1000 * config + event):
 
 * ``C1``  one A-side sector (sector 0), 200 helices from the origin with
-  0 < eta < 0.9 and phi0 uniform inside the sector, 1 % noise (~30 k clusters).
+  0 < eta < 0.9 and phi0 uniform inside the sector, 1 % noise (~10 k clusters).
 * ``C2``  a full central event: 36 sectors, 8000 primaries with |eta| < 0.9
   over the full azimuth plus 10 % secondaries with vertex radius U(0, 50) cm,
   2 % noise (~1.3 M clusters).
 * ``C3``  continuous-readout slice: 100 collisions with Exp(800) tracks each,
   pT truncated to [0.05, 10] GeV, drift shift U(0, 250) cm per collision,
-  2 % noise (~12 M clusters).
+  2 % noise (~9.9 M clusters).
 * ``C4``  256 sector instances of uneven occupancy: instance j is sector
-  j mod 36 with round(exp(U(ln 50, ln 2000))) helices, 1 % noise.
+  j mod 36 with round(exp(U(ln 50, ln 2000))) helices, 1 % noise (~6.6 M clusters).
 * ``C2x8`` eight central events (seeds 2000..2007 law, one generator call) in
-  288 instances.
+  288 instances (~10.9 M clusters).
 * ``C5``  twelve central events whose clusters are displaced by a smooth
   synthetic space-charge map (amplitude 0.5 cm) before the smear: the input
   of the differentiable refit.
