@@ -211,7 +211,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     Layout L;
     size_t o_yz = L.add(8 * N), o_sid = L.add(4 * N), o_pos = L.add(4 * N);
     size_t o_bs = L.add(4 * (N + nseg + 1)), o_hdr = L.add(sizeof(SegHdr) * nseg);
-    size_t o_up = L.add(4 * N), o_dn = L.add(4 * N), o_upc = L.add(4 * N), o_dnc = L.add(4 * N);
+    size_t o_up = L.add(4 * N), o_dn = L.add(4 * N), o_upc = L.add(4 * N), o_dnc = L.add(4 * N), o_sf = L.add(N);
     size_t o_st = L.add(4 * cap_s), o_sti = L.add(4 * cap_s), o_so = L.add(4 * cap_s), o_sl = L.add(4 * cap_s);
     size_t o_tn = L.add(4 * cap_s), o_tt = L.add(4 * cap_s), o_tr = L.add(4 * cap_s), o_ts = L.add(80 * cap_s);
     size_t o_tpp = L.add(4 * cap_s * nr), o_tpr = L.add((size_t)cap_s * nr);
@@ -236,6 +236,7 @@ void carve(tpcca_ctx* ctx, Bufs& b, int64_t N, int64_t nseg, int64_t ninst, bool
     b.dn = (int32_t*)(base + o_dn);
     b.upc = (int32_t*)(base + o_upc);
     b.dnc = (int32_t*)(base + o_dnc);
+    b.start_flag = (uint8_t*)(base + o_sf);
     b.cap_starts = cap_s;
     b.starts = (int32_t*)(base + o_st);
     b.start_inst = (int32_t*)(base + o_sti);

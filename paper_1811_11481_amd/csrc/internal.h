@@ -69,6 +69,7 @@ struct Bufs {
     int32_t* dn;
     int32_t* upc;
     int32_t* dnc;
+    uint8_t* start_flag; // [N] grid-position space: 1 at a start hit (written by the cleaning)
     // starts and tracklets
     int64_t cap_starts;
     int32_t* starts;     // grid position of the start hit

@@ -460,8 +460,18 @@ __global__ void k_clean(Bufs b, int64_t c0, int64_t c1) {
     for (int64_t p = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < c1;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t u = b.up[p], d = b.dn[p];
-        b.upc[p] = (u >= 0 && b.dn[u] == p) ? u : -1;
-        b.dnc[p] = (d >= 0 && b.up[d] == p) ? d : -1;
+        const int32_t uc = (u >= 0 && b.dn[u] == p) ? u : -1;
+        const int32_t dc = (d >= 0 && b.up[d] == p) ? d : -1;
+        b.upc[p] = uc;
+        b.dnc[p] = dc;
+        // a start hit: no cleaned link down, and cleaned links up twice (the
+        // next hit's cleaned up link, from the same uncleaned links)
+        bool start = false;
+        if (dc == -1 && uc != -1) {
+            const int32_t w = b.up[uc];
+            start = w >= 0 && b.dn[w] == uc;
+        }
+        b.start_flag[p] = start ? 1 : 0;
     }
 }
 
@@ -496,8 +506,15 @@ __device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long
     return r;
 }
 
+// Elements per thread and tile of the scan kernels, Op::kVec: a thread takes
+// kVec consecutive elements, so their value() loads are in flight together
+// and a block-wide scan runs once per tile of kVec * blockDim elements (8 for
+// the start hits, a cheap value over every cluster; 1 where write() is heavy
+// and a block's chunk short).
+
 template <class Op>
 __global__ void k_scan_part(Op op, unsigned long long* part) {
+    constexpr int kScanVec = Op::kVec;
     __shared__ unsigned long long sh[17];
     if (input_rejected(op.b.ctr)) return;
     const int64_t b0 = op.begin(), e0 = op.end();
@@ -506,7 +523,13 @@ __global__ void k_scan_part(Op op, unsigned long long* part) {
     const int64_t lo = b0 + blockIdx.x * chunk;
     const int64_t hi = min(lo + chunk, e0);
     unsigned long long s = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += op.value(i);
+    for (int64_t t0 = lo + (int64_t)threadIdx.x * kScanVec; t0 < hi; t0 += (int64_t)blockDim.x * kScanVec) {
+        unsigned long long v[kScanVec];
+#pragma unroll
+        for (int k = 0; k < kScanVec; ++k) v[k] = (t0 + k < hi) ? op.value(t0 + k) : 0ull;
+#pragma unroll
+        for (int k = 0; k < kScanVec; ++k) s += v[k];
+    }
     unsigned long long tot;
     block_excl_scan(s, sh, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -531,6 +554,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* part, Cou
 
 template <class Op>
 __global__ void k_scan_apply(Op op, const unsigned long long* part, const Counters* ctr, int slot) {
+    constexpr int kScanVec = Op::kVec;
     __shared__ unsigned long long sh[17];
     if (input_rejected(ctr)) return;
     const int64_t b0 = op.begin(), e0 = op.end();
@@ -538,44 +562,66 @@ __global__ void k_scan_apply(Op op, const unsigned long long* part, const Counte
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = b0 + blockIdx.x * chunk;
     const int64_t hi = min(lo + chunk, e0);
+    const int64_t tile = (int64_t)blockDim.x * kScanVec;
     unsigned long long run = ctr->slot[slot][1] + part[blockIdx.x];
-    for (int64_t t0 = lo; t0 < hi; t0 += blockDim.x) {  // uniform trip count per block
-        const int64_t i = t0 + threadIdx.x;
-        const unsigned long long v = (i < hi) ? op.value(i) : 0ull;
+    // per-block context for write() (the start hits: the instance of the
+    // block's first cluster, found once)
+    __shared__ int s_hint;
+    if (threadIdx.x == 0) s_hint = lo < hi ? op.hint(lo) : 0;
+    __syncthreads();
+    const int hint = s_hint;
+    for (int64_t t0 = lo; t0 < hi; t0 += tile) {  // uniform trip count per block
+        const int64_t i0 = t0 + (int64_t)threadIdx.x * kScanVec;  // this thread's consecutive elements
+        unsigned long long v[kScanVec], s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanVec; ++k) {
+            v[k] = (i0 + k < hi) ? op.value(i0 + k) : 0ull;
+            s += v[k];
+        }
         unsigned long long tot;
-        const unsigned long long ex = block_excl_scan(v, sh, &tot);
-        if (i < hi && v) op.write(i, run + ex, v);
+        unsigned long long ex = block_excl_scan(s, sh, &tot);
+#pragma unroll
+        for (int k = 0; k < kScanVec; ++k) {
+            if (v[k]) op.write(i0 + k, run + ex, v[k], hint);
+            ex += v[k];
+        }
         run += tot;
     }
 }
 
 // Start hits, over cluster ids [c0, c1) of an instance range.
 struct StartOp {
+    static constexpr int kVec = 8;
     Bufs b;
     int64_t c0, c1;
     int i0, i1;
     __device__ int64_t begin() const { return c0; }
     __device__ int64_t end() const { return c1; }
-    __device__ unsigned long long value(int64_t id) const {
-        const int32_t p = b.pos_of[id];
-        const int32_t u = b.upc[p];
-        return (b.dnc[p] == -1 && u != -1 && b.upc[u] != -1) ? 1ull : 0ull;
-    }
-    __device__ void write(int64_t id, unsigned long long prefix, unsigned long long) const {
-        const int64_t j = (int64_t)(prefix & 0xFFFFFFFFull);
-        if (j >= b.cap_starts) {
-            raise_err(b.ctr, ERR_SCRATCH);
-            return;
-        }
-        const int nr = b.K->n_rows;
-        int lo = i0, hi = i1;  // instance: last k with row_start[k*nr] <= id
+    __device__ unsigned long long value(int64_t id) const { return b.start_flag[b.pos_of[id]]; }
+    // instance of cluster id: the last k with row_start[k * n_rows] <= id
+    __device__ int hint(int64_t id) const {
+        const int nr = b.n_rows;
+        int lo = i0, hi = i1;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (b.row_start[(int64_t)mid * nr] <= id) lo = mid;
             else hi = mid;
         }
+        return lo;
+    }
+    // inst0: the instance of an earlier cluster of the block's chunk (a chunk
+    // rarely crosses an instance boundary, so this walks at most a few steps)
+    __device__ void write(int64_t id, unsigned long long prefix, unsigned long long, int inst0) const {
+        const int64_t j = (int64_t)(prefix & 0xFFFFFFFFull);
+        if (j >= b.cap_starts) {
+            raise_err(b.ctr, ERR_SCRATCH);
+            return;
+        }
+        const int nr = b.n_rows;
+        int inst = inst0;
+        while (inst + 1 < i1 && b.row_start[(int64_t)(inst + 1) * nr] <= id) ++inst;
         b.starts[j] = b.pos_of[id];
-        b.start_inst[j] = lo;
+        b.start_inst[j] = inst;
     }
 };
 
@@ -585,6 +631,7 @@ __device__ __forceinline__ uint32_t packed_weight(int nh, int tid) {
 }
 
 struct SelectOp {
+    static constexpr int kVec = 1;
     Bufs b;
     __device__ int64_t begin() const { return (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull); }
     __device__ int64_t end() const {
@@ -595,7 +642,8 @@ struct SelectOp {
         const int own = b.tl_own[j];
         return own >= b.K->n_min ? ((1ull << 32) | (unsigned long long)own) : 0ull;
     }
-    __device__ void write(int64_t j, unsigned long long prefix, unsigned long long v) const {
+    __device__ int hint(int64_t) const { return 0; }
+    __device__ void write(int64_t j, unsigned long long prefix, unsigned long long v, int) const {
         const int64_t si = (int64_t)(prefix >> 32);
         const int64_t ho = (int64_t)(prefix & 0xFFFFFFFFull);
         const int own = (int)(v & 0xFFFFFFFFull);
@@ -706,6 +754,7 @@ __device__ __forceinline__ float vertex_z(double kB, double x, const float* p) {
 
 // Output tracks, over the current range of selected tracklets.
 struct TrackOp {
+    static constexpr int kVec = 1;
     Bufs b;
     __device__ int64_t begin() const { return (int64_t)(b.ctr->slot[SL_SEL][1] >> 32); }
     __device__ int64_t end() const {
@@ -715,7 +764,8 @@ struct TrackOp {
     __device__ unsigned long long value(int64_t si) const {
         return b.rf_ok[si] ? ((1ull << 32) | (unsigned long long)b.rf_nacc[si]) : 0ull;
     }
-    __device__ void write(int64_t si, unsigned long long prefix, unsigned long long v) const {
+    __device__ int hint(int64_t) const { return 0; }
+    __device__ void write(int64_t si, unsigned long long prefix, unsigned long long v, int) const {
         const int64_t t = (int64_t)(prefix >> 32);
         const int64_t ho = (int64_t)(prefix & 0xFFFFFFFFull);
         const int nacc = (int)(v & 0xFFFFFFFFull);
