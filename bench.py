@@ -260,8 +260,9 @@ def next_leg(torch, np, synth, cs, dc, warmup, steps):
     """The steps that follow the sector tracking, each timed on the headline
     workload (device time around the call, inputs resident): the cross-sector
     merge after a track call (its one count read-back included), the batched
-    track call on native (pad, time) clusters, and the batched track call that
-    also writes the compression residuals (every call writes z0)."""
+    track call on native (pad, time) clusters, the corrected final fit of a
+    track call's tracks, and the batched track call that also writes the
+    compression residuals (every call writes z0)."""
     from paper_1811_11481_amd import FLAG_MERGE, DeviceNativeClusters, Tracker, default_params
 
     def timed(fn):
@@ -302,12 +303,28 @@ def next_leg(torch, np, synth, cs, dc, warmup, steps):
     res["native_input"] = {"ms_per_step": round(nms, 4), "clusters_per_s": round(cs.n_clusters / (nms * 1e-3), 1),
                            "n_tracks": out.n_tracks}
     del dn, out
+    # corrected final fit: clusters moved to each track's absolute frame and
+    # corrected by a random smooth map, three passes again (the track call's
+    # outputs stay alive for it)
+    rng = np.random.default_rng(11)
+    coef = torch.as_tensor((0.1 * rng.standard_normal(3 * 16 * 16 * 32)).astype(np.float32), device="cuda")
+    out = trk.alloc_tracks(dc)
+    trk.track(dc, out, batched=True)
+    cst = {}
+
+    def do_corr():
+        cst["g"] = trk.fit_corrected(coef=coef)
+
+    cms = timed(do_corr)
+    res["corrected_fit"] = {"ms": round(cms, 4), "n_tracks": out.n_tracks,
+                            "n_fitted": int((cst["g"]["ndf"] >= 0).sum().item())}
+    del cst, out
     # compression residuals (int16 per cluster and coordinate, step 2^-7 cm)
     out = trk.alloc_tracks(dc).want_residuals(-7)
     rms = timed(lambda: trk.track(dc, out, batched=True))
     res["residuals"] = {"ms_per_step": round(rms, 4), "n_tracks": out.n_tracks, "n_hits": out.n_hits}
-    print("[bench] next steps: merge %.3f ms, native %.3f ms/step, residuals %.3f ms/step"
-          % (mms, nms, rms), file=sys.stderr, flush=True)
+    print("[bench] next steps: merge %.3f ms, native %.3f ms/step, corrected fit %.3f ms, residuals %.3f ms/step"
+          % (mms, nms, cms, rms), file=sys.stderr, flush=True)
     return res
 
 

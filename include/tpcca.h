@@ -410,6 +410,29 @@ tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* clusters, con
 tpcca_status tpcca_refit_bwd(tpcca_ctx* ctx, const float* grad_chi2, double* grad_params0, double* grad_map,
                              double* grad_hit_yz, void* hip_stream);
 
+/* Corrected final fit of the tracks of the last synchronous track call on ctx
+ * (Section 4, continuous readout: with a track's vertex z, i.e. its collision
+ * time, estimated, the space-point correction, which depends on the absolute
+ * z, can be applied, and the track is fitted again). Per track: its output
+ * clusters and its output state are moved to the absolute frame (z - z0), the
+ * clusters corrected by the map in the form of tpcca_refit_fwd (none if
+ * map_coef is NULL), and the three passes of the final fit (covariance reset,
+ * chi2 <= chi2_rej acceptance) run again from that state. That call must have
+ * written z0 (out->z0 not NULL); its inputs and outputs must still be valid.
+ * Outputs (device, caller-owned, per track of that call): param [n*5] (z
+ * absolute), cov [n*15], chi2 [n] (last pass), ndf [n] (2 accepted - 5, or -1
+ * when a row step fails or fewer than n_min clusters are kept; the other
+ * outputs of that track are then unspecified), x_ref [n], z0 [n] (refined:
+ * the old z0 plus the closest approach of the new state), masks [n_hits] or
+ * NULL (bit p: cluster used in pass p), hit_yz [n_hits * 2] or NULL (the
+ * corrected coordinates, absolute z, binary32). Uses the differentiable refit's
+ * scratch (a recorded forward is dropped). Does not synchronise. Errors:
+ * TPCCA_E_ARG (no usable last call or no z0, null outputs), TPCCA_E_DEVICE,
+ * TPCCA_E_OOM. */
+tpcca_status tpcca_fit_corrected(tpcca_ctx* ctx, const float* map_coef, float* param, float* cov, float* chi2,
+                                 int32_t* ndf, float* x_ref, float* z0, uint8_t* masks, float* hit_yz,
+                                 void* hip_stream);
+
 /* Arithmetic self-check: out_div[i] = a[i] / b[i], out_sqrt[i] = sqrt(|a[i]|) with the
  * library's binary32 operations (for bit comparison with a CPU). Synchronous. */
 tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div, float* out_sqrt, int64_t n,

@@ -110,6 +110,8 @@ def lib():
         L.orc_track_decode.argtypes = [ctypes.POINTER(Params), vp, i32, i32, vp, vp, i32, vp, vp]
         L.orc_vertex_z.restype = dbl
         L.orc_vertex_z.argtypes = [ctypes.POINTER(Params), dbl, vp]
+        L.orc_fit_corrected.restype = None
+        L.orc_fit_corrected.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 16
         L.orc_native_to_local.restype = None
         L.orc_native_to_local.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
         _lib = L
@@ -540,3 +542,28 @@ def native_to_local(n_rows, inst_sector, row_start, pad, time, geo=None):
     lib().orc_native_to_local(int(n_rows), len(sec), _ptr(sec), _ptr(rs), _ptr(pw), _ptr(pc),
                               float(geo["z_per_bin"]), float(geo["z_readout"]), _ptr(pad), _ptr(time), _ptr(y), _ptr(z))
     return y, z
+
+
+def fit_corrected(st0, row0, z0, alpha, hit_start, hit_rows, ys, zs, coef=None, params=None):
+    """FP64 corrected final fit (orc_fit_corrected): per track, clusters and
+    start state moved to the absolute frame by the track's vertex z, clusters
+    corrected by the map (coef [3*16*16*32] or None), three passes with chi2
+    rejection. Returns dict(ok, state [n,20], chi2, nacc, row, z0, masks)."""
+    p = params if params is not None else default_params(planes_f32=1)
+    st0 = np.ascontiguousarray(st0, np.float64)
+    n = len(st0)
+    row0 = np.ascontiguousarray(row0, np.int32)
+    z0 = np.ascontiguousarray(z0, np.float64)
+    alpha = np.ascontiguousarray(alpha, np.float64)
+    hs = np.ascontiguousarray(hit_start, np.int64)
+    rows = np.ascontiguousarray(hit_rows, np.int32)
+    ys = np.ascontiguousarray(ys, np.float64)
+    zs = np.ascontiguousarray(zs, np.float64)
+    cf = None if coef is None else np.ascontiguousarray(coef, np.float64)
+    out = dict(state=np.zeros((n, 20)), chi2=np.zeros(n), nacc=np.zeros(n, np.int32), row=np.zeros(n, np.int32),
+               z0=np.zeros(n), ok=np.zeros(n, np.int32), masks=np.zeros(max(len(rows), 1), np.uint8))
+    lib().orc_fit_corrected(ctypes.byref(p), n, _ptr(st0), _ptr(row0), _ptr(z0), _ptr(alpha), _ptr(hs), _ptr(rows),
+                            _ptr(ys), _ptr(zs), _ptr(cf), _ptr(out["state"]), _ptr(out["chi2"]), _ptr(out["nacc"]),
+                            _ptr(out["row"]), _ptr(out["z0"]), _ptr(out["ok"]), _ptr(out["masks"]))
+    out["masks"] = out["masks"][:len(rows)]
+    return out

@@ -1673,6 +1673,47 @@ double orc_vertex_z(const orc_params* p, double x, const double* state5) {
     return z + tl * s;
 }
 
+// The corrected final fit of continuous readout (Section 4: a track's vertex z
+// from its closest approach to the beam line stands for the collision time;
+// with it known, the space-point correction, which depends on the absolute z,
+// can be applied, and the track is fitted again). Per track: the clusters and
+// the start state are moved to the absolute frame (z - z0), the clusters
+// corrected by the map inside their pad-row planes (none if coef is null),
+// and the three passes of the final fit run with chi2 rejection from the
+// start state at its row. Outputs: state, chi2 and count of the last pass's
+// accepted clusters, the row of the output state, the refined vertex z (z0
+// plus the closest approach of the new state) and the accept masks.
+void orc_fit_corrected(const orc_params* p, int64_t n_tracks, const double* st0, const int32_t* row0,
+                       const double* z0, const double* alpha, const int64_t* hit_start, const int32_t* hit_rows,
+                       const double* ys, const double* zs, const double* coef, double* st_out, double* chi2_out,
+                       int32_t* nacc_out, int32_t* row_out, double* z0_out, int32_t* ok_out, uint8_t* mask_out) {
+    Consts<double> k(*p);
+    for (int64_t t = 0; t < n_tracks; ++t) {
+        State<double> s;
+        load_state(st0 + 20 * t, s);
+        s.p[1] = s.p[1] - z0[t];
+        const int64_t a = hit_start[t];
+        const int n = (int)(hit_start[t + 1] - a);
+        std::vector<double> yc(n), zc(n);
+        for (int i = 0; i < n; ++i) {
+            const double za = zs[a + i] - z0[t];
+            if (coef) correct_cluster(coef, alpha[t], k.X[hit_rows[a + i]], ys[a + i], za, &yc[i], &zc[i]);
+            else {
+                yc[i] = ys[a + i];
+                zc[i] = za;
+            }
+        }
+        RefitOut<double> o = refit(k, s, row0[t], n, hit_rows + a, yc.data(), zc.data(), mask_out + a, nullptr);
+        ok_out[t] = o.ok ? 1 : 0;
+        if (!o.ok) continue;
+        store_state(o.s, st_out + 20 * t);
+        chi2_out[t] = o.chi2;
+        nacc_out[t] = o.nacc;
+        row_out[t] = o.row;
+        z0_out[t] = z0[t] + orc_vertex_z(p, k.X[o.row], st_out + 20 * t);
+    }
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- track-model compression

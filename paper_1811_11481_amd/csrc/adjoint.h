@@ -86,6 +86,37 @@ void enqueue_refit_total(const AdjBufs& a, hipStream_t st);
 // one recomputed pass segment, whose adjoint is carried to the next (earlier)
 // segment in a.carry.
 void enqueue_refit_reverse(const AdjBufs& a, int64_t t0, int64_t t1, int seg, hipStream_t st);
+// The corrected final fit of the last track call's tracks (tpcca_fit_corrected).
+struct CorrBufs {
+    const DevConsts* K;
+    int n_rows;
+    const int32_t* inst_sector;
+    const int64_t* row_start;
+    const float2* yz;        // grid coordinates of the last call
+    const int32_t* pos_of;   // grid position of each cluster id
+    int64_t n_tracks, n_hits;
+    const int32_t* inst;     // the last call's outputs
+    const float* param;
+    const float* cov;
+    const float* xref;
+    const float* z0;
+    const int64_t* hit_start;
+    const int32_t* hit_id;
+    const float* coef;       // may be null: no correction
+    float2* cyz;             // scratch [n_hits]: corrected coordinates, absolute frame
+    uint8_t* crow;           // scratch [n_hits]: pad row
+    float* o_param;          // outputs
+    float* o_cov;
+    float* o_chi2;
+    int32_t* o_ndf;
+    float* o_xref;
+    float* o_z0;
+    uint8_t* o_mask;         // may be null
+    float* o_hit_yz;         // may be null: corrected coordinates [n_hits * 2]
+};
+
+void enqueue_fit_corrected(const CorrBufs& c, hipStream_t st);
+
 // Map gradient (grad_map) and per-cluster gradient (sum over passes) from the
 // reverse sweeps; the map gradient uses map_grad_scratch_bytes(n_hits) of scratch.
 size_t map_grad_scratch_bytes(int64_t n_hits);

@@ -89,6 +89,27 @@ __device__ __forceinline__ ClusterGeo cluster_geo(const AdjBufs& a, int row, int
     return g;
 }
 
+// The cluster (y, z) of geometry g moved by the map: (delta r, delta r*phi,
+// delta z) at (r, phi, z), applied inside the pad-row plane.
+__device__ __forceinline__ void map_correct(const float* coef, const ClusterGeo& g, float& y, float& z) {
+    const MapCell c = map_cell(g.r, g.phi, z);
+    float d[3];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        float acc = 0.0f;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                const float wij = c.wr[i] * c.wphi[j];
+                const float* cf = coef + map_index(comp, c.ir + i, c.iphi + j, c.iz);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc = acc + (wij * c.wz[e]) * cf[e];
+            }
+        d[comp] = acc;
+    }
+    y = y - (d[0] * y + d[1] * g.x) / g.r;
+    z = z - d[2];
+}
+
 // ------------------------------------------------------------ tape
 enum : int { OP_PROP = 1, OP_RESET = 2, OP_UPD = 3 };
 
@@ -407,22 +428,7 @@ __global__ void k_map_correct(AdjBufs a) {
         float y = a.y[id], z = a.z[id];
         if (a.coef) {
             const ClusterGeo g = cluster_geo(a, lo, inst, y);
-            const MapCell c = map_cell(g.r, g.phi, z);
-            float d[3];
-#pragma unroll
-            for (int comp = 0; comp < 3; ++comp) {
-                float acc = 0.0f;
-                for (int i = 0; i < 4; ++i)
-                    for (int j = 0; j < 4; ++j) {
-                        const float wij = c.wr[i] * c.wphi[j];
-                        const float* cf = a.coef + map_index(comp, c.ir + i, c.iphi + j, c.iz);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) acc = acc + (wij * c.wz[e]) * cf[e];
-                    }
-                d[comp] = acc;
-            }
-            y = y - (d[0] * y + d[1] * g.x) / g.r;
-            z = z - d[2];
+            map_correct(a.coef, g, y, z);
         }
         a.hit_yz[h] = make_float2(y, z);
     }
@@ -1019,6 +1025,158 @@ void enqueue_refit_hit_grad(const AdjBufs& a, double* out, hipStream_t st) {
     if (a.n_hits > 0)
         hipLaunchKernelGGL(k_hit_grad_out, dim3(blocks_for(a.n_hits, 256, 16384)), dim3(256), 0, st, a,
                            (double2*)out);
+}
+
+namespace {
+
+// Corrected final fit, first step: every output cluster of the last track
+// call in its track's absolute frame (z minus the track's vertex z) and
+// corrected by the map; one wave per track, one lane per cluster.
+__global__ __launch_bounds__(256) void k_corr_clusters(CorrBufs c) {
+    const DevConsts& K = *c.K;
+    const int nr = c.n_rows;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; t < c.n_tracks; t += nwave) {
+        const int32_t inst = c.inst[t];
+        const int64_t* rs = c.row_start + (int64_t)inst * nr;
+        const int sec = c.inst_sector[inst];
+        const float zv = c.z0[t];
+        for (int64_t q = c.hit_start[t] + lane; q < c.hit_start[t + 1]; q += 64) {
+            const int32_t id = c.hit_id[q];
+            int lo = 0, hi = nr;  // rs[lo] <= id < rs[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rs[mid] <= id) lo = mid;
+                else hi = mid;
+            }
+            const float2 p = c.yz[c.pos_of[id]];
+            float y = p.x, z = p.y - zv;
+            if (c.coef) {
+                ClusterGeo g;
+                g.x = K.X[lo];
+                g.r = __builtin_sqrtf(g.x * g.x + y * y);
+                g.phi = K.alpha[((sec % 18) + 18) % 18] + atan2f(y, g.x);
+                map_correct(c.coef, g, y, z);
+            }
+            c.cyz[q] = make_float2(y, z);
+            c.crow[q] = (uint8_t)lo;
+            if (c.o_hit_yz) {
+                c.o_hit_yz[2 * q] = y;
+                c.o_hit_yz[2 * q + 1] = z;
+            }
+        }
+    }
+}
+
+// Corrected final fit, second step: one lane per track, the three passes of
+// the final fit (covariance reset, chi2 rejection, reference point moved to
+// each accepted cluster) over the corrected clusters, from the track's output
+// state moved to the absolute frame; the next cluster is loaded one step
+// ahead. ndf = 2 accepted - 5, or -1 when a step fails or fewer than n_min
+// clusters are kept (the other outputs are then unspecified).
+__global__ __launch_bounds__(128) void k_fit_corrected(CorrBufs c) {
+    const DevConsts& K = *c.K;
+    const KfConsts kc = kf_consts(K);
+    __shared__ float sX[kMaxRows];
+    kf_load_rows(sX, K);
+    const int nr = c.n_rows;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < c.n_tracks;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t h0 = c.hit_start[t];
+        const int n = (int)(c.hit_start[t + 1] - h0);
+        const float zv = c.z0[t];
+        KState s;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s.p[q] = c.param[t * 5 + q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) s.C[q] = c.cov[t * 15 + q];
+        s.p[1] = s.p[1] - zv;
+        int cur = 0;  // the row of x_ref (pad-row planes ascending)
+        {
+            const float x = c.xref[t];
+            int lo = 0, hi = nr - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sX[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            cur = lo;
+        }
+        float ref_y = s.p[0], ref_z = s.p[1];
+        s.p[0] = 0.0f;
+        s.p[1] = 0.0f;
+        bool ok = n > 0;
+        const int outer = ok ? (int)c.crow[h0 + n - 1] : 0;
+        while (ok && cur != outer) {
+            const int nx = cur < outer ? cur + 1 : cur - 1;
+            if (!kf_propagate(s, sX[cur], sX[nx], kc)) ok = false;
+            else cur = nx;
+        }
+        if (c.o_mask)
+            for (int i = 0; i < n; ++i) c.o_mask[h0 + i] = 0;
+        float chi2sum = 0.0f;
+        int nacc = 0;
+        for (int pass = 0; pass < 3 && ok; ++pass) {
+            kf_reset(s, kc);
+            const bool inward = pass != 1;
+            int i_n = inward ? n - 1 : 0;
+            int t_n = c.crow[h0 + i_n];
+            float2 c_n = c.cyz[h0 + i_n];
+            for (int q = 0; q < n && ok; ++q) {
+                const int i = i_n, target = t_n;
+                const float2 cc = c_n;
+                if (q + 1 < n) {
+                    i_n = inward ? n - 2 - q : q + 1;
+                    t_n = c.crow[h0 + i_n];
+                    c_n = c.cyz[h0 + i_n];
+                }
+                while (cur != target) {
+                    const int nx = cur < target ? cur + 1 : cur - 1;
+                    if (!kf_propagate(s, sX[cur], sX[nx], kc)) {
+                        ok = false;
+                        break;
+                    }
+                    cur = nx;
+                }
+                if (!ok) break;
+                const Innov inn = kf_innovation(s, cc.x - ref_y, cc.y - ref_z, kc);
+                if (inn.chi2 <= kc.chi2_rej) {
+                    kf_update(s, inn);
+                    s.p[0] = s.p[0] + (ref_y - cc.x);
+                    s.p[1] = s.p[1] + (ref_z - cc.y);
+                    ref_y = cc.x;
+                    ref_z = cc.y;
+                    if (c.o_mask) c.o_mask[h0 + i] = (uint8_t)(c.o_mask[h0 + i] | (1u << pass));
+                    if (pass == 2) {
+                        chi2sum = chi2sum + inn.chi2;
+                        ++nacc;
+                    }
+                }
+            }
+        }
+        s.p[0] = ref_y + s.p[0];
+        s.p[1] = ref_z + s.p[1];
+        ok = ok && nacc >= kc.n_min;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) c.o_param[t * 5 + q] = s.p[q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) c.o_cov[t * 15 + q] = s.C[q];
+        c.o_chi2[t] = chi2sum;
+        c.o_ndf[t] = ok ? 2 * nacc - 5 : -1;
+        c.o_xref[t] = sX[cur];
+        c.o_z0[t] = ok ? zv + vertex_z(K.kB_f64, (double)sX[cur], s.p) : zv;
+    }
+}
+
+}  // namespace
+
+void enqueue_fit_corrected(const CorrBufs& c, hipStream_t st) {
+    if (c.n_tracks <= 0) return;
+    const int64_t w = c.n_tracks * 64;
+    const int64_t g1 = (w + 255) / 256, g2 = (c.n_tracks + 127) / 128;
+    hipLaunchKernelGGL(k_corr_clusters, dim3((unsigned)(g1 < 16384 ? g1 : 16384)), dim3(256), 0, st, c);
+    hipLaunchKernelGGL(k_fit_corrected, dim3((unsigned)(g2 < 16384 ? g2 : 16384)), dim3(128), 0, st, c);
 }
 
 }  // namespace tpcca

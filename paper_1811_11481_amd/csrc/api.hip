@@ -1217,6 +1217,58 @@ tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div
     return TPCCA_OK;
 }
 
+tpcca_status tpcca_fit_corrected(tpcca_ctx* ctx, const float* map_coef, float* param, float* cov, float* chi2,
+                                 int32_t* ndf, float* x_ref, float* z0, uint8_t* masks, float* hit_yz,
+                                 void* hip_stream) {
+    if (!ctx) return TPCCA_E_ARG;
+    if (!ctx->has_last) return fail(ctx, TPCCA_E_ARG, "tpcca_fit_corrected needs a completed synchronous track call");
+    const Bufs& lb = ctx->last;
+    if (!lb.o_z0) return fail(ctx, TPCCA_E_ARG, "the last track call did not write z0");
+    const unsigned long long tot = ctx->last_ctr.slot[SL_TRK][0];
+    const int64_t nt = (int64_t)(tot >> 32), nh = (int64_t)(tot & 0xFFFFFFFFull);
+    if (nt > lb.cap_tracks || nh > lb.cap_hits)
+        return fail(ctx, TPCCA_E_ARG, "the last track call did not fit its outputs");
+    if (nt > 0 && (!param || !cov || !chi2 || !ndf || !x_ref || !z0))
+        return fail(ctx, TPCCA_E_ARG, "null output arrays");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->adj_valid = false;  // its scratch is reused
+    tpcca_status s = ensure_adj_arena(ctx, std::max<int64_t>(nt, 1), std::max<int64_t>(nh, 1));
+    if (s != TPCCA_OK) return s;
+    const AdjLayout L = adj_layout(ctx->adj_cap_t, ctx->adj_cap_h);
+    char* base = (char*)ctx->adj_base;
+    CorrBufs c{};
+    c.K = ctx->dK;
+    c.n_rows = ctx->params.n_rows;
+    c.inst_sector = lb.inst_sector;
+    c.row_start = lb.row_start;
+    c.yz = lb.yz;
+    c.pos_of = lb.pos_of;
+    c.n_tracks = nt;
+    c.n_hits = nh;
+    c.inst = lb.o_inst;
+    c.param = lb.o_param;
+    c.cov = lb.o_cov;
+    c.xref = lb.o_xref;
+    c.z0 = lb.o_z0;
+    c.hit_start = lb.o_hit_start;
+    c.hit_id = lb.o_hit_id;
+    c.coef = map_coef;
+    c.cyz = (float2*)(base + L.o_yz);
+    c.crow = (uint8_t*)(base + L.o_row);
+    c.o_param = param;
+    c.o_cov = cov;
+    c.o_chi2 = chi2;
+    c.o_ndf = ndf;
+    c.o_xref = x_ref;
+    c.o_z0 = z0;
+    c.o_mask = masks;
+    c.o_hit_yz = hit_yz;
+    enqueue_fit_corrected(c, st);
+    HIP_TRY(hipGetLastError());
+    return TPCCA_OK;
+}
+
 tpcca_status tpcca_refit_fwd(tpcca_ctx* ctx, const tpcca_clusters* in, const tpcca_refit_set* set,
                              const float* map_coef, float* chi2_track, int32_t* track_ok, double* chi2_total,
                              int32_t record, void* hip_stream) {

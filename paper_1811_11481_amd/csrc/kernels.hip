@@ -728,29 +728,6 @@ __global__ void k_sel_fill(Bufs b) {
     }
 }
 
-// z of the point of closest approach of the helix (state p at local x) to
-// the beam line, the z axis of every sector frame: the turning angle d from
-// the state solves A cos d + (B + 1/c) sin d = 0 with A = x cos phi + y sin phi,
-// B = -x sin phi + y cos phi and curvature c = kB q/pT, so d = atan2(-A c,
-// 1 + B c) and z0 = z + tan(lambda) d / c (as A/(1 + B c) atan(w)/w, w = -A c /
-// (1 + B c), where 1 + B c > 0: exact in the straight-line limit). FP64: a
-// derived output, evaluated once per track, not part of the Kalman filter.
-__device__ __forceinline__ float vertex_z(double kB, double x, const float* p) {
-    const double y = p[0], z = p[1], sp = p[2], tl = p[3], q = p[4];
-    const double cp = sqrt(1.0 - sp * sp);
-    const double c = kB * q;
-    const double A = x * cp + y * sp, B = -x * sp + y * cp;
-    const double den = 1.0 + B * c;
-    double s;
-    if (den > 0.0) {
-        const double w = -A * c / den;
-        const double g = (w == 0.0) ? 1.0 : atan(w) / w;
-        s = -A / den * g;
-    } else {
-        s = atan2(-A * c, den) / c;
-    }
-    return (float)(z + tl * s);
-}
 
 // Output tracks, over the current range of selected tracklets.
 struct TrackOp {

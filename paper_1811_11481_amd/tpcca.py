@@ -33,7 +33,7 @@ EXPORTED = [
     "tpcca_track_async_noalloc", "tpcca_merge", "tpcca_track_native", "tpcca_native_to_local", "tpcca_autotune",
     "tpcca_export_sizes", "tpcca_export_grid", "tpcca_export_links", "tpcca_export_tracklets",
     "tpcca_export_selected", "tpcca_get_stats", "tpcca_get_stage_times", "tpcca_fp32_selfcheck",
-    "tpcca_refit_fwd", "tpcca_refit_bwd",
+    "tpcca_refit_fwd", "tpcca_refit_bwd", "tpcca_fit_corrected",
 ]
 
 
@@ -227,6 +227,8 @@ def load():
         L.tpcca_refit_fwd.restype = st
         L.tpcca_refit_fwd.argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(RefitSetC), vp, vp, vp, vp,
                                       i32, vp]
+        L.tpcca_fit_corrected.restype = st
+        L.tpcca_fit_corrected.argtypes = [vp] * 11
         L.tpcca_refit_bwd.restype = st
         L.tpcca_refit_bwd.argtypes = [vp] * 6
         _lib = L
@@ -499,6 +501,37 @@ class Tracker:
                                          _stream(stream)))
         out.n_tracks, out.n_hits = int(c.n_tracks), int(c.n_hits)
         return out, nseg[:out.n_tracks], nxt[:nt]
+
+    def fit_corrected(self, coef=None, want_masks: bool = False, want_yz: bool = False, stream=None) -> dict:
+        """Corrected final fit of the last synchronous track call's tracks (their
+        output, z0 included, must still be alive): clusters and states moved to
+        the absolute frame by each track's z0 and corrected by the map coef
+        (float32 device tensor [3*16*16*32] or None). Returns device tensors
+        param [n,5], cov [n,15], chi2, ndf (-1: failed), x_ref, z0 and, with
+        want_masks / want_yz, the accept masks and the corrected (y, z) per
+        output cluster."""
+        torch = _torch()
+        sz = self.sizes()
+        nt, nh = sz["n_tracks"], sz["n_track_hits"]
+        dev = "cuda"
+        o = {"param": torch.empty(max(nt, 1) * 5, dtype=torch.float32, device=dev),
+             "cov": torch.empty(max(nt, 1) * 15, dtype=torch.float32, device=dev),
+             "chi2": torch.empty(max(nt, 1), dtype=torch.float32, device=dev),
+             "ndf": torch.empty(max(nt, 1), dtype=torch.int32, device=dev),
+             "x_ref": torch.empty(max(nt, 1), dtype=torch.float32, device=dev),
+             "z0": torch.empty(max(nt, 1), dtype=torch.float32, device=dev)}
+        masks = torch.empty(max(nh, 1), dtype=torch.uint8, device=dev) if want_masks else None
+        yz = torch.empty(max(nh, 1) * 2, dtype=torch.float32, device=dev) if want_yz else None
+        self._check(self.lib.tpcca_fit_corrected(self.h, _ptr(coef), _ptr(o["param"]), _ptr(o["cov"]), _ptr(o["chi2"]),
+                                                 _ptr(o["ndf"]), _ptr(o["x_ref"]), _ptr(o["z0"]), _ptr(masks), _ptr(yz),
+                                                 _stream(stream)))
+        out = {"param": o["param"][:nt * 5].view(nt, 5), "cov": o["cov"][:nt * 15].view(nt, 15),
+               "chi2": o["chi2"][:nt], "ndf": o["ndf"][:nt], "x_ref": o["x_ref"][:nt], "z0": o["z0"][:nt]}
+        if want_masks:
+            out["masks"] = masks[:nh]
+        if want_yz:
+            out["hit_yz"] = yz[:2 * nh].view(nh, 2)
+        return out
 
     def autotune(self, clusters: DeviceClusters, repeats: int = 3, stream=None) -> Tuning:
         t = Tuning()
