@@ -144,6 +144,28 @@ def measured_issue(kernel: str, workload: str, launch_ms: float):
             "busy_frac": round(n * 4 / (1024 * 2.4e9 * launch_ms * 1e-3), 4)}
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Device copy bandwidth measured here (read + write of a mib-MiB buffer,
+    HIP events around each copy, best of reps): the attainable counterpart of
+    the 8 TB/s vendor peak."""
+    n = mib * (1 << 18)
+    src = torch.empty(n, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2.0 * n * 4 / (best * 1e-3) / 1e9
+
+
 def stage_kernels(stage, tuning):
     """The kernels one launch of a stage runs (their times add up to the
     stage's event-timed duration)."""
@@ -410,6 +432,9 @@ def main():
         print("[bench] plain: %.3f ms/step" % plain_ms, file=sys.stderr, flush=True)
 
     stages, roofline = stage_roofline(trk, dc, cs, args.workload, args.warmup, args.steps)
+    copy_gbs = copy_bandwidth(torch)
+    roofline["copy_measured_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 5)
     print("[bench] stages (ms): %s" % {k: v["ms"] for k, v in stages.items()}, file=sys.stderr, flush=True)
 
     extra = {}
@@ -463,13 +488,21 @@ def main():
         oracle.run(one, 32, threads=1)
         dt1 = time.perf_counter() - c1
         print("[bench] cpu oracle (1 thread, %d instances): %.2fs" % (one.n_inst, dt1), file=sys.stderr, flush=True)
+        # the binary64 oracle on the same one-event sample, one thread (context)
+        c2 = time.perf_counter()
+        oracle.run(one, 64, threads=1)
+        dt2 = time.perf_counter() - c2
+        print("[bench] cpu oracle binary64 (1 thread, %d instances): %.2fs" % (one.n_inst, dt2), file=sys.stderr,
+              flush=True)
         cpu = {"value": round(sample.n_clusters / dt, 1), "unit": "clusters/s", "cores": nthr, "kind": "oracle",
                "sample": "%s (%d clusters), binary32 oracle, %d worker threads over sector instances"
                          % (note, sample.n_clusters, nthr),
                "seconds": round(dt, 3), "tracks_per_s": round(r.n_tracks / dt, 1),
                "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
                "single_thread": {"clusters_per_s": round(one.n_clusters / dt1, 1), "seconds": round(dt1, 3),
-                                 "sample": "first %d instances (%d clusters)" % (one.n_inst, one.n_clusters)}}
+                                 "sample": "first %d instances (%d clusters)" % (one.n_inst, one.n_clusters)},
+               "single_thread_binary64": {"clusters_per_s": round(one.n_clusters / dt2, 1),
+                                          "seconds": round(dt2, 3)}}
 
     line = {
         "metric": METRIC,
