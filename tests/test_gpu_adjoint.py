@@ -103,12 +103,50 @@ def _scaled_err(g, ref, scale):
     return np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)
 
 
+def _subset(rset, idx):
+    """A refit set of the tracks idx (their cluster lists gathered into one CSR)."""
+    import torch
+
+    from paper_1811_11481_amd import RefitSet
+    hs = rset.hit_start.cpu().numpy()
+    lens = np.diff(hs)[idx]
+    cl = np.concatenate([np.arange(hs[t], hs[t + 1]) for t in idx])
+    ti = torch.as_tensor(np.asarray(idx, np.int64), device="cuda")
+    ci = torch.as_tensor(cl, device="cuda")
+    return RefitSet(rset.params0[ti].contiguous(), rset.cov0[ti].contiguous(), rset.row0[ti].contiguous(),
+                    rset.inst[ti].contiguous(),
+                    torch.as_tensor(np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), device="cuda"),
+                    rset.hit_id[ci].contiguous(), rset.hit_mask[ci].contiguous())
+
+
 @pytest.mark.parametrize("f64", [False, True])
 def test_gradients_against_fp64_finite_differences(c1_setup, f64):
+    cs, _, dc, _, rset = c1_setup
+    _fd_check(cs, dc, rset, f64)
+
+
+def test_gradients_against_fp64_finite_differences_central_event():
+    # every 40th track of the central event: all 36 sectors, both sides, the
+    # map's full phi and z range
+    from paper_1811_11481_amd import DeviceClusters, RefitSet, Tracker
+    cs = synth.generate("C2")
+    trk = Tracker()
+    dc = DeviceClusters.from_host(cs)
+    trk.track(dc)
+    full = RefitSet.from_tracker(trk)
+    idx = np.arange(0, full.n_tracks, 40)
+    rset = _subset(full, idx)
+    log("C2: finite differences on %d of %d tracks" % (rset.n_tracks, full.n_tracks))
+    # start-state gradient error bound in units of the track's largest
+    # cluster sensitivity: 1e-6 is 16 binary32 ulp of that unit (C1's 1e-7 is
+    # under 2 ulp, met there with room; a central-event track reaches 2.5 ulp)
+    _fd_check(cs, dc, rset, False, drop_failed=True, start_tol=1e-6)
+
+
+def _fd_check(cs, dc, rset, f64, drop_failed=False, start_tol=1e-7):
     import torch
 
     from paper_1811_11481_amd import FLAG_ADJOINT_F64, Tracker, default_params
-    cs, _, dc, _, rset = c1_setup
     trk = Tracker(params=default_params(flags=FLAG_ADJOINT_F64 if f64 else 0))
     coef = _smooth_map(12)
     n = rset.n_tracks
@@ -127,6 +165,11 @@ def test_gradients_against_fp64_finite_differences(c1_setup, f64):
     # little with the start state that smaller steps drown in rounding
     ok, gp_fd, gc_fd = oracle.frozen_chi2_grad_fd(h, coef=coef.astype(np.float64), coef_index=sample,
                                                   h_param=1e-2 * sig)
+    if drop_failed and not ok.all():
+        # a step of a few tracks near the |sin phi| guard fails at a +-h
+        # evaluation: their difference quotient is undefined; check the rest
+        log("finite differences undefined for %d tracks: dropped" % (~ok.astype(bool)).sum())
+        return _fd_check(cs, dc, _subset(rset, np.nonzero(ok)[0]), f64, start_tol=start_tol)
     assert ok.all()
     hs = h["hit_start"]
     # The pass-3 chi2 barely depends on the start state (three covariance
@@ -142,7 +185,7 @@ def test_gradients_against_fp64_finite_differences(c1_setup, f64):
     log("adjoint %s: start-state gradient error %.3g (max, cluster-sensitivity units), median relative %.3g; "
         "map gradient error max %.3g of max|g| = %.3g" % ("f64" if f64 else "f32", err_n.max(), np.median(rel_p),
                                                           err_c.max(), np.abs(gc_fd).max()))
-    assert err_n.max() <= 1e-7
+    assert err_n.max() <= start_tol
     assert np.median(rel_p) <= 2e-2
     assert err_c.max() <= (2e-5 if f64 else 1e-4)
     # identities of the exact derivative
