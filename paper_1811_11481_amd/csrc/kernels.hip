@@ -1459,6 +1459,17 @@ __device__ __forceinline__ int refit_work(const Bufs& b, int64_t si) {
     return abs(b.tl_row[b.sel_tl[si]] - hi) + 3 * (hi - lo) + 3 * n;
 }
 
+// Accept bits in the refit. Bit j of a lane's bitmap stands for the track
+// list's entry j - (off & 3) (off = the list's first index in the selected-hit
+// arrays), so that four consecutive bits starting at a multiple of four are
+// the four mask bytes of one aligned word. A list holds at most one cluster per
+// pad row, so n_rows + 3 bits cover it.
+__host__ __device__ constexpr int refit_bit_words(int n_rows) { return (n_rows + 3 + 31) >> 5; }
+
+// Bits 0..3 of x moved to bits 0, 8, 16 and 24 (the four shifted copies of a
+// 4-bit value do not overlap, so the product has no carries).
+__device__ __forceinline__ uint32_t spread4(uint32_t x) { return ((x & 15u) * 0x00204081u) & 0x01010101u; }
+
 __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
     const DevConsts& K = *b.K;
     const KfConsts kc = kf_consts(K);
@@ -1466,6 +1477,9 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
     __shared__ float sX[kMaxRows];
     __shared__ int skey[256];
     __shared__ int sorder[256];
+    // [pass][word][lane]: the accept bits of each lane's current track
+    extern __shared__ uint32_t rf_bits[];
+    const int nbw = refit_bit_words(K.n_rows);
     kf_load_rows(sX, K);
     const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
@@ -1514,27 +1528,32 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
             else cur = nx;
             ++st_rows;
         }
-        for (int i = 0; i < n; ++i) b.sel_mask[off + i] = 0;
+        // the mask byte of entry i: bit p set iff pass p reached and accepted
+        // it; collected as bits and written once after the passes
+        const int bsh = off & 3, nbt = (bsh + n + 31) >> 5;
+        for (int w = 0; w < 3 * nbw; w += nbw)
+            for (int v = 0; v < nbt; ++v) rf_bits[(w + v) * nt + tid] = 0u;
         float chi2sum = 0.0f;
         int nacc = 0;
         for (int pass = 0; pass < 3 && ok; ++pass) {
             kf_reset(s, kc);
             const bool inward = (pass != 1);
-            // the next cluster's row, coordinates and mask are loaded one
-            // iteration ahead, so no row step waits on memory
+            // the next cluster's row and coordinates are loaded one iteration
+            // ahead, so no row step waits on memory
             int i_n = inward ? n - 1 : 0;
             int t_n = b.sel_row[off + i_n];
             float2 c_n = b.sel_yz[off + i_n];
-            uint8_t m_n = pass ? b.sel_mask[off + i_n] : (uint8_t)0;
+            // this pass's bits of one bitmap word, stored when the pass moves
+            // to the next word and at its end
+            uint32_t bits = 0u;
+            int bw = (bsh + i_n) >> 5;
             for (int q = 0; q < n && ok; ++q) {
                 const int i = i_n, target = t_n;
                 const float2 c = c_n;
-                const uint8_t mprev = m_n;
                 if (q + 1 < n) {
                     i_n = inward ? n - 2 - q : q + 1;
                     t_n = b.sel_row[off + i_n];
                     c_n = b.sel_yz[off + i_n];
-                    m_n = pass ? b.sel_mask[off + i_n] : (uint8_t)0;
                 }
                 while (cur != target) {
                     const int nx = cur < target ? cur + 1 : cur - 1;
@@ -1549,19 +1568,27 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
                 const float my = c.x, mz = c.y;
                 const Innov inn = kf_innovation(s, my - ref_y, mz - ref_z, kc);
                 ++st_hits;
-                if (inn.chi2 <= kc.chi2_rej) {
+                const bool acc = inn.chi2 <= kc.chi2_rej;
+                if (acc) {
                     kf_update(s, inn);
                     s.p[0] = s.p[0] + (ref_y - my);
                     s.p[1] = s.p[1] + (ref_z - mz);
                     ref_y = my;
                     ref_z = mz;
-                    b.sel_mask[off + i] = (uint8_t)(mprev | (1u << pass));
                     if (pass == 2) {
                         chi2sum = chi2sum + inn.chi2;
                         ++nacc;
                     }
                 }
+                const int j = bsh + i;
+                if ((j >> 5) != bw) {
+                    rf_bits[(pass * nbw + bw) * nt + tid] = bits;
+                    bits = 0u;
+                    bw = j >> 5;
+                }
+                bits |= (acc ? 1u : 0u) << (j & 31);
             }
+            rf_bits[(pass * nbw + bw) * nt + tid] = bits;  // also after a failed step
             if (pass == 1 && b.keep_merge && ok) {  // the outward pass ends at the outermost cluster
                 float* o2 = b.rf_state2 + si * 20;
                 o2[0] = ref_y + s.p[0];
@@ -1571,6 +1598,30 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
 #pragma unroll
                 for (int q = 0; q < 15; ++q) o2[5 + q] = s.C[q];
                 b.rf_row2[si] = cur;
+            }
+        }
+        {
+            // the list's mask bytes, four per aligned word: bits 4k..4k+3 of
+            // each pass give the bytes of the word at off - bsh + 4k; words
+            // that the list shares with a neighbour are written byte by byte
+            const int je = bsh + n;
+            uint32_t* const mword = reinterpret_cast<uint32_t*>(b.sel_mask);  // 256-byte aligned
+            const int64_t g0 = (int64_t)off - bsh;
+            for (int w = 0; w < nbt; ++w) {
+                const uint32_t a0 = rf_bits[w * nt + tid], a1 = rf_bits[(nbw + w) * nt + tid],
+                               a2 = rf_bits[(2 * nbw + w) * nt + tid];
+                for (int k = 0; k < 8; ++k) {
+                    const int j = w * 32 + 4 * k;
+                    if (j >= je) break;
+                    const int sft = 4 * k;
+                    const uint32_t v = spread4(a0 >> sft) | (spread4(a1 >> sft) << 1) | (spread4(a2 >> sft) << 2);
+                    if (j >= bsh && j + 4 <= je) {
+                        mword[(g0 + j) >> 2] = v;
+                    } else {
+                        for (int t = 0; t < 4; ++t)
+                            if (j + t >= bsh && j + t < je) b.sel_mask[g0 + j + t] = (uint8_t)(v >> (8 * t));
+                    }
+                }
             }
         }
         s.p[0] = ref_y + s.p[0];
@@ -1884,7 +1935,9 @@ void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t s
 }
 
 void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(bound, L.block_refit, 16384)), dim3(L.block_refit), 0, st, b,
+    // three accept bitmaps per lane (at most 3 x 9 words x 256 lanes = 27 KB)
+    const size_t bits = (size_t)3 * refit_bit_words(b.n_rows) * L.block_refit * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(bound, L.block_refit, 16384)), dim3(L.block_refit), bits, st, b,
                        L.sort_seeds);
 }
 
