@@ -73,6 +73,26 @@ struct KState {
 
 __device__ __forceinline__ int pk(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
+// Correctly rounded binary32 square root, the same value as sqrtf, for the
+// arguments of the helix step: +-0, normal numbers of at least 2^-96, +inf,
+// negative numbers and NaN. The hardware square root is within one ulp; the
+// result is its neighbour below or above when the residual x - s'*s of that
+// neighbour s', formed by one fused multiply-add, shows the exact root to lie
+// past the midpoint (the one-ulp correction of a faithful square root). The
+// library call adds a scaling of arguments below 2^-96, where the residuals
+// would lose bits, and a class test for 0 and inf (both come out right here
+// without it). The helix step never takes a root there: 1 - s^2 of a binary32
+// sine s below 1 in magnitude is at least 2^-23, and 1 + t^2 is at least 1.
+__device__ __forceinline__ float sqrt_step(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float sd = __int_as_float(__float_as_int(s) - 1);
+    const float su = __int_as_float(__float_as_int(s) + 1);
+    float r = s;
+    if (__builtin_fmaf(-sd, s, x) <= 0.0f) r = sd;
+    if (__builtin_fmaf(-su, s, x) > 0.0f) r = su;
+    return r;
+}
+
 // asin(u)/u by its Maclaurin series through u^12 (coefficients (2n)!/(4^n (n!)^2 (2n+1))).
 __device__ __forceinline__ float asin_over_u(float u) {
     const float w = u * u;
@@ -111,11 +131,11 @@ __device__ __forceinline__ bool kf_propagate(KState& s, float x1, float x2, cons
     const float kq = K.kB * s.p[4];
     const float s2 = __builtin_fmaf(kq, dx, s1);
     if (!(__builtin_fabsf(s2) < K.sinphi_max)) return false;
-    const float c1 = __builtin_sqrtf(__builtin_fmaf(-s1, s1, 1.0f));
-    const float c2 = __builtin_sqrtf(__builtin_fmaf(-s2, s2, 1.0f));
+    const float c1 = sqrt_step(__builtin_fmaf(-s1, s1, 1.0f));
+    const float c2 = sqrt_step(__builtin_fmaf(-s2, s2, 1.0f));
     const float tt = (s1 + s2) / (c1 + c2);
     const float w = __builtin_fmaf(tt, tt, 1.0f);
-    const float lc = dx * __builtin_sqrtf(w);
+    const float lc = dx * sqrt_step(w);
     const float u = (kq * lc) * 0.5f;
     if (!(u * u <= K.u_max2)) return false;
     const float g = asin_over_u(u);
@@ -175,11 +195,11 @@ __device__ __forceinline__ bool kf_step_state(float* p, float x1, float x2, cons
     const float kq = K.kB * p[4];
     const float s2 = __builtin_fmaf(kq, dx, s1);
     if (!(__builtin_fabsf(s2) < K.sinphi_max)) return false;
-    const float c1 = __builtin_sqrtf(__builtin_fmaf(-s1, s1, 1.0f));
-    const float c2 = __builtin_sqrtf(__builtin_fmaf(-s2, s2, 1.0f));
+    const float c1 = sqrt_step(__builtin_fmaf(-s1, s1, 1.0f));
+    const float c2 = sqrt_step(__builtin_fmaf(-s2, s2, 1.0f));
     const float tt = (s1 + s2) / (c1 + c2);
     const float w = __builtin_fmaf(tt, tt, 1.0f);
-    const float lc = dx * __builtin_sqrtf(w);
+    const float lc = dx * sqrt_step(w);
     const float u = (kq * lc) * 0.5f;
     if (!(u * u <= K.u_max2)) return false;
     const float arc = lc * asin_over_u(u);
