@@ -438,6 +438,16 @@ tpcca_status tpcca_fit_corrected(tpcca_ctx* ctx, const float* map_coef, float* p
 tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div, float* out_sqrt, int64_t n,
                                   void* hip_stream);
 
+/* Self-check of the square root in the helix step (Section 3's track model;
+ * the step takes roots of 1 - sin^2 phi and of 1 + tan^2). It adds to
+ * *count (device memory, caller-initialised) the number of binary32 bit
+ * patterns x in [first, last] (as unsigned integers) for which that root
+ * differs from the correctly rounded sqrtf; two NaN results count as equal.
+ * The root is exact for +-0, for normal arguments of at least 2^-96, for +inf,
+ * negative arguments and NaN. Synchronous. Errors: TPCCA_E_ARG (null count,
+ * first > last), TPCCA_E_DEVICE. */
+tpcca_status tpcca_sqrt_step_check(uint32_t first, uint32_t last, unsigned long long* count, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1217,6 +1217,14 @@ tpcca_status tpcca_fp32_selfcheck(const float* a, const float* b, float* out_div
     return TPCCA_OK;
 }
 
+tpcca_status tpcca_sqrt_step_check(uint32_t first, uint32_t last, unsigned long long* count, void* hip_stream) {
+    if (!count || first > last) return TPCCA_E_ARG;
+    enqueue_sqrt_step_check(first, last, count, (hipStream_t)hip_stream);
+    if (hipGetLastError() != hipSuccess) return TPCCA_E_DEVICE;
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return TPCCA_E_DEVICE;
+    return TPCCA_OK;
+}
+
 tpcca_status tpcca_fit_corrected(tpcca_ctx* ctx, const float* map_coef, float* param, float* cov, float* chi2,
                                  int32_t* ndf, float* x_ref, float* z0, uint8_t* masks, float* hit_yz,
                                  void* hip_stream) {

@@ -209,5 +209,6 @@ void enqueue_export_tracklets(const Bufs& b, int64_t n_starts, int32_t* start_hi
 void enqueue_export_selected(const Bufs& b, int64_t n_sel, int32_t* sel_tl, int64_t* hit_start, int32_t* hit_id,
                              uint8_t* mask, int32_t* status, hipStream_t st);
 void enqueue_fp32_selfcheck(const float* a, const float* bb, float* od, float* os, int64_t n, hipStream_t st);
+void enqueue_sqrt_step_check(uint32_t first, uint32_t last, unsigned long long* count, hipStream_t st);
 
 }  // namespace tpcca

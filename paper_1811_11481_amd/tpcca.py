@@ -33,7 +33,7 @@ EXPORTED = [
     "tpcca_track_async_noalloc", "tpcca_merge", "tpcca_track_native", "tpcca_native_to_local", "tpcca_autotune",
     "tpcca_export_sizes", "tpcca_export_grid", "tpcca_export_links", "tpcca_export_tracklets",
     "tpcca_export_selected", "tpcca_get_stats", "tpcca_get_stage_times", "tpcca_fp32_selfcheck",
-    "tpcca_refit_fwd", "tpcca_refit_bwd", "tpcca_fit_corrected",
+    "tpcca_refit_fwd", "tpcca_refit_bwd", "tpcca_fit_corrected", "tpcca_sqrt_step_check",
 ]
 
 
@@ -224,6 +224,8 @@ def load():
         L.tpcca_get_stage_times.argtypes = [vp, vp]
         L.tpcca_fp32_selfcheck.restype = st
         L.tpcca_fp32_selfcheck.argtypes = [vp, vp, vp, vp, i64, vp]
+        L.tpcca_sqrt_step_check.restype = st
+        L.tpcca_sqrt_step_check.argtypes = [ctypes.c_uint32, ctypes.c_uint32, vp, vp]
         L.tpcca_refit_fwd.restype = st
         L.tpcca_refit_fwd.argtypes = [vp, ctypes.POINTER(Clusters), ctypes.POINTER(RefitSetC), vp, vp, vp, vp,
                                       i32, vp]
@@ -752,6 +754,18 @@ def refit_chi2(tracker: Tracker, clusters: DeviceClusters, rset: RefitSet, param
             return gp.reshape(fctx.p_shape), None if gm is None else gm.reshape(fctx.c_shape)
 
     return _RefitChi2.apply(params0, coef)
+
+
+def sqrt_step_check(first, last, stream=None):
+    """Number of binary32 bit patterns in [first, last] for which the helix
+    step's square root differs from sqrtf on the device."""
+    torch = _torch()
+    lib = load()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = lib.tpcca_sqrt_step_check(int(first), int(last), _ptr(cnt), _stream(stream))
+    if st != OK:
+        raise TpccaError(st, "sqrt self-check failed")
+    return int(cnt.item())
 
 
 def fp32_selfcheck(a, b, stream=None):

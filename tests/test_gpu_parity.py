@@ -60,6 +60,18 @@ def test_fp32_division_and_sqrt_are_correctly_rounded():
         assert np.array_equal(s.view(np.uint32), np.sqrt(np.abs(a)).view(np.uint32))
 
 
+def test_helix_step_sqrt_equals_sqrtf_over_its_domain():
+    """Every binary32 argument from 2^-96 to +inf (1.9 G bit patterns), the
+    zeros, a run of negatives and of NaNs: the helix step's root is bit-equal
+    to sqrtf (itself checked against numpy above)."""
+    from paper_1811_11481_amd import sqrt_step_check
+    ranges = [(0x0F800000, 0x7F800000), (0x00000000, 0x00000000), (0x80000000, 0x80000000),
+              (0xBF800000, 0xBF8FFFFF), (0x7F800001, 0x7F80FFFF), (0x7FC00000, 0x7FC0FFFF), (0xFFC00000, 0xFFC0FFFF)]
+    for lo, hi in ranges:
+        log("sqrt step check %08x..%08x" % (lo, hi))
+        assert sqrt_step_check(lo, hi) == 0, (hex(lo), hex(hi))
+
+
 def test_golden_neighbour_cases_on_gpu():
     cases = json.load(open(os.path.join(GOLDEN, "neighbour_cases.json")))["cases"]
     for case in cases:
