@@ -136,6 +136,62 @@ __global__ __launch_bounds__(256) void k_native_local(Bufs b, int64_t nseg, floa
 }
 
 // ------------------------------------------------------------------ grid
+// Bitonic sort of the 256 R keys key[0 .. 256 R) by 256 threads, thread t
+// holding keys t + 256 r (r < R) in registers: partners at a distance of 256
+// or more are in the same thread, 64 and 128 in another wave of the block
+// (exchanged through LDS), below 64 in the same wave (lane shuffles). The
+// network is unrolled, so every register index is a constant. Keys at and
+// beyond `count` read as the largest key. All 256 threads must call it.
+template <int R>
+__device__ __forceinline__ void bitonic_regs(uint32_t* key, int count, int tid) {
+    constexpr int N = 256 * R;
+    uint32_t x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = (tid + 256 * r < count) ? key[tid + 256 * r] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 256) {
+                const int jr = j >> 8;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r & jr) continue;
+                    const bool asc = ((tid + 256 * r) & k) == 0;
+                    const uint32_t lo = x[r], hi = x[r | jr];
+                    const uint32_t mn = lo < hi ? lo : hi, mx = lo < hi ? hi : lo;
+                    x[r] = asc ? mn : mx;
+                    x[r | jr] = asc ? mx : mn;
+                }
+            } else {
+                uint32_t y[R];
+                if (j < 64) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) y[r] = __shfl_xor(x[r], j, 64);
+                } else {
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < R; ++r) key[tid + 256 * r] = x[r];
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < R; ++r) y[r] = key[(tid ^ j) + 256 * r];
+                }
+                const bool low = (tid & j) == 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool asc = ((tid + 256 * r) & k) == 0;
+                    const uint32_t mn = x[r] < y[r] ? x[r] : y[r], mx = x[r] < y[r] ? y[r] : x[r];
+                    x[r] = (low == asc) ? mn : mx;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) key[tid + 256 * r] = x[r];
+    __syncthreads();
+}
+
 // One workgroup per (instance, row): exact ranges, bin layout, stable sort of
 // (bin, cluster index) keys by a bitonic network in LDS, gather of the sorted
 // coordinates, bin starts.
@@ -237,30 +293,16 @@ __global__ __launch_bounds__(256) void k_grid(Bufs b, int64_t seg0) {
         }
     }
     __syncthreads();
-    if (P <= nt && nt == 256) {
-        // one key per thread, padded to 256: partners within a wave are
-        // exchanged by lane shuffles, only the three distances of 64 and more
-        // go through LDS
-        uint32_t x = tid < P ? key[tid] : 0xFFFFFFFFu;
-        for (int k = 2; k <= 256; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                uint32_t y;
-                if (j < 64) {
-                    y = __shfl_xor(x, j, 64);
-                } else {
-                    __syncthreads();
-                    key[tid] = x;
-                    __syncthreads();
-                    y = key[tid ^ j];
-                }
-                const bool asc = (tid & k) == 0, low = (tid & j) == 0;
-                const uint32_t mn = x < y ? x : y, mx = x < y ? y : x;
-                x = (low == asc) ? mn : mx;
-            }
-        }
-        __syncthreads();
-        key[tid] = x;
-        __syncthreads();
+    // keys in registers (padded to 256 R) up to 2048 keys; larger rows sort in
+    // LDS with a barrier per stage
+    if (nt == 256 && P <= 256) {
+        bitonic_regs<1>(key, P, tid);
+    } else if (nt == 256 && P == 512) {
+        bitonic_regs<2>(key, P, tid);
+    } else if (nt == 256 && P == 1024) {
+        bitonic_regs<4>(key, P, tid);
+    } else if (nt == 256 && P == 2048 && MAXN >= 2048) {
+        bitonic_regs<8>(key, P, tid);
     } else {
         for (int k = 2; k <= P; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
@@ -1852,6 +1894,21 @@ __global__ void k_fp32_selfcheck(const float* a, const float* bb, float* od, flo
     }
 }
 
+// Counts the binary32 bit patterns x in [first, last] for which the helix
+// step's square root differs from sqrtf (two NaN results count as equal).
+// Lanes add to the counter only for a difference.
+__global__ void k_sqrt_step_check(uint32_t first, uint32_t last, unsigned long long* count) {
+    const uint64_t n = (uint64_t)last - first + 1;
+    unsigned long long bad = 0;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        const float x = __uint_as_float(first + (uint32_t)k);
+        const float r = sqrt_step(x), e = __builtin_sqrtf(x);
+        const bool same = __float_as_uint(r) == __float_as_uint(e) || (r != r && e != e);
+        bad += same ? 0ull : 1ull;
+    }
+    if (bad != 0ull) atomicAdd(count, bad);
+}
+
 inline int grid_for(int64_t n, int block, int cap = 65536) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -1985,6 +2042,11 @@ void enqueue_export_selected(const Bufs& b, int64_t n_sel, int32_t* sel_tl, int6
     if (n_sel <= 0) return;
     hipLaunchKernelGGL(k_export_selected, dim3(grid_for(n_sel, 256, 8192)), dim3(256), 0, st, b, n_sel, sel_tl,
                        hit_start, hit_id, mask, status);
+}
+
+void enqueue_sqrt_step_check(uint32_t first, uint32_t last, unsigned long long* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_sqrt_step_check, dim3(grid_for((int64_t)last - first + 1, 256, 16384)), dim3(256), 0, st, first,
+                       last, count);
 }
 
 void enqueue_fp32_selfcheck(const float* a, const float* bb, float* od, float* os, int64_t n, hipStream_t st) {
