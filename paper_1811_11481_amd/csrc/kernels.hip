@@ -729,9 +729,9 @@ __global__ void k_own(Bufs b) {
         }
         if (lane == 0) {
             b.tl_own[j] = own;
-            uint32_t* dst = b.tl_ownmask + j * 8;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) dst[q] = mk[q];
+            uint4* dst = reinterpret_cast<uint4*>(b.tl_ownmask + j * 8);  // 32-byte aligned rows
+            dst[0] = make_uint4(mk[0], mk[1], mk[2], mk[3]);
+            dst[1] = make_uint4(mk[4], mk[5], mk[6], mk[7]);
         }
     }
 }
@@ -755,12 +755,15 @@ __global__ void k_sel_fill(Bufs b) {
         if (ho + own > b.n_clusters) continue;  // flagged by the scan
         const int nh = b.tl_nhits[j];
         const uint32_t* mask = b.tl_ownmask + (int64_t)j * 8;
+        int run = 0;  // owned picks in the chunks before this one
         for (int c = 0; c < nh; c += 64) {
             const int k = c + lane;
-            if (k >= nh || !((mask[k >> 5] >> (k & 31)) & 1u)) continue;
-            int le = 0;  // owned picks with index <= k
-            for (int q = 0; q < (k >> 5); ++q) le += __popc(mask[q]);
-            le += __popc(mask[k >> 5] & (uint32_t)((2ull << (k & 31)) - 1ull));
+            const bool o = k < nh && ((mask[k >> 5] >> (k & 31)) & 1u);
+            const unsigned long long bal = __ballot(o);
+            const int before = run;
+            run += __popcll(bal);
+            if (!o) continue;
+            const int le = before + __popcll(bal & ((2ull << lane) - 1ull));  // owned picks with index <= k
             const int64_t m = ho + (own - le);
             const int32_t pos = b.tl_pick_pos[(int64_t)j * nr + k];
             b.sel_pos[m] = pos;
