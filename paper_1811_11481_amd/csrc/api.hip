@@ -187,7 +187,7 @@ tpcca_status check_tuning(tpcca_ctx* ctx, const tpcca_tuning& t) {
     if (t.ckpt != 0 && t.ckpt != 1) return fail(ctx, TPCCA_E_ARG, "ckpt must be 0 or 1");
     if (t.inward_wgs < 0 || t.inward_wgs > 65536) return fail(ctx, TPCCA_E_ARG, "inward_wgs must be in [0, 65536]");
     if (t.inward_sort != 0 && t.inward_sort != 1) return fail(ctx, TPCCA_E_ARG, "inward_sort must be 0 or 1");
-    if (t.sort_seeds != 0 && t.sort_seeds != 1) return fail(ctx, TPCCA_E_ARG, "sort_seeds must be 0 or 1");
+    if (t.sort_seeds < 0 || t.sort_seeds > 2) return fail(ctx, TPCCA_E_ARG, "sort_seeds must be 0, 1 or 2");
     return TPCCA_OK;
 }
 
@@ -1086,13 +1086,17 @@ tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_
     tpcca_status s = time_it(best, &best_ms);
     const int hpb[] = {1, 2, 3, 4, 6, 8};
     const int blk[] = {64, 128, 256};
-    for (int dim = 0; dim < 4 && s == TPCCA_OK; ++dim) {
-        const int* vals = dim == 0 ? hpb : blk;
-        const int nv = dim == 0 ? 6 : 3;
+    const int rord[] = {0, 2};  // refit in chunk order, or by work estimate (pays when few tracks fill the GPU)
+    for (int dim = 0; dim < 5 && s == TPCCA_OK; ++dim) {
+        const int* vals = dim == 0 ? hpb : dim == 4 ? rord : blk;
+        const int nv = dim == 0 ? 6 : dim == 4 ? 2 : 3;
         for (int k = 0; k < nv && s == TPCCA_OK; ++k) {
             tpcca_tuning t = best;
-            int* field = dim == 0 ? &t.hits_per_bin : dim == 1 ? &t.block_tracklet : dim == 2 ? &t.block_refit
-                                                                                        : &t.block_links;
+            int* field = dim == 0   ? &t.hits_per_bin
+                         : dim == 1 ? &t.block_tracklet
+                         : dim == 2 ? &t.block_refit
+                         : dim == 3 ? &t.block_links
+                                    : &t.sort_seeds;
             if (*field == vals[k]) continue;
             *field = vals[k];
             float m = 0;

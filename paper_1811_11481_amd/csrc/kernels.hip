@@ -1504,6 +1504,52 @@ __device__ __forceinline__ int refit_work(const Bufs& b, int64_t si) {
     return abs(b.tl_row[b.sel_tl[si]] - hi) + 3 * (hi - lo) + 3 * n;
 }
 
+// With rank_by_work = 2 the refit reads its tracks in the order this kernel
+// writes into seed_order (free once the tracklet stage has run): per chunk of
+// kOrderChunk consecutive selected tracks, a counting sort by the work
+// estimate (in steps of four, longest first). Order within a bucket follows
+// the LDS atomics; every track still writes only its own slots.
+constexpr int kRefitBuckets = 512;
+
+__global__ __launch_bounds__(256) void k_rf_order(Bufs b) {
+    __shared__ int hist[kRefitBuckets];
+    const int64_t base = (int64_t)(b.ctr->slot[SL_SEL][1] >> 32);
+    int64_t cnt = (int64_t)(b.ctr->slot[SL_SEL][2] >> 32);
+    if (base + cnt > b.cap_sel) cnt = b.cap_sel > base ? b.cap_sel - base : 0;
+    if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;  // never hit: sel <= starts
+    for (int64_t c0 = (int64_t)blockIdx.x * kOrderChunk; c0 < cnt; c0 += (int64_t)gridDim.x * kOrderChunk) {
+        const int n = (int)min((int64_t)kOrderChunk, cnt - c0);
+        for (int i = threadIdx.x; i < kRefitBuckets; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        int key[kOrderChunk / 256];
+#pragma unroll
+        for (int u = 0; u < kOrderChunk / 256; ++u) {
+            const int i = threadIdx.x + 256 * u;
+            key[u] = 0;
+            if (i < n) {
+                key[u] = kRefitBuckets - 1 - min(refit_work(b, base + c0 + i) >> 2, kRefitBuckets - 1);
+                atomicAdd(&hist[key[u]], 1);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int run = 0;
+            for (int k = 0; k < kRefitBuckets; ++k) {
+                const int v = hist[k];
+                hist[k] = run;
+                run += v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kOrderChunk / 256; ++u) {
+            const int i = threadIdx.x + 256 * u;
+            if (i < n) b.seed_order[base + c0 + atomicAdd(&hist[key[u]], 1)] = (int32_t)(c0 + i);
+        }
+        __syncthreads();
+    }
+}
+
 // Accept bits in the refit. Bit j of a lane's bitmap stands for the track
 // list's entry j - (off & 3) (off = the list's first index in the selected-hit
 // arrays), so that four consecutive bits starting at a multiple of four are
@@ -1515,7 +1561,7 @@ __host__ __device__ constexpr int refit_bit_words(int n_rows) { return (n_rows +
 // 4-bit value do not overlap, so the product has no carries).
 __device__ __forceinline__ uint32_t spread4(uint32_t x) { return ((x & 15u) * 0x00204081u) & 0x01010101u; }
 
-__global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
+__global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work, int remap) {
     const DevConsts& K = *b.K;
     const KfConsts kc = kf_consts(K);
     const int stats = K.stats;
@@ -1532,10 +1578,20 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work) {
     unsigned int st_rows = 0, st_hits = 0;
     const int nt = blockDim.x, tid = threadIdx.x;
     const int64_t nchunk = (cnt + nt - 1) / nt;
-    for (int64_t chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {  // uniform over the workgroup
+    // workgroups renumbered per XCD as in the tracklet kernels: the chunks one
+    // XCD runs are consecutive, so the tracks of one sort chunk
+    // (rank_by_work = 2) and their cluster lists share one L2
+    int64_t lg = blockIdx.x, period = gridDim.x;
+    if (remap && gridDim.x >= 8) {
+        period = min((nchunk + 7) / 8 * 8, (int64_t)(gridDim.x & ~7u));
+        lg = blockIdx.x < period ? xcd_logical(blockIdx.x, period) : nchunk;  // past the period: no tracks
+    }
+    for (int64_t chunk = lg; chunk < nchunk; chunk += period) {  // uniform over the workgroup
         const int64_t k0 = chunk * nt;
         int64_t k = k0 + tid;
-        if (rank_by_work) {  // uniform
+        if (rank_by_work == 2) {
+            if (k < cnt) k = b.seed_order[base + k];
+        } else if (rank_by_work) {  // uniform
             const int key = (k0 + tid < cnt) ? refit_work(b, base + k0 + tid) : -1;
             skey[tid] = key;
             __syncthreads();
@@ -1995,10 +2051,12 @@ void enqueue_select(const Bufs& b, const Launch& L, int64_t bound, hipStream_t s
 }
 
 void enqueue_refit(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
+    if (L.sort_seeds == 2)
+        hipLaunchKernelGGL(k_rf_order, dim3(grid_for(bound, kOrderChunk, 4096)), dim3(256), 0, st, b);
     // three accept bitmaps per lane (at most 3 x 9 words x 256 lanes = 27 KB)
     const size_t bits = (size_t)3 * refit_bit_words(b.n_rows) * L.block_refit * sizeof(uint32_t);
     hipLaunchKernelGGL(k_refit, dim3(grid_for(bound, L.block_refit, 16384)), dim3(L.block_refit), bits, st, b,
-                       L.sort_seeds);
+                       L.sort_seeds, L.xcd_remap);
 }
 
 void enqueue_write(const Bufs& b, const Launch& L, int64_t bound, hipStream_t st) {
