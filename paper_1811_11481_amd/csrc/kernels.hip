@@ -1490,13 +1490,14 @@ __global__ __launch_bounds__(256) void k_tracklet_in(Bufs b) {
 //
 // A wave lasts as long as its longest track, and track lengths vary from ten
 // to a few hundred row steps. Each workgroup takes a chunk of consecutive
-// tracks (their cluster lists are adjacent in memory); with rank_by_work it
-// hands them to its lanes longest first (a rank by an estimate of the row
-// steps of the walk and the three passes, plus the updates), so that the
-// tracks of one wave have similar lengths. Every track is independent and
-// writes its own slots: the assignment changes no result. Measured: no faster
-// on the central events (the refit waits on memory more than on its longest
-// lane), so it is a tuning option, off by default.
+// tracks (their cluster lists are adjacent in memory). With rank_by_work = 1
+// it hands them to its lanes longest first (a rank by an estimate of the row
+// steps of the walk and the three passes, plus the updates); with 2 the lanes
+// take the tracks of a chunk of kOrderChunk in the order of k_rf_order (the
+// same estimate), so that the tracks of one wave have similar lengths. Every
+// track is independent and writes its own slots: the assignment changes no
+// result. Both are tuning options, off by default: the second pays where few
+// tracks fill the GPU and loses a little on dense batches.
 __device__ __forceinline__ int refit_work(const Bufs& b, int64_t si) {
     const int off = b.sel_off[si], n = b.sel_n[si];
     if (n <= 0) return 0;
