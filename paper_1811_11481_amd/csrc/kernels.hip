@@ -1579,11 +1579,12 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work, int rem
     unsigned int st_rows = 0, st_hits = 0;
     const int nt = blockDim.x, tid = threadIdx.x;
     const int64_t nchunk = (cnt + nt - 1) / nt;
-    // workgroups renumbered per XCD as in the tracklet kernels: the chunks one
-    // XCD runs are consecutive, so the tracks of one sort chunk
-    // (rank_by_work = 2) and their cluster lists share one L2
+    // in work order (rank_by_work = 2), workgroups renumbered per XCD as in
+    // the tracklet kernels: the chunks one XCD runs are consecutive, so the
+    // tracks of one sort chunk and their cluster lists share one L2 (in chunk
+    // order, the interleaved numbering balances the XCDs better)
     int64_t lg = blockIdx.x, period = gridDim.x;
-    if (remap && gridDim.x >= 8) {
+    if (remap && rank_by_work == 2 && gridDim.x >= 8) {
         period = min((nchunk + 7) / 8 * 8, (int64_t)(gridDim.x & ~7u));
         lg = blockIdx.x < period ? xcd_logical(blockIdx.x, period) : nchunk;  // past the period: no tracks
     }
