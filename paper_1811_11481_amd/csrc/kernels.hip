@@ -459,8 +459,27 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     dc[0] = pd;
                     ++nd;
                 }
+            } else {
+                // a window over three or more bin rows (small bins of dense
+                // rows): the same collection row by row, given up as soon as
+                // more than kNbKeep candidates are inside
+                for (int dz = dz0; dz <= dz1 && nd <= kNbKeep; ++dz) {
+                    const int t0 = bsd[dz * gd.ny + dy0], t1 = bsd[dz * gd.ny + dy1 + 1];
+                    for (int t = t0; t < t1 && nd <= kNbKeep; ++t) {
+                        const float2 pd = cd[t];
+                        if (!(__builtin_fabsf(pd.x - yh) <= wyd && __builtin_fabsf(pd.y - zh) <= wzd)) continue;
+#pragma unroll
+                        for (int i = kNbKeep - 1; i > 0; --i) {
+                            dt[i] = dt[i - 1];
+                            dc[i] = dc[i - 1];
+                        }
+                        dt[0] = t;
+                        dc[0] = pd;
+                        ++nd;
+                    }
+                }
             }
-            const bool kept = short_d && nd <= kNbKeep;
+            const bool kept = nd <= kNbKeep;
             for (int uz = uz0; uz <= uz1; ++uz) {
                 const int q0 = bsu[uz * gu.ny + uy0], q1 = bsu[uz * gu.ny + uy1 + 1];
                 for (int q = q0; q < q1; ++q) {
