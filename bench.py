@@ -166,16 +166,20 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2.0 * n * 4 / (best * 1e-3) / 1e9
 
 
-def stage_kernels(stage, tuning):
+def stage_kernels(stage, tuning, max_row=0):
     """The kernels one launch of a stage runs (their times add up to the
-    stage's event-timed duration)."""
+    stage's event-timed duration); max_row is the largest row of the batch
+    (rows next to one of more than 512 clusters go to the neighbour kernel's
+    second variant)."""
     if stage == "tracklets":
         if tuning.inward_wgs > 0:
             return ["k_tracklet<1>", "k_tracklet_in"]
         if tuning.inward_sort:
             return ["k_tracklet<1>", "k_tl_order", "k_tracklet_inward"]
         return ["k_tracklet<0>"]
-    return [{"refit": "k_refit", "links": "k_links", "grid": "k_grid<4096>"}.get(stage, stage)]
+    if stage == "links":
+        return ["k_links<8>", "k_links<16>"] if max_row > 512 else ["k_links<8>"]
+    return [{"refit": "k_refit", "grid": "k_grid<4096>"}.get(stage, stage)]
 
 
 def stage_roofline(trk, dc, cs, workload, warmup, steps):
@@ -210,7 +214,8 @@ def stage_roofline(trk, dc, cs, workload, warmup, steps):
     dom_bytes = stages[dom]["alg_bytes"]
     achieved = dom_bytes / (stages[dom]["ms"] * 1e-3) / 1e9
     kname = {"tracklets": "k_tracklet", "refit": "k_refit", "links": "k_links", "grid": "k_grid"}.get(dom, dom)
-    kernels = stage_kernels(dom, trk.tuning)
+    import numpy as np
+    kernels = stage_kernels(dom, trk.tuning, int(np.diff(np.asarray(cs.row_start)).max()) if cs.n_clusters else 0)
     roofline = {"bound": "hbm", "kernel": " + ".join(kernels), "stage": dom, "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),

@@ -26,7 +26,12 @@ namespace {
 
 constexpr float kBinMargin = 0.01f;  // cm: bin ranges of window queries are widened by this
 constexpr int kCandChunk = 8;         // window candidates loaded per memory round trip
-constexpr int kNbKeep = 8;            // neighbour candidates in row r-1 kept in registers per hit
+// neighbour candidates in row r-1 kept in registers per hit: 8 where both
+// adjacent rows hold at most kDenseRow clusters, 16 in denser rows (more
+// registers, which slow the sparse rows down)
+constexpr int kNbKeep = 8;
+constexpr int kNbKeepDense = 16;
+constexpr int kDenseRow = 512;
 constexpr int kSmallRow = 4096;
 constexpr int kLargeRow = 16384;      // TPCCA_MAX_ROW_CLUSTERS
 constexpr int kKeyShift = 14;         // key = bin << 14 | local index (both < 16384)
@@ -355,7 +360,10 @@ __device__ __forceinline__ int64_t xcd_logical(int64_t g, int64_t P) { return (g
 // deviation score wins, ties to the smaller (id_u, id_d). When both adjacent
 // rows fit in `cap` clusters, their coordinates and bin starts are staged in
 // LDS once per workgroup and every candidate read is an LDS read.
-__global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t nseg, int cap, int remap) {
+// rows: 0 every row; 1 the rows whose adjacent rows both hold at most
+// kDenseRow clusters (and the first and last rows); 2 the others.
+template <int KEEP>
+__global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t nseg, int cap, int remap, int rows) {
     extern __shared__ unsigned char smem[];
     const DevConsts& K = *b.K;
     const int nr = K.n_rows;
@@ -365,6 +373,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
     const int r = (int)(seg % nr);
     const int64_t a = b.row_start[seg], e = b.row_start[seg + 1];
     if (r == 0 || r == nr - 1) {
+        if (rows == 2) return;
         for (int64_t p = a + threadIdx.x; p < e; p += blockDim.x) {
             b.up[p] = -1;
             b.dn[p] = -1;
@@ -373,6 +382,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
     }
     const GridView gu = grid_view(b, seg + 1);
     const GridView gd = grid_view(b, seg - 1);
+    if (rows != 0 && ((gu.n > kDenseRow || gd.n > kDenseRow) != (rows == 2))) return;  // uniform: the other launch
     const int nbu = gu.ny * gu.nz, nbd = gd.ny * gd.nz;
     const bool lds = cap > 0 && gu.n <= cap && gd.n <= cap;  // uniform over the workgroup
     float2* su = reinterpret_cast<float2*>(smem);
@@ -427,13 +437,13 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     bd = t;
                 }
             };
-            // the d candidates inside their box, scanned once: up to kNbKeep kept
+            // the d candidates inside their box, scanned once: up to KEEP kept
             // in registers (a shift register, no indexed register access)
             int nd = 0;
-            int dt[kNbKeep];
-            float2 dc[kNbKeep];
+            int dt[KEEP];
+            float2 dc[KEEP];
 #pragma unroll
-            for (int i = 0; i < kNbKeep; ++i) {
+            for (int i = 0; i < KEEP; ++i) {
                 dt[i] = 0;
                 dc[i] = make_float2(0.0f, 0.0f);
             }
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     const float2 pd = cd[t];
                     if (!(__builtin_fabsf(pd.x - yh) <= wyd && __builtin_fabsf(pd.y - zh) <= wzd)) continue;
 #pragma unroll
-                    for (int i = kNbKeep - 1; i > 0; --i) {
+                    for (int i = KEEP - 1; i > 0; --i) {
                         dt[i] = dt[i - 1];
                         dc[i] = dc[i - 1];
                     }
@@ -462,14 +472,14 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
             } else {
                 // a window over three or more bin rows (small bins of dense
                 // rows): the same collection row by row, given up as soon as
-                // more than kNbKeep candidates are inside
-                for (int dz = dz0; dz <= dz1 && nd <= kNbKeep; ++dz) {
+                // more than KEEP candidates are inside
+                for (int dz = dz0; dz <= dz1 && nd <= KEEP; ++dz) {
                     const int t0 = bsd[dz * gd.ny + dy0], t1 = bsd[dz * gd.ny + dy1 + 1];
-                    for (int t = t0; t < t1 && nd <= kNbKeep; ++t) {
+                    for (int t = t0; t < t1 && nd <= KEEP; ++t) {
                         const float2 pd = cd[t];
                         if (!(__builtin_fabsf(pd.x - yh) <= wyd && __builtin_fabsf(pd.y - zh) <= wzd)) continue;
 #pragma unroll
-                        for (int i = kNbKeep - 1; i > 0; --i) {
+                        for (int i = KEEP - 1; i > 0; --i) {
                             dt[i] = dt[i - 1];
                             dc[i] = dc[i - 1];
                         }
@@ -479,7 +489,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     }
                 }
             }
-            const bool kept = nd <= kNbKeep;
+            const bool kept = nd <= KEEP;
             for (int uz = uz0; uz <= uz1; ++uz) {
                 const int q0 = bsu[uz * gu.ny + uy0], q1 = bsu[uz * gu.ny + uy1 + 1];
                 for (int q = q0; q < q1; ++q) {
@@ -489,7 +499,7 @@ __global__ __launch_bounds__(1024) void k_links(Bufs b, int64_t seg0, int64_t ns
                     ++n_cu;
                     if (kept) {
 #pragma unroll
-                        for (int i = 0; i < kNbKeep; ++i)
+                        for (int i = 0; i < KEEP; ++i)
                             if (nd > i) pair(q, yu, zu, dt[i], dc[i].x, dc[i].y);
                         continue;
                     }
@@ -2040,8 +2050,15 @@ void enqueue_links(const Bufs& b, const Launch& L, int i0, int i1, int max_row, 
     const int cap = max_row < 1 ? 1 : min(max_row, cap_lds);
     const size_t bytes = (size_t)cap * 2 * sizeof(float2) + (size_t)(cap + 1) * 2 * sizeof(int32_t);
     const int64_t grid = L.xcd_remap ? (nseg + 7) / 8 * 8 : nseg;
-    hipLaunchKernelGGL(k_links, dim3((unsigned)grid), dim3(L.block_links), bytes, st, b, seg0, nseg, cap,
-                       L.xcd_remap);
+    if (max_row <= kDenseRow) {
+        hipLaunchKernelGGL(k_links<kNbKeep>, dim3((unsigned)grid), dim3(L.block_links), bytes, st, b, seg0, nseg, cap,
+                           L.xcd_remap, 0);
+        return;
+    }
+    hipLaunchKernelGGL(k_links<kNbKeep>, dim3((unsigned)grid), dim3(L.block_links), bytes, st, b, seg0, nseg, cap,
+                       L.xcd_remap, 1);
+    hipLaunchKernelGGL(k_links<kNbKeepDense>, dim3((unsigned)grid), dim3(L.block_links), bytes, st, b, seg0, nseg,
+                       cap, L.xcd_remap, 2);
 }
 
 void enqueue_clean_starts(const Bufs& b, const Launch& L, int i0, int i1, int64_t c0, int64_t c1, hipStream_t st) {

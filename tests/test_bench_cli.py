@@ -24,3 +24,5 @@ def test_tracklet_byte_model_is_the_per_unit_figures():
     t = SimpleNamespace(inward_wgs=0, inward_sort=1)
     assert bench.stage_kernels("tracklets", t) == ["k_tracklet<1>", "k_tl_order", "k_tracklet_inward"]
     assert bench.stage_kernels("tracklets", SimpleNamespace(inward_wgs=0, inward_sort=0)) == ["k_tracklet<0>"]
+    assert bench.stage_kernels("links", t, max_row=321) == ["k_links<8>"]
+    assert bench.stage_kernels("links", t, max_row=2284) == ["k_links<8>", "k_links<16>"]
