@@ -99,12 +99,11 @@ typedef struct {
     int32_t block_tracklet;   /* threads per block of the tracklet kernels (64..256), default 64 */
     int32_t block_refit;      /* threads per block of the refit kernel (64..256), default 128 */
     int32_t block_scan;       /* threads per block of scans/compactions, default 256 */
-    int32_t sort_seeds;       /* order of the refit's tracks over its lanes (results identical): 0 (default)
-                                 consecutive tracks; 1: each workgroup hands its chunk to its lanes longest
-                                 first; 2: a counting sort by estimated work over chunks of 1024 tracks,
-                                 longest first (faster when few tracks fill the GPU, e.g. 256 uneven
-                                 sector instances; slower on dense batches, whose cluster lists are then
-                                 read from scattered lines). tpcca_autotune tries 0 and 2. */
+    int32_t sort_seeds;       /* order of the refit's tracks over its lanes (results identical): 0
+                                 consecutive tracks; 1 (default): each workgroup hands its chunk of
+                                 consecutive tracks to its lanes longest first; 2: a counting sort by
+                                 estimated work over chunks of 1024 tracks, longest first (its lanes'
+                                 cluster lists are then far apart). tpcca_autotune tries all three. */
     int32_t tape_mb;          /* device memory for the differentiable refit's tape [MiB], default 32768;
                                  a larger set is recomputed batch by batch in tpcca_refit_bwd */
     int32_t xcd_remap;        /* 1: workgroups renumbered so that each of the 8 XCDs (own L2) works on

@@ -766,7 +766,7 @@ tpcca_status tpcca_default_tuning(tpcca_tuning* t) {
     t->block_tracklet = 64;
     t->block_refit = 128;
     t->block_scan = 256;
-    t->sort_seeds = 0;
+    t->sort_seeds = 1;
     t->tape_mb = 32768;
     t->xcd_remap = 1;
     t->ckpt = 0;
@@ -1086,10 +1086,10 @@ tpcca_status tpcca_autotune(tpcca_ctx* ctx, const tpcca_clusters* sample, int32_
     tpcca_status s = time_it(best, &best_ms);
     const int hpb[] = {1, 2, 3, 4, 6, 8};
     const int blk[] = {64, 128, 256};
-    const int rord[] = {0, 2};  // refit in chunk order, or by work estimate (pays when few tracks fill the GPU)
+    const int rord[] = {0, 1, 2};  // the refit's track order over its lanes
     for (int dim = 0; dim < 5 && s == TPCCA_OK; ++dim) {
         const int* vals = dim == 0 ? hpb : dim == 4 ? rord : blk;
-        const int nv = dim == 0 ? 6 : dim == 4 ? 2 : 3;
+        const int nv = dim == 0 ? 6 : 3;
         for (int k = 0; k < nv && s == TPCCA_OK; ++k) {
             tpcca_tuning t = best;
             int* field = dim == 0   ? &t.hits_per_bin

@@ -1525,8 +1525,9 @@ __global__ __launch_bounds__(256) void k_tracklet_in(Bufs b) {
 // take the tracks of a chunk of kOrderChunk in the order of k_rf_order (the
 // same estimate), so that the tracks of one wave have similar lengths. Every
 // track is independent and writes its own slots: the assignment changes no
-// result. Both are tuning options, off by default: the second pays where few
-// tracks fill the GPU and loses a little on dense batches.
+// result. The first is the default; the second pays where few tracks fill
+// the GPU and loses a little on dense batches (the lists of a wave's tracks
+// are then far apart in memory).
 __device__ __forceinline__ int refit_work(const Bufs& b, int64_t si) {
     const int off = b.sel_off[si], n = b.sel_n[si];
     if (n <= 0) return 0;

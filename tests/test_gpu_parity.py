@@ -139,7 +139,8 @@ def test_batched_graph_follows_new_output_buffers(c1):
                                   dict(inward_wgs=1024), dict(inward_wgs=3, block_tracklet=64, xcd_remap=0),
                                   dict(inward_sort=0, block_tracklet=256), dict(inward_sort=0, block_tracklet=64, xcd_remap=0),
                                   dict(inward_sort=1, block_tracklet=256, xcd_remap=0), dict(sort_seeds=2),
-                                  dict(sort_seeds=2, block_refit=64, xcd_remap=0)])
+                                  dict(sort_seeds=2, block_refit=64, xcd_remap=0), dict(sort_seeds=0),
+                                  dict(sort_seeds=0, block_refit=256)])
 def test_results_independent_of_tuning(c1, c1_oracle, tune):
     from paper_1811_11481_amd import default_tuning
     log("C1 tuning %s" % tune)
@@ -172,8 +173,11 @@ def test_c2_split_inward_pass_bit_exact(c2, c2_oracle):
 def test_c2_refit_in_work_order_bit_exact(c2, c2_oracle):
     # the refit's tracks counting-sorted by estimated work per chunk of 1024
     # (sort_seeds = 2): batched against the oracle, and the plain form (one
-    # launch per instance, selection ranges that start past zero) against it
+    # launch per instance, selection ranges that start past zero) against it;
+    # the consecutive order (sort_seeds = 0) against the oracle too
     from paper_1811_11481_amd import default_tuning
+    log("C2 batched, refit in chunk order")
+    compare_with_oracle(run_gpu(c2, tuning=default_tuning(sort_seeds=0)), c2_oracle)
     log("C2 batched, refit in work order")
     g = run_gpu(c2, tuning=default_tuning(sort_seeds=2))
     compare_with_oracle(g, c2_oracle)
@@ -278,9 +282,10 @@ def test_c4_uneven_instances_sampled_parity():
     p = run_gpu(cs, batched=False, exports=False)
     assert tracks_equal(g, p)
     from paper_1811_11481_amd import default_tuning
-    log("C4 batched, refit in work order")
-    w = run_gpu(cs, exports=False, tuning=default_tuning(sort_seeds=2))
-    assert tracks_equal(g, w)
+    for order in (0, 2):
+        log("C4 batched, refit order %d" % order)
+        w = run_gpu(cs, exports=False, tuning=default_tuning(sort_seeds=order))
+        assert tracks_equal(g, w)
 
 
 def test_vertex_z_of_every_track(c2):
