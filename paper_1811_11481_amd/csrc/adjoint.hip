@@ -498,6 +498,27 @@ __device__ __forceinline__ float* ckpt_at(const AdjBufs& a, int pass, int64_t t)
     return a.ckpt + ((int64_t)pass * a.n_tracks + t) * kCkptWords;
 }
 
+// Lanes take the tracks of their workgroup's chunk [c0, c0 + blockDim.x)
+// longest first (key: an estimate of the track's work, -1 past the end; equal
+// keys in chunk order), so that the tracks of one wave have similar lengths.
+// Every track is independent and writes its own slots: the assignment changes
+// no result. All threads of the workgroup must call it.
+__device__ __forceinline__ int64_t chunk_track_by_work(int* skey, int* sorder, int64_t c0, int key) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    skey[tid] = key;
+    __syncthreads();
+    int rank = 0;
+    for (int j = 0; j < nt; ++j) {
+        const int kj = skey[j];
+        rank += (kj > key || (kj == key && j < tid)) ? 1 : 0;
+    }
+    sorder[rank] = tid;
+    __syncthreads();
+    const int64_t t = c0 + sorder[tid];
+    __syncthreads();  // skey and sorder are rewritten for the next chunk
+    return t;
+}
+
 // Passes [pass_lo, pass_hi) of the refit. pass_lo = 0 starts from the start
 // state and walks to the outermost cluster first; pass_lo > 0 starts from
 // that pass's checkpoint (a segment recompute, which then counts its own
@@ -509,11 +530,26 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
     const DevConsts& K = *a.K;
     const KfConsts kc = kf_consts(K);
     __shared__ float sX[kMaxRows];
-    kf_load_rows(sX, K);  // before the status test: every thread reaches its barrier
-    if (a.status->err) return;
+    __shared__ int skey[256], sorder[256], s_err;
+    kf_load_rows(sX, K);
+    // the error flag read once per workgroup (other workgroups may raise it
+    // meanwhile): the return, like the barriers below, is uniform
+    if (threadIdx.x == 0) s_err = a.status->err;
+    __syncthreads();
+    if (s_err) return;
     const int cap = a.tape_ops;
-    for (int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t1;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    const int nt = blockDim.x;
+    for (int64_t c0 = t0 + blockIdx.x * (int64_t)nt; c0 < t1; c0 += (int64_t)gridDim.x * nt) {  // uniform
+        int key = -1;  // row steps of the walk and the three passes, plus the updates
+        if (c0 + threadIdx.x < t1) {
+            const int64_t tk = c0 + threadIdx.x, o = a.hit_start[tk];
+            const int nk = (int)(a.hit_start[tk + 1] - o);
+            key = nk > 0 ? abs(a.row0[tk] - (int)a.hit_row[o + nk - 1]) +
+                               3 * abs((int)a.hit_row[o + nk - 1] - (int)a.hit_row[o]) + 3 * nk
+                         : 0;
+        }
+        const int64_t t = chunk_track_by_work(skey, sorder, c0, key);
+        if (t >= t1) continue;
         const int64_t off = a.hit_start[t];
         const int n = (int)(a.hit_start[t + 1] - off);
         const uint8_t* rows = a.hit_row + off;
@@ -633,10 +669,18 @@ __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_
     const DevConsts& K = *a.K;
     const KfConsts kc = kf_consts(K);
     __shared__ float sX[kMaxRows];
+    __shared__ int skey[256], sorder[256];
     kf_load_rows(sX, K);
     const int64_t NH = a.n_hits;
-    for (int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t1;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    const int nt = blockDim.x;
+    for (int64_t c0 = t0 + blockIdx.x * (int64_t)nt; c0 < t1; c0 += (int64_t)gridDim.x * nt) {  // uniform
+        int key = -1;  // the recorded operations: the exact length of the reverse sweep
+        if (c0 + threadIdx.x < t1) {
+            const int64_t tk = c0 + threadIdx.x;
+            key = max(seg < 0 ? a.nops[tk] : a.seg_nops[tk], 0);
+        }
+        const int64_t t = chunk_track_by_work(skey, sorder, c0, key);
+        if (t >= t1) continue;
         const int64_t off = a.hit_start[t];
         const int n = (int)(a.hit_start[t + 1] - off);
         const bool first = seg < 0 || seg == 2;  // the last operations of the refit come first
