@@ -498,27 +498,6 @@ __device__ __forceinline__ float* ckpt_at(const AdjBufs& a, int pass, int64_t t)
     return a.ckpt + ((int64_t)pass * a.n_tracks + t) * kCkptWords;
 }
 
-// Lanes take the tracks of their workgroup's chunk [c0, c0 + blockDim.x)
-// longest first (key: an estimate of the track's work, -1 past the end; equal
-// keys in chunk order), so that the tracks of one wave have similar lengths.
-// Every track is independent and writes its own slots: the assignment changes
-// no result. All threads of the workgroup must call it.
-__device__ __forceinline__ int64_t chunk_track_by_work(int* skey, int* sorder, int64_t c0, int key) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    skey[tid] = key;
-    __syncthreads();
-    int rank = 0;
-    for (int j = 0; j < nt; ++j) {
-        const int kj = skey[j];
-        rank += (kj > key || (kj == key && j < tid)) ? 1 : 0;
-    }
-    sorder[rank] = tid;
-    __syncthreads();
-    const int64_t t = c0 + sorder[tid];
-    __syncthreads();  // skey and sorder are rewritten for the next chunk
-    return t;
-}
-
 // Passes [pass_lo, pass_hi) of the refit. pass_lo = 0 starts from the start
 // state and walks to the outermost cluster first; pass_lo > 0 starts from
 // that pass's checkpoint (a segment recompute, which then counts its own
@@ -548,7 +527,7 @@ __global__ __launch_bounds__(256) void k_refit_fwd(AdjBufs a, int64_t t0, int64_
                                3 * abs((int)a.hit_row[o + nk - 1] - (int)a.hit_row[o]) + 3 * nk
                          : 0;
         }
-        const int64_t t = chunk_track_by_work(skey, sorder, c0, key);
+        const int64_t t = chunk_item_by_work(skey, sorder, c0, key);
         if (t >= t1) continue;
         const int64_t off = a.hit_start[t];
         const int n = (int)(a.hit_start[t + 1] - off);
@@ -679,7 +658,7 @@ __global__ __launch_bounds__(256) void k_refit_bwd(AdjBufs a, int64_t t0, int64_
             const int64_t tk = c0 + threadIdx.x;
             key = max(seg < 0 ? a.nops[tk] : a.seg_nops[tk], 0);
         }
-        const int64_t t = chunk_track_by_work(skey, sorder, c0, key);
+        const int64_t t = chunk_item_by_work(skey, sorder, c0, key);
         if (t >= t1) continue;
         const int64_t off = a.hit_start[t];
         const int n = (int)(a.hit_start[t + 1] - off);
@@ -1123,10 +1102,19 @@ __global__ __launch_bounds__(128) void k_fit_corrected(CorrBufs c) {
     const DevConsts& K = *c.K;
     const KfConsts kc = kf_consts(K);
     __shared__ float sX[kMaxRows];
+    __shared__ int skey[128], sorder[128];
     kf_load_rows(sX, K);
     const int nr = c.n_rows;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < c.n_tracks;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    const int nt = blockDim.x;
+    for (int64_t c0 = blockIdx.x * (int64_t)nt; c0 < c.n_tracks; c0 += (int64_t)gridDim.x * nt) {  // uniform
+        int key = -1;  // row steps of the three passes, plus the updates
+        if (c0 + threadIdx.x < c.n_tracks) {
+            const int64_t tk = c0 + threadIdx.x, hk = c.hit_start[tk];
+            const int nk = (int)(c.hit_start[tk + 1] - hk);
+            key = nk > 0 ? 3 * abs((int)c.crow[hk + nk - 1] - (int)c.crow[hk]) + 3 * nk : 0;
+        }
+        const int64_t t = chunk_item_by_work(skey, sorder, c0, key);
+        if (t >= c.n_tracks) continue;
         const int64_t h0 = c.hit_start[t];
         const int n = (int)(c.hit_start[t + 1] - h0);
         const float zv = c.z0[t];

@@ -1624,18 +1624,7 @@ __global__ __launch_bounds__(256) void k_refit(Bufs b, int rank_by_work, int rem
         if (rank_by_work == 2) {
             if (k < cnt) k = b.seed_order[base + k];
         } else if (rank_by_work) {  // uniform
-            const int key = (k0 + tid < cnt) ? refit_work(b, base + k0 + tid) : -1;
-            skey[tid] = key;
-            __syncthreads();
-            int rank = 0;  // longer first; equal work in chunk order
-            for (int j = 0; j < nt; ++j) {
-                const int kj = skey[j];
-                rank += (kj > key || (kj == key && j < tid)) ? 1 : 0;
-            }
-            sorder[rank] = tid;
-            __syncthreads();
-            k = k0 + sorder[tid];
-            __syncthreads();  // skey and sorder are rewritten by the next chunk
+            k = chunk_item_by_work(skey, sorder, k0, (k0 + tid < cnt) ? refit_work(b, base + k0 + tid) : -1);
         }
         if (k >= cnt) continue;
         const int64_t si = base + k;

@@ -278,6 +278,28 @@ __device__ __forceinline__ float vertex_z(double kB, double x, const float* p) {
     return (float)(z + tl * s);
 }
 
+// Lanes take the items (tracks, chains) of their workgroup's chunk
+// [c0, c0 + blockDim.x) longest first (key: an estimate of the item's serial
+// work, -1 past the end; equal keys in chunk order), so that the lanes of one
+// wave end at similar times. Each item is independent and writes its own
+// slots: the assignment changes no result. All threads of the workgroup must
+// call it; skey and sorder hold blockDim.x ints in LDS.
+__device__ __forceinline__ int64_t chunk_item_by_work(int* skey, int* sorder, int64_t c0, int key) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    skey[tid] = key;
+    __syncthreads();
+    int rank = 0;
+    for (int j = 0; j < nt; ++j) {
+        const int kj = skey[j];
+        rank += (kj > key || (kj == key && j < tid)) ? 1 : 0;
+    }
+    sorder[rank] = tid;
+    __syncthreads();
+    const int64_t k = c0 + sorder[tid];
+    __syncthreads();  // skey and sorder are rewritten for the next chunk
+    return k;
+}
+
 // Covariance reset at a turn or pass start: variances scaled, correlations dropped.
 template <class KC>
 __device__ __forceinline__ void kf_reset(KState& s, const KC& K) {

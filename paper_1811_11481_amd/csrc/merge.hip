@@ -375,10 +375,22 @@ __global__ __launch_bounds__(128) void k_mrg_refit(MergeBufs m) {
     const DevConsts& K = *b.K;
     const KfConsts kc = kf_consts(K);
     __shared__ float sX[kMaxRows];
+    __shared__ int skey[128], sorder[128];
     kf_load_rows(sX, K);
     const int nr = K.n_rows;
     const int64_t nheads = (int64_t)*m.nheads;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nheads; k += (int64_t)gridDim.x * blockDim.x) {
+    const int nt = blockDim.x;
+    for (int64_t c0 = blockIdx.x * (int64_t)nt; c0 < nheads; c0 += (int64_t)gridDim.x * nt) {  // uniform
+        int key = -1;  // the chain's clusters: three passes over them
+        if (c0 + threadIdx.x < nheads) {
+            const int32_t h = m.heads[c0 + threadIdx.x];
+            int nk = (int)(b.o_hit_start[h + 1] - b.o_hit_start[h]), sk = 1;
+            for (int32_t u = m.next[h]; u >= 0 && sk < kMaxChain; u = m.next[u], ++sk)
+                nk += (int)(b.o_hit_start[u + 1] - b.o_hit_start[u]);
+            key = nk;
+        }
+        const int64_t k = chunk_item_by_work(skey, sorder, c0, key);
+        if (k >= nheads) continue;
         const int32_t t = m.heads[k];
         // the chain: at most kMaxChain segments from t along next
         int nseg = 1, n = (int)(b.o_hit_start[t + 1] - b.o_hit_start[t]);
