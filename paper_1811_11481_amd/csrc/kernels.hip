@@ -731,14 +731,35 @@ struct SelectOp {
 // Owned picks of every tracklet of the current range: count and bitmask. One
 // wave per tracklet, one lane per pick (the picks' weight reads are
 // independent, so they overlap instead of queueing behind one lane).
+// A contiguous block of items for each wave, the workgroups numbered per
+// XCD: the waves of one XCD cover one contiguous share of the items. In the
+// ownership test the items are tracklets in instance order, so one XCD
+// gathers the weights of a contiguous share of the instances and they stay in
+// its L2 (C3, dense instances: 0.74 -> 0.54 ms; the selection-list and output
+// kernels balance better with the interleaved loop). The range is uniform
+// over the wave.
+struct WaveBlock {
+    int64_t lo, hi;
+};
+__device__ __forceinline__ WaveBlock wave_block(int64_t cnt) {
+    const int64_t wpb = blockDim.x >> 6;
+    const int64_t P = gridDim.x >= 8 ? (int64_t)(gridDim.x & ~7u) : (int64_t)gridDim.x;
+    if ((int64_t)blockIdx.x >= P) return WaveBlock{0, 0};
+    const int64_t lg = gridDim.x >= 8 ? xcd_logical(blockIdx.x, P) : (int64_t)blockIdx.x;
+    const int64_t nw = P * wpb, w = lg * wpb + (threadIdx.x >> 6);
+    const int64_t per = (cnt + nw - 1) / nw;
+    const int64_t lo = min(cnt, w * per);
+    return WaveBlock{lo, min(cnt, lo + per)};
+}
+
 __global__ void k_own(Bufs b) {
     const int nr = b.K->n_rows, n_min = b.K->n_min;
     const int64_t base = (int64_t)(b.ctr->slot[SL_START][1] & 0xFFFFFFFFull);
     int64_t cnt = (int64_t)(b.ctr->slot[SL_START][2] & 0xFFFFFFFFull);
     if (base + cnt > b.cap_starts) cnt = b.cap_starts > base ? b.cap_starts - base : 0;
     const int lane = threadIdx.x & 63;
-    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t k0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; k0 < cnt; k0 += nwave) {
+    const WaveBlock wb = wave_block(cnt);
+    for (int64_t k0 = wb.lo; k0 < wb.hi; ++k0) {
         const int64_t j = base + k0;
         const int nh = b.tl_nhits[j];
         uint32_t mk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
